@@ -1,0 +1,784 @@
+/*
+ * kpx_oracle.c -- plain float64 reference of Kino-PAX+ (arXiv 2602.02846).
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use this file; the planner library never links it.
+ *
+ * Deliberately slow and literal: one slot after another, one node after
+ * another, O(n) loops, no blocking, no fusion, no reordering.  Each function
+ * names the passage of the paper it follows.  Readings taken where the paper
+ * is silent are marked "Reading:".
+ */
+#include "kpx_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+int ora_state_dim(int32_t dyn)
+{
+    switch (dyn) {
+    case ORA_DI6: return 6;
+    case ORA_QUAD12: return 12;
+    case ORA_DUBINS6: return 6;
+    default: return -1;
+    }
+}
+
+int ora_control_dim(int32_t dyn)
+{
+    switch (dyn) {
+    case ORA_DI6: return 3;
+    case ORA_QUAD12: return 4;
+    case ORA_DUBINS6: return 3;
+    default: return -1;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11).  Each round multiplies counter words 0 and 2 by */
+/* the two published 32-bit multipliers, and builds the new counter from the */
+/* high halves xor-ed with the other two words and the key, and the low      */
+/* halves.  The key is advanced by the two published Weyl increments before */
+/* every round after the first.                                              */
+/* ------------------------------------------------------------------------ */
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t mul0 = 0xD2511F53u, mul1 = 0xCD9E8D57u;
+    const uint32_t weyl0 = 0x9E3779B9u, weyl1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += weyl0;
+            k1 += weyl1;
+        }
+        uint64_t p0 = (uint64_t)mul0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)mul1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Random control and duration of one expansion (Alg. 2 line 3; Alg. 6 line 4).
+ * Reading: counter = (iteration, slot, query, block), key = (seed low, seed
+ * high).  Block b yields words 4b..4b+3.  Control i takes word i; the step
+ * count takes word m (m = control dimension).  A word w maps to the uniform
+ * (w >> 8) * 2^-24, and control i is fmaf(uniform, hi_i - lo_i, lo_i) in
+ * float32 with one rounding.  The duration is n * dt with
+ * n = n_min + floor(w_m * (n_max - n_min + 1) / 2^32), the discrete reading of
+ * "duration in (0, T_prop]". */
+void ora_sample(const ora_problem* P, uint32_t iter, uint32_t slot, float u[ORA_MAX_CONTROL],
+                int32_t* n)
+{
+    uint32_t key[2] = {(uint32_t)(P->seed & 0xFFFFFFFFu), (uint32_t)(P->seed >> 32)};
+    uint32_t words[8];
+    for (uint32_t b = 0; b < 2; ++b) {
+        uint32_t ctr[4] = {iter, slot, P->query_id, b};
+        ora_philox4x32_10(ctr, key, &words[4 * b]);
+    }
+    int m = ora_control_dim(P->dynamics);
+    for (int i = 0; i < ORA_MAX_CONTROL; ++i) u[i] = 0.0f;
+    for (int i = 0; i < m; ++i) {
+        float unit = (float)(words[i] >> 8) * 0x1p-24f;
+        float span = P->u_hi[i] - P->u_lo[i];
+        u[i] = fmaf(unit, span, P->u_lo[i]);
+    }
+    uint64_t range = (uint64_t)(P->steps_max - P->steps_min + 1);
+    *n = P->steps_min + (int32_t)(((uint64_t)words[m] * range) >> 32);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dynamics x' = f(x, u) (Eq. 1).  The paper only cites the models; the     */
+/* equations below are the standard forms.  The integrated vector z carries  */
+/* the state in z[0..d-1] and the accumulated path length in z[d].           */
+/* ------------------------------------------------------------------------ */
+void ora_deriv(const ora_problem* P, const double* z, const double* u, double* zdot)
+{
+    switch (P->dynamics) {
+    case ORA_DI6: {
+        /* position' = velocity, velocity' = acceleration control */
+        for (int i = 0; i < 3; ++i) {
+            zdot[i] = z[3 + i];
+            zdot[3 + i] = u[i];
+        }
+        zdot[6] = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+        break;
+    }
+    case ORA_QUAD12: {
+        /* state: position, ZYX Euler angles (roll phi, pitch theta, yaw psi),
+         * world-frame velocity, body rates (p, q, r);
+         * control: collective thrust T and body torques. */
+        const double mass = P->dyn_params[0];
+        const double jx = P->dyn_params[1], jy = P->dyn_params[2], jz = P->dyn_params[3];
+        const double grav = P->dyn_params[4];
+        const double phi = z[3], theta = z[4], psi = z[5];
+        const double vx = z[6], vy = z[7], vz = z[8];
+        const double wp = z[9], wq = z[10], wr = z[11];
+        const double sphi = sin(phi), cphi = cos(phi);
+        const double sth = sin(theta), cth = cos(theta);
+        const double spsi = sin(psi), cpsi = cos(psi);
+        zdot[0] = vx;
+        zdot[1] = vy;
+        zdot[2] = vz;
+        /* Euler-angle rates from body rates */
+        zdot[3] = wp + (sphi * wq + cphi * wr) * (sth / cth);
+        zdot[4] = cphi * wq - sphi * wr;
+        zdot[5] = (sphi * wq + cphi * wr) / cth;
+        /* thrust along the body z axis rotated to the world frame, minus gravity */
+        const double acc = u[0] / mass;
+        zdot[6] = acc * (cpsi * sth * cphi + spsi * sphi);
+        zdot[7] = acc * (spsi * sth * cphi - cpsi * sphi);
+        zdot[8] = acc * (cth * cphi) - grav;
+        /* Euler's rigid-body equations with a diagonal inertia */
+        zdot[9] = (u[1] - (jz - jy) * wq * wr) / jx;
+        zdot[10] = (u[2] - (jx - jz) * wp * wr) / jy;
+        zdot[11] = (u[3] - (jy - jx) * wp * wq) / jz;
+        zdot[12] = sqrt(vx * vx + vy * vy + vz * vz);
+        break;
+    }
+    case ORA_DUBINS6: {
+        /* state: x, y, z, yaw psi, pitch gamma, speed v;
+         * control: yaw rate, pitch rate, acceleration */
+        const double psi = z[3], gam = z[4], v = z[5];
+        zdot[0] = v * cos(psi) * cos(gam);
+        zdot[1] = v * sin(psi) * cos(gam);
+        zdot[2] = v * sin(gam);
+        zdot[3] = u[0];
+        zdot[4] = u[1];
+        zdot[5] = u[2];
+        zdot[6] = v;
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+/* Classical four-stage Runge-Kutta step of size h on z = (x, length).
+ * Reading: PropagateODE (Alg. 2 line 4) is not specified; RK4 with a fixed
+ * step dt is used. */
+void ora_rk4_step(const ora_problem* P, double* z, const double* u, double h)
+{
+    const int dim = ora_state_dim(P->dynamics) + 1;
+    double k1[ORA_MAX_STATE + 1], k2[ORA_MAX_STATE + 1], k3[ORA_MAX_STATE + 1],
+        k4[ORA_MAX_STATE + 1], t[ORA_MAX_STATE + 1];
+    ora_deriv(P, z, u, k1);
+    for (int i = 0; i < dim; ++i) t[i] = z[i] + 0.5 * h * k1[i];
+    ora_deriv(P, t, u, k2);
+    for (int i = 0; i < dim; ++i) t[i] = z[i] + 0.5 * h * k2[i];
+    ora_deriv(P, t, u, k3);
+    for (int i = 0; i < dim; ++i) t[i] = z[i] + h * k3[i];
+    ora_deriv(P, t, u, k4);
+    for (int i = 0; i < dim; ++i) z[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+void ora_integrate(const ora_problem* P, const double* x0, const double* u, int32_t n, double h,
+                   double* z_out)
+{
+    const int d = ora_state_dim(P->dynamics);
+    for (int i = 0; i < d; ++i) z_out[i] = x0[i];
+    z_out[d] = 0.0;
+    for (int32_t k = 0; k < n; ++k) ora_rk4_step(P, z_out, u, h);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Valid set (Sec. III): inside the workspace, within the state bounds and   */
+/* outside every obstacle.  Reading: the robot is a point at its position    */
+/* coordinates, obstacles are closed boxes (touching a face collides), the   */
+/* workspace and bounds are closed (touching them is allowed).  For planning */
+/* the boxes grow by `margin` and the workspace, bounds and goal shrink by   */
+/* it (a clearance margin); verification uses margin 0.                      */
+/*                                                                           */
+/* Returns bit 0 = invalid (exact float64 decision), bit 1 = the decision is */
+/* within `band` of a threshold and no check is violated by more than band.  */
+/* ------------------------------------------------------------------------ */
+int ora_point_status(const ora_problem* P, const double* x, double margin, double band,
+                     uint32_t* flags)
+{
+    const int d = ora_state_dim(P->dynamics);
+    int invalid = 0, clear_violation = 0, near = 0;
+    uint32_t fl = 0;
+    for (int a = 0; a < 3; ++a) {
+        double lo = (double)P->ws_lo[a] + margin, hi = (double)P->ws_hi[a] - margin;
+        double s = fmin(x[a] - lo, hi - x[a]);
+        if (s < 0.0) invalid = 1;
+        if (s < -band) clear_violation = 1;
+        else if (fabs(s) <= band) { near = 1; fl |= ORA_FLAG_WORKSPACE; }
+    }
+    for (int i = 0; i < d; ++i) {
+        double blo = (double)P->x_lo[i], bhi = (double)P->x_hi[i];
+        if (isfinite(blo)) {
+            double s = x[i] - (blo + margin);
+            double b = band * fmax(1.0, fabs(blo));
+            if (s < 0.0) invalid = 1;
+            if (s < -b) clear_violation = 1;
+            else if (fabs(s) <= b) { near = 1; fl |= ORA_FLAG_BOUND; }
+        }
+        if (isfinite(bhi)) {
+            double s = (bhi - margin) - x[i];
+            double b = band * fmax(1.0, fabs(bhi));
+            if (s < 0.0) invalid = 1;
+            if (s < -b) clear_violation = 1;
+            else if (fabs(s) <= b) { near = 1; fl |= ORA_FLAG_BOUND; }
+        }
+    }
+    for (int k = 0; k < P->n_boxes; ++k) {
+        const float* bx = P->boxes + 6 * k;
+        /* Chebyshev signed distance to the grown box: <= 0 means inside */
+        double dist = -INFINITY;
+        for (int a = 0; a < 3; ++a) {
+            double lo = (double)bx[a] - margin, hi = (double)bx[3 + a] + margin;
+            dist = fmax(dist, fmax(lo - x[a], x[a] - hi));
+        }
+        if (dist <= 0.0) invalid = 1;
+        if (dist < -band) clear_violation = 1;
+        else if (fabs(dist) <= band) { near = 1; fl |= ORA_FLAG_BOX; }
+    }
+    int amb = (!clear_violation && near) ? 1 : 0;
+    if (amb && flags) *flags |= fl;
+    return invalid | (amb << 1);
+}
+
+/* Region of a state (Alg. 2 line 6).  Reading: a uniform grid over the
+ * workspace, grid[a] cells per position axis, clamped at the far faces,
+ * row-major over (x, y, z); with sign bins, three bits (velocity >= 0) are
+ * appended.  A coordinate within band of an interior face is ambiguous; there a
+ * hinted index is adopted if it is one of the two adjacent indices. */
+static int vel_index(int32_t dyn)
+{
+    return dyn == ORA_DI6 ? 3 : (dyn == ORA_QUAD12 ? 6 : -1);
+}
+
+int64_t ora_cell_of(const ora_problem* P, const double* x, const int64_t* hint, uint32_t* flags)
+{
+    int64_t hidx[3] = {-1, -1, -1};
+    int64_t hbits = -1;
+    if (hint && *hint >= 0) {
+        int64_t c = *hint;
+        if (P->vel_sign_bins) { hbits = c % 8; c /= 8; }
+        hidx[2] = c % P->grid[2]; c /= P->grid[2];
+        hidx[1] = c % P->grid[1]; c /= P->grid[1];
+        hidx[0] = c;
+    }
+    int64_t idx[3];
+    for (int a = 0; a < 3; ++a) {
+        const double lo = P->ws_lo[a], hi = P->ws_hi[a];
+        const int g = P->grid[a];
+        double t = (double)g * (x[a] - lo) / (hi - lo);
+        int64_t i = (int64_t)floor(t);
+        if (i < 0) i = 0;
+        if (i > g - 1) i = g - 1;
+        double kf = nearbyint(t);
+        if (kf >= 1.0 && kf <= (double)(g - 1)) {
+            double face = lo + kf * (hi - lo) / (double)g;
+            if (fabs(x[a] - face) <= P->band) {
+                if (flags) *flags |= ORA_FLAG_CELL;
+                int64_t k = (int64_t)kf;
+                if (hidx[a] == k - 1 || hidx[a] == k) i = hidx[a];
+            }
+        }
+        idx[a] = i;
+    }
+    int64_t cell = (idx[0] * P->grid[1] + idx[1]) * P->grid[2] + idx[2];
+    if (P->vel_sign_bins) {
+        int vi = vel_index(P->dynamics);
+        int64_t bits = 0;
+        for (int a = 0; a < 3; ++a) {
+            int64_t b = x[vi + a] >= 0.0 ? 1 : 0;
+            if (fabs(x[vi + a]) <= P->band) {
+                if (flags) *flags |= ORA_FLAG_VSIGN;
+                if (hbits >= 0) b = (hbits >> (2 - a)) & 1;
+            }
+            bits |= b << (2 - a);
+        }
+        cell = cell * 8 + bits;
+    }
+    return cell;
+}
+
+/* Goal set (Alg. 4 line 5).  Reading: a closed ball over the position
+ * coordinates, tested at the end state of each edge. */
+int ora_goal_test(const ora_problem* P, const double* x, double radius, const uint8_t* hint,
+                  uint32_t* flags)
+{
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double dlt = x[a] - (double)P->goal_center[a];
+        s += dlt * dlt;
+    }
+    double dist = sqrt(s);
+    int in = dist <= radius;
+    if (fabs(dist - radius) <= P->band) {
+        if (flags) *flags |= ORA_FLAG_GOAL;
+        if (hint) in = *hint ? 1 : 0;
+    }
+    return in;
+}
+
+/* One expansion (Alg. 2 lines 4-5): integrate n RK4 steps of size dt from x0
+ * with the constant control u, testing validity after every step.
+ * Reading: validity is checked at the substep end points x_1..x_n (x_0 is a
+ * tree node and already valid) and integration stops at the first invalid
+ * one.  hint_first_invalid < 0 means no hint. */
+void ora_propagate_edge(const ora_problem* P, const double* x0, const float* u, int32_t n,
+                        int32_t hint_first_invalid, ora_edge* out)
+{
+    const int d = ora_state_dim(P->dynamics);
+    const int m = ora_control_dim(P->dynamics);
+    double z[ORA_MAX_STATE + 1];
+    double uu[ORA_MAX_CONTROL] = {0, 0, 0, 0};
+    for (int i = 0; i < d; ++i) z[i] = x0[i];
+    z[d] = 0.0;
+    for (int i = 0; i < m; ++i) uu[i] = (double)u[i];
+    const double h = (double)P->dt;
+    out->first_invalid = 0;
+    out->flags = 0;
+    out->substeps = 0;
+    for (int32_t k = 1; k <= n; ++k) {
+        ora_rk4_step(P, z, uu, h);
+        out->substeps = k;
+        uint32_t fl = 0;
+        int st = ora_point_status(P, z, (double)P->margin, P->band, &fl);
+        int bad = st & 1;
+        if (st & 2) {
+            out->flags |= fl;
+            if (hint_first_invalid >= 0) bad = (hint_first_invalid == k);
+        }
+        if (bad) {
+            out->first_invalid = k;
+            break;
+        }
+    }
+    for (int i = 0; i < d; ++i) out->xn[i] = z[i];
+    for (int i = d; i < ORA_MAX_STATE; ++i) out->xn[i] = 0.0;
+    out->length = z[d];
+}
+
+/* ------------------------------------------------------------------------ */
+/* App. A: exclusiveScan of a boolean mask and GraphSearch (Alg. 5),         */
+/* I[S[tid]] = tid for every set tid.  The count of set entries is           */
+/* S[n-1] + mask[n-1] (the last entry itself may be set).                    */
+/* ------------------------------------------------------------------------ */
+void ora_exclusive_scan(const uint8_t* mask, int64_t n, int64_t* S)
+{
+    int64_t acc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        S[i] = acc;
+        acc += mask[i] ? 1 : 0;
+    }
+}
+
+int64_t ora_graph_search(const uint8_t* mask, const int64_t* S, int64_t n, int64_t* I)
+{
+    for (int64_t tid = 0; tid < n; ++tid)
+        if (mask[tid]) I[S[tid]] = tid;
+    return n > 0 ? S[n - 1] + (mask[n - 1] ? 1 : 0) : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tree state                                                                */
+/* ------------------------------------------------------------------------ */
+static int64_t n_cells_of(const ora_problem* P)
+{
+    return (int64_t)P->grid[0] * P->grid[1] * P->grid[2] * (P->vel_sign_bins ? 8 : 1);
+}
+
+static int64_t survivors_bound(const ora_problem* P)
+{
+    int64_t slots = (int64_t)P->n_select * P->samples_per_node;
+    int64_t cells = n_cells_of(P);
+    return slots < cells ? slots : cells;
+}
+
+/* lexicographic (cost, id): equal costs are ordered by id (Reading: the
+ * paper compares costs for equality; ties go to the lower id, so a tree node
+ * beats this iteration's candidates and candidates are ordered by slot) */
+static int key_less(double c1, int64_t i1, double c2, int64_t i2)
+{
+    if (c1 < c2) return 1;
+    if (c1 > c2) return 0;
+    return i1 < i2;
+}
+
+/* Alg. 1 lines 1-5.  Reading: the root's region holds cost 0 and the root id,
+ * so that the root counts as its region's best node. */
+int ora_init(const ora_problem* P, ora_tree* T)
+{
+    const int d = ora_state_dim(P->dynamics);
+    const int m = ora_control_dim(P->dynamics);
+    if (d < 0 || m < 0) return ORA_ERR_ARG;
+    if (P->cost != ORA_COST_TIME && P->cost != ORA_COST_PATH) return ORA_ERR_ARG;
+    for (int a = 0; a < 3; ++a) {
+        if (P->grid[a] < 1) return ORA_ERR_ARG;
+        if (!(P->ws_lo[a] < P->ws_hi[a])) return ORA_ERR_ARG;
+    }
+    for (int i = 0; i < m; ++i)
+        if (!(P->u_lo[i] <= P->u_hi[i])) return ORA_ERR_ARG;
+    if (P->vel_sign_bins && vel_index(P->dynamics) < 0) return ORA_ERR_ARG;
+    if (P->n_select < 1 || P->samples_per_node < 1) return ORA_ERR_ARG;
+    if (P->steps_min < 1 || P->steps_max < P->steps_min) return ORA_ERR_ARG;
+    if (!(P->dt > 0.0f) || !(P->margin >= 0.0f) || !(P->goal_radius > P->margin)) return ORA_ERR_ARG;
+    if (P->n_boxes < 0 || (P->n_boxes > 0 && !P->boxes)) return ORA_ERR_ARG;
+    if (T->cap < 1 + survivors_bound(P)) return ORA_ERR_ARG;
+    if (T->n_cells != n_cells_of(P)) return ORA_ERR_ARG;
+
+    double x0[ORA_MAX_STATE];
+    for (int i = 0; i < ORA_MAX_STATE; ++i) x0[i] = i < d ? (double)P->x_init[i] : 0.0;
+    if (ora_point_status(P, x0, (double)P->margin, 0.0, NULL) & 1) return ORA_ERR_INVALID_START;
+
+    for (int64_t c = 0; c < T->n_cells; ++c) {
+        T->tbl_cost[c] = INFINITY;
+        T->tbl_id[c] = -1;
+    }
+    for (int i = 0; i < ORA_MAX_STATE; ++i) T->x[i] = x0[i];
+    for (int i = 0; i < ORA_MAX_CONTROL; ++i) T->u[i] = 0.0f;
+    T->steps[0] = 0;
+    T->parent[0] = -1;
+    T->cost[0] = 0.0;
+    T->cell[0] = ora_cell_of(P, x0, NULL, NULL);
+    T->status[0] = ORA_ACTIVE;
+    T->icount[0] = 0;
+    T->tbl_cost[T->cell[0]] = 0.0;
+    T->tbl_id[T->cell[0]] = 0;
+    T->n_tree = 1;
+    T->cursor = 0;
+    T->iter = 0;
+    T->sol_cost = INFINITY;
+    T->sol_id = -1;
+    T->first_sol_iter = -1;
+    T->full = 0;
+    T->last_n_sel = T->last_n_valid = T->last_n_surv = 0;
+    return ORA_OK;
+}
+
+/* Which nodes of V_A are expanded this iteration.  Reading: at most n_select
+ * nodes are expanded; V_A is ordered by region index rotated to start at the
+ * cursor region and the first n_select are taken; the cursor moves past the
+ * last one taken.  Every active node is therefore expanded again within a
+ * bounded number of iterations (Thm. 1 needs every region-best node to be
+ * selected infinitely often). */
+typedef struct {
+    int64_t rot, idx;
+} ora_rank;
+
+static int cmp_rank(const void* a, const void* b)
+{
+    const ora_rank* x = (const ora_rank*)a;
+    const ora_rank* y = (const ora_rank*)b;
+    if (x->rot != y->rot) return x->rot < y->rot ? -1 : 1;
+    if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;
+    return 0;
+}
+
+int64_t ora_select(const ora_problem* P, const ora_tree* T, int64_t* sel, int64_t* cursor_next)
+{
+    int64_t n_active = 0;
+    for (int64_t i = 0; i < T->n_tree; ++i)
+        if (T->status[i] == ORA_ACTIVE) ++n_active;
+    ora_rank* r = (ora_rank*)malloc(sizeof(ora_rank) * (size_t)(n_active > 0 ? n_active : 1));
+    int64_t k = 0;
+    for (int64_t i = 0; i < T->n_tree; ++i) {
+        if (T->status[i] != ORA_ACTIVE) continue;
+        int64_t rot = T->cell[i] - T->cursor;
+        if (rot < 0) rot += T->n_cells;
+        r[k].rot = rot;
+        r[k].idx = i;
+        ++k;
+    }
+    qsort(r, (size_t)n_active, sizeof(ora_rank), cmp_rank);
+    int64_t n_sel = n_active < P->n_select ? n_active : P->n_select;
+    for (int64_t j = 0; j < n_sel; ++j) sel[j] = r[j].idx;
+    *cursor_next = T->cursor;
+    if (n_sel > 0) *cursor_next = (T->cell[sel[n_sel - 1]] + 1) % T->n_cells;
+    free(r);
+    return n_sel;
+}
+
+/* Alg. 3 PruneNodes, one node after another, in the printed order.
+ * "x is its region's best" is read as: the region's (cost, id) minimum is x
+ * itself (ties by id, see key_less).  Terminal nodes are visited too; they
+ * can never be their region's best again, so they stay terminal. */
+void ora_prune(const ora_problem* P, ora_tree* T)
+{
+    for (int64_t i = 0; i < T->n_tree; ++i) {
+        const int best = T->tbl_id[T->cell[i]] == i;
+        /* lines 3-7: a dormant region-best node counts up and wakes past I_max */
+        if (best && T->status[i] == ORA_INACTIVE) {
+            T->icount[i] += 1;
+            if (T->icount[i] > P->i_max) {
+                T->status[i] = ORA_ACTIVE;
+                continue;
+            }
+        }
+        /* lines 8-9: a woken region-best node is left alone */
+        if (T->icount[i] > P->i_max && best) continue;
+        /* lines 10-12: beaten in its region -> terminal */
+        if (!best) {
+            T->status[i] = ORA_TERMINAL;
+            continue;
+        }
+        /* lines 13-15: an ancestor beaten in its own region -> inactive */
+        for (int64_t p = T->parent[i]; p >= 0; p = T->parent[p]) {
+            if (T->tbl_id[T->cell[p]] != p) {
+                T->status[i] = ORA_INACTIVE;
+                break;
+            }
+        }
+    }
+}
+
+static int near_tie(double a, double b, double rel)
+{
+    double s = fmax(fabs(a), fabs(b));
+    return fabs(a - b) <= rel * s;
+}
+
+/* One iteration of Alg. 1 (lines 7-9): Propagate, PruneNodes, UpdateTree.
+ * Reading: before anything else, if n_tree plus the most survivors one
+ * iteration can add exceeds the capacity, nothing is done and ORA_FULL is
+ * returned (the paper only notes that overflowing t_e would fault). */
+int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H)
+{
+    const int d = ora_state_dim(P->dynamics);
+    const int m = ora_control_dim(P->dynamics);
+    const int64_t K = P->samples_per_node;
+    if (T->full || T->n_tree + survivors_bound(P) > T->cap) {
+        T->full = 1;
+        C->n_slots = 0;
+        return ORA_FULL;
+    }
+    if (C->cap_slots < (int64_t)P->n_select * K) return ORA_ERR_ARG;
+    const int64_t n_tree = T->n_tree;
+
+    /* which nodes of V_A are expanded */
+    int64_t* sel = (int64_t*)malloc(sizeof(int64_t) * (size_t)P->n_select);
+    int64_t cursor_next = T->cursor;
+    const int64_t n_sel = ora_select(P, T, sel, &cursor_next);
+    const int64_t n_slots = n_sel * K;
+    C->n_slots = n_slots;
+    C->substeps_total = 0;
+
+    /* Alg. 2 lines 1-7: each of the K expansions of each selected node */
+    int64_t n_valid = 0;
+    for (int64_t s = 0; s < n_slots; ++s) {
+        const int64_t par = sel[s / K];
+        float u[ORA_MAX_CONTROL];
+        int32_t n;
+        ora_sample(P, (uint32_t)T->iter, (uint32_t)s, u, &n);
+        C->parent[s] = par;
+        for (int i = 0; i < ORA_MAX_CONTROL; ++i) C->u[s * ORA_MAX_CONTROL + i] = u[i];
+        C->n[s] = n;
+        ora_edge e;
+        const int32_t hint_fi = (H && H->first_invalid) ? H->first_invalid[s] : -1;
+        ora_propagate_edge(P, &T->x[par * ORA_MAX_STATE], u, n, hint_fi, &e);
+        C->substeps[s] = e.substeps;
+        C->substeps_total += e.substeps;
+        C->first_invalid[s] = e.first_invalid;
+        C->flags[s] = e.flags;
+        C->valid[s] = e.first_invalid == 0;
+        for (int i = 0; i < ORA_MAX_STATE; ++i) C->xn[s * ORA_MAX_STATE + i] = e.xn[i];
+        C->survivor[s] = 0;
+        C->new_index[s] = -1;
+        C->goal[s] = 0;
+        C->cell[s] = -1;
+        C->cost[s] = INFINITY;
+        if (!C->valid[s]) continue;
+        ++n_valid;
+        uint32_t fl = 0;
+        C->cell[s] = ora_cell_of(P, e.xn, (H && H->cell) ? &H->cell[s] : NULL, &fl);
+        /* Alg. 2 line 7: additive cost; TIME counts steps, PATH adds length */
+        const double edge_cost = P->cost == ORA_COST_TIME ? (double)n : e.length;
+        C->cost[s] = T->cost[par] + edge_cost;
+        C->goal[s] = (uint8_t)ora_goal_test(P, e.xn, (double)P->goal_radius - (double)P->margin,
+                                            (H && H->goal) ? &H->goal[s] : NULL, &fl);
+        C->flags[s] |= fl;
+    }
+
+    /* Alg. 2 line 8: region minimum over this iteration's arrivals; the
+     * arrival id of slot s is n_tree + s */
+    double* old_cost = (double*)malloc(sizeof(double) * (size_t)T->n_cells);
+    int64_t* old_id = (int64_t*)malloc(sizeof(int64_t) * (size_t)T->n_cells);
+    memcpy(old_cost, T->tbl_cost, sizeof(double) * (size_t)T->n_cells);
+    memcpy(old_id, T->tbl_id, sizeof(int64_t) * (size_t)T->n_cells);
+    for (int64_t s = 0; s < n_slots; ++s) {
+        if (!C->valid[s]) continue;
+        const int64_t c = C->cell[s];
+        if (key_less(C->cost[s], n_tree + s, T->tbl_cost[c], T->tbl_id[c])) {
+            T->tbl_cost[c] = C->cost[s];
+            T->tbl_id[c] = n_tree + s;
+        }
+    }
+    if (P->cost == ORA_COST_PATH) {
+        /* path lengths are real numbers: a rival within the relative band of
+         * the minimum makes the region's winner ambiguous */
+        uint8_t* amb = (uint8_t*)calloc((size_t)T->n_cells, 1);
+        for (int64_t s = 0; s < n_slots; ++s) {
+            if (!C->valid[s]) continue;
+            const int64_t c = C->cell[s];
+            if (T->tbl_id[c] != n_tree + s && near_tie(C->cost[s], T->tbl_cost[c], P->band))
+                amb[c] = 1;
+        }
+        for (int64_t c = 0; c < T->n_cells; ++c)
+            if (old_id[c] >= 0 && old_id[c] != T->tbl_id[c] &&
+                near_tie(old_cost[c], T->tbl_cost[c], P->band))
+                amb[c] = 1;
+        for (int64_t s = 0; s < n_slots; ++s)
+            if (C->valid[s] && amb[C->cell[s]] && near_tie(C->cost[s], T->tbl_cost[C->cell[s]], P->band))
+                C->flags[s] |= ORA_FLAG_TIE;
+        if (H && H->survivor) {
+            for (int64_t c = 0; c < T->n_cells; ++c) {
+                if (!amb[c]) continue;
+                int64_t pick = -1;
+                for (int64_t s = 0; s < n_slots; ++s)
+                    if (C->valid[s] && C->cell[s] == c && H->survivor[s]) pick = s;
+                if (pick >= 0 && near_tie(C->cost[pick], T->tbl_cost[c], P->band)) {
+                    T->tbl_cost[c] = C->cost[pick];
+                    T->tbl_id[c] = n_tree + pick;
+                } else if (pick < 0 && old_id[c] >= 0 && near_tie(old_cost[c], T->tbl_cost[c], P->band)) {
+                    T->tbl_cost[c] = old_cost[c];
+                    T->tbl_id[c] = old_id[c];
+                }
+            }
+        }
+        free(amb);
+    }
+    free(old_cost);
+    free(old_id);
+
+    /* Alg. 3 against the updated regions */
+    ora_prune(P, T);
+
+    /* Alg. 4 + App. A: V_U = arrivals still holding their region minimum;
+     * exclusive scan + GraphSearch give each its place |T| + rank */
+    uint8_t* mask = (uint8_t*)calloc((size_t)(n_slots > 0 ? n_slots : 1), 1);
+    int64_t* S = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_slots > 0 ? n_slots : 1));
+    int64_t* I = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_slots > 0 ? n_slots : 1));
+    for (int64_t s = 0; s < n_slots; ++s)
+        mask[s] = C->valid[s] && T->tbl_id[C->cell[s]] == n_tree + s;
+    ora_exclusive_scan(mask, n_slots, S);
+    const int64_t n_surv = ora_graph_search(mask, S, n_slots, I);
+    for (int64_t t = 0; t < n_surv; ++t) {
+        const int64_t s = I[t];
+        const int64_t i = n_tree + t;
+        for (int k = 0; k < ORA_MAX_STATE; ++k) T->x[i * ORA_MAX_STATE + k] = k < d ? C->xn[s * ORA_MAX_STATE + k] : 0.0;
+        for (int k = 0; k < ORA_MAX_CONTROL; ++k) T->u[i * ORA_MAX_CONTROL + k] = k < m ? C->u[s * ORA_MAX_CONTROL + k] : 0.0f;
+        T->steps[i] = C->n[s];
+        T->parent[i] = C->parent[s];
+        T->cost[i] = C->cost[s];
+        T->cell[i] = C->cell[s];
+        T->status[i] = ORA_ACTIVE;
+        T->icount[i] = 0;
+        T->tbl_id[C->cell[s]] = i;
+        C->survivor[s] = 1;
+        C->new_index[s] = i;
+        /* Alg. 4 lines 5-7: a goal node that beats the solution replaces it */
+        if (C->goal[s] && key_less(C->cost[s], i, T->sol_cost, T->sol_id)) {
+            if (T->sol_id < 0) T->first_sol_iter = T->iter;
+            T->sol_cost = C->cost[s];
+            T->sol_id = i;
+        }
+    }
+    T->n_tree = n_tree + n_surv;
+    T->cursor = cursor_next;
+    T->last_n_sel = n_sel;
+    T->last_n_valid = n_valid;
+    T->last_n_surv = n_surv;
+    T->iter += 1;
+    free(mask);
+    free(S);
+    free(I);
+    free(sel);
+    return ORA_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trajectory check: re-integrate the controls open loop from x_init in      */
+/* float64, test every substep against the exact valid set (no margin),      */
+/* test the end state against the exact goal ball and recompute the cost     */
+/* (additivity, Assumption 1).                                               */
+/* ------------------------------------------------------------------------ */
+int ora_verify(const ora_problem* P, int32_t n_edges, const float* controls, const int32_t* steps,
+               const float* states, double reported_cost, ora_verify_report* rep)
+{
+    const int d = ora_state_dim(P->dynamics);
+    const int m = ora_control_dim(P->dynamics);
+    memset(rep, 0, sizeof(*rep));
+    rep->first_bad_edge = -1;
+    rep->first_bad_substep = -1;
+    rep->min_clearance = INFINITY;
+    rep->collision_free = 1;
+    rep->within_bounds = 1;
+    rep->starts_at_init = 1;
+    if (states)
+        for (int i = 0; i < d; ++i)
+            if (states[i] != P->x_init[i]) rep->starts_at_init = 0;
+    double z[ORA_MAX_STATE + 1];
+    for (int i = 0; i < d; ++i) z[i] = (double)P->x_init[i];
+    z[d] = 0.0;
+    const double h = (double)P->dt;
+    double total_steps = 0.0, length = 0.0;
+    for (int32_t e = 0; e < n_edges; ++e) {
+        double uu[ORA_MAX_CONTROL] = {0, 0, 0, 0};
+        for (int i = 0; i < m; ++i) uu[i] = (double)controls[e * ORA_MAX_CONTROL + i];
+        z[d] = 0.0;
+        for (int32_t k = 1; k <= steps[e]; ++k) {
+            ora_rk4_step(P, z, uu, h);
+            for (int b = 0; b < P->n_boxes; ++b) {
+                const float* bx = P->boxes + 6 * b;
+                double dist = -INFINITY;
+                for (int a = 0; a < 3; ++a)
+                    dist = fmax(dist, fmax((double)bx[a] - z[a], z[a] - (double)bx[3 + a]));
+                if (dist < rep->min_clearance) rep->min_clearance = dist;
+                if (dist <= 0.0 && rep->collision_free) {
+                    rep->collision_free = 0;
+                    if (rep->first_bad_edge < 0) { rep->first_bad_edge = e; rep->first_bad_substep = k; }
+                }
+            }
+            uint32_t fl = 0;
+            /* bounds and workspace with margin 0: bit 0 covers them together
+             * with the boxes, so test the non-box part on its own */
+            ora_problem Q = *P;
+            Q.n_boxes = 0;
+            if (ora_point_status(&Q, z, 0.0, 0.0, &fl) & 1) {
+                if (rep->within_bounds && rep->first_bad_edge < 0) {
+                    rep->first_bad_edge = e;
+                    rep->first_bad_substep = k;
+                }
+                rep->within_bounds = 0;
+            }
+        }
+        total_steps += steps[e];
+        length += z[d];
+        if (states) {
+            for (int i = 0; i < d; ++i) {
+                double gap = fabs(z[i] - (double)states[(e + 1) * ORA_MAX_STATE + i]);
+                if (gap > rep->max_gap) rep->max_gap = gap;
+            }
+        }
+    }
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double dlt = z[a] - (double)P->goal_center[a];
+        s += dlt * dlt;
+    }
+    rep->goal_distance = sqrt(s);
+    rep->reaches_goal = n_edges > 0 && rep->goal_distance <= (double)P->goal_radius;
+    if (P->cost == ORA_COST_TIME) {
+        rep->cost = total_steps;
+        rep->cost_ok = reported_cost == total_steps;
+    } else {
+        rep->cost = length;
+        rep->cost_ok = fabs(reported_cost - length) <= 1e-4 * fmax(1.0, fabs(length));
+    }
+    rep->ok = rep->starts_at_init && rep->collision_free && rep->within_bounds &&
+              rep->reaches_goal && rep->cost_ok;
+    return rep->ok ? ORA_OK : ORA_ERR_ARG;
+}

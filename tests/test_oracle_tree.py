@@ -1,0 +1,238 @@
+"""Pins of the oracle's node-set logic: Alg. 3 on hand-built trees with
+hand-computed outcomes, the rotating selection, and invariants that every
+iteration of a full run must keep (brute-force region minimum, additive cost,
+one live node per region, monotone region and solution costs)."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+A, I, T = 0, 1, 2  # ACTIVE, INACTIVE, TERMINAL
+
+
+def _tree(ora, nodes, i_max=2, n_select=2, **kw):
+    """nodes: list of (parent, cell, cost, status, icount); region owners are
+    the lowest (cost, id) per cell unless overridden by the caller."""
+    w = W.make_workload("di6", 0, i_max=i_max, n_select=n_select, samples=2, tree_cap=64, **kw)
+    P = ora.Problem(w.problem, w.params)
+    tr = ora.Tree(P, cap=64)
+    for i, (par, cell, cost, st, ic) in enumerate(nodes):
+        tr.parent[i], tr.cell[i], tr.cost[i], tr.status[i], tr.icount[i] = par, cell, cost, st, ic
+        if cost < tr.tbl_cost[cell] or (cost == tr.tbl_cost[cell] and i < tr.tbl_id[cell]):
+            tr.tbl_cost[cell], tr.tbl_id[cell] = cost, i
+    tr.set_scalars(n_tree=len(nodes))
+    return tr
+
+
+def test_prune_all_best_stays_active(ora):
+    tr = _tree(ora, [(-1, 0, 0, A, 0), (0, 1, 5, A, 0), (1, 2, 9, A, 0), (0, 3, 6, A, 0)])
+    tr.prune()
+    assert tr.status[:4].tolist() == [A, A, A, A]
+
+
+def test_prune_beaten_node_terminal_and_descendants_inactive(ora):
+    # node 5 beats node 1 in cell 1; 2, 3 (children of 1) and 4 (grandchild) go dormant
+    nodes = [(-1, 0, 0, A, 0), (0, 1, 5, A, 0), (1, 2, 9, A, 0), (1, 3, 8, A, 0),
+             (2, 4, 12, A, 0), (0, 1, 4, A, 0), (0, 6, 7, A, 0)]
+    tr = _tree(ora, nodes)
+    assert tr.tbl_id[1] == 5
+    tr.prune()
+    assert tr.status[:7].tolist() == [A, T, I, I, I, A, A]
+    assert tr.icount[:7].tolist() == [0] * 7
+
+
+def test_prune_inactive_counts_then_wakes(ora):
+    # node 2 is dormant and region-best; I_max = 2: counts 1 -> 2 (dormant), 3 (> I_max: wakes)
+    nodes = [(-1, 0, 0, A, 0), (0, 1, 5, T, 0), (1, 2, 9, I, 1), (0, 1, 4, A, 0)]
+    tr = _tree(ora, nodes)
+    tr.prune()
+    assert tr.status[2] == I and tr.icount[2] == 2
+    tr.prune()
+    assert tr.status[2] == A and tr.icount[2] == 3
+    # woken and still best: left alone although its parent stays beaten (lines 8-9)
+    tr.prune()
+    assert tr.status[2] == A and tr.icount[2] == 3
+
+
+def test_prune_dormant_or_woken_but_beaten_is_terminal(ora):
+    nodes = [(-1, 0, 0, A, 0), (0, 1, 5, I, 1), (0, 2, 5, A, 3), (0, 1, 3, A, 0), (0, 2, 4, A, 0)]
+    tr = _tree(ora, nodes)
+    tr.prune()
+    assert tr.status[:5].tolist() == [A, T, T, A, A]
+    assert tr.icount[1] == 1  # a beaten dormant node does not count
+
+
+def test_prune_grandparent_beaten(ora):
+    # 3's parent 2 is best, grandparent 1 is beaten by 4
+    nodes = [(-1, 0, 0, A, 0), (0, 1, 6, A, 0), (1, 2, 9, A, 0), (2, 3, 14, A, 0), (0, 1, 5, A, 0)]
+    tr = _tree(ora, nodes)
+    tr.prune()
+    assert tr.status[:5].tolist() == [A, T, I, I, A]
+
+
+def test_prune_ties_go_to_the_lower_id(ora):
+    nodes = [(-1, 0, 0, A, 0), (0, 1, 5, A, 0), (0, 1, 5, A, 0)]
+    tr = _tree(ora, nodes)
+    tr.prune()
+    assert tr.status[:3].tolist() == [A, A, T]
+
+
+def test_select_rotates_from_the_cursor(ora):
+    nodes = [(-1, 10, 0, A, 0), (0, 3, 5, A, 0), (0, 7, 5, A, 0), (0, 20, 5, A, 0),
+             (0, 12, 5, I, 0), (0, 15, 5, T, 0)]
+    tr = _tree(ora, nodes, n_select=2)
+    tr.set_scalars(cursor=8)
+    sel, cur = tr.select()
+    assert sel.tolist() == [0, 3] and cur == 21
+    tr.set_scalars(cursor=21)
+    sel, cur = tr.select()
+    assert sel.tolist() == [1, 2] and cur == 8
+    tr.set_scalars(cursor=0)
+    sel, cur = tr.select()
+    assert sel.tolist() == [1, 2]
+
+
+def test_select_takes_all_when_few_are_active(ora):
+    nodes = [(-1, 10, 0, I, 0), (0, 3, 5, A, 0)]
+    tr = _tree(ora, nodes, n_select=4)
+    sel, cur = tr.select()
+    assert sel.tolist() == [1] and cur == 4
+
+
+def _run_with_invariants(ora, w, iterations):
+    P = ora.Problem(w.problem, w.params)
+    tr = ora.Tree(P)
+    assert tr.init() == ora.OK
+    nc = P.n_cells
+    K = w.params.samples_per_node
+    prev_tbl = tr.tbl_cost.copy()
+    prev_sol = np.inf
+    sols = []
+    for it in range(iterations):
+        n0 = tr.n_tree
+        pre_status = tr.status[:n0].copy()
+        pre_cost = tr.cost[:n0].copy()
+        pre_cell = tr.cell[:n0].copy()
+        pre_owner = tr.tbl_id.copy()
+        sel, _ = tr.select()
+        rc = tr.step()
+        if rc == ora.FULL:
+            break
+        c = tr.cands.view()
+        S = tr.cands.n_slots
+        assert S == len(sel) * K
+        assert np.array_equal(c["parent"], np.repeat(sel, K))
+        # selected nodes were ACTIVE
+        assert np.all(pre_status[sel] == A)
+        # brute-force region minimum over incumbents and this iteration's arrivals
+        best = {}
+        for cell in set(c["cell"][c["valid"] == 1].tolist()):
+            if pre_owner[cell] >= 0:
+                best[cell] = (pre_cost[pre_owner[cell]], pre_owner[cell])
+        for s in range(S):
+            if c["valid"][s]:
+                key = (c["cost"][s], n0 + s)
+                cell = int(c["cell"][s])
+                if cell not in best or key < best[cell]:
+                    best[cell] = key
+        winners = {v[1] - n0 for v in best.values() if v[1] >= n0}
+        surv = set(np.flatnonzero(c["survivor"]).tolist())
+        assert surv == winners
+        # survivors appended in slot order
+        order = sorted(surv)
+        assert [int(c["new_index"][s]) for s in order] == list(range(n0, n0 + len(order)))
+        n1 = tr.n_tree
+        assert n1 == n0 + len(order) <= n0 + min(nc, S)
+        # additive cost, parent before child, exact re-integration of stored edges
+        for i in range(n0, n1):
+            p = tr.parent[i]
+            assert 0 <= p < i
+            ec = tr.steps[i] if w.problem.cost == "TIME" else None
+            z = ora.integrate(P, tr.x[p, : P.d], tr.u[i, : P.m].astype(float), int(tr.steps[i]))
+            assert np.array_equal(z[: P.d], tr.x[i, : P.d])
+            if ec is not None:
+                assert tr.cost[i] == tr.cost[p] + ec
+            else:
+                assert abs(tr.cost[i] - (tr.cost[p] + z[P.d])) <= 1e-12 * max(1.0, tr.cost[i])
+            assert tr.cell[i] == ora.cell_of(P, tr.x[i, : P.d])[0]
+        # one live node per region, and it is the region's owner
+        live = np.flatnonzero(tr.status[:n1] != T)
+        cells = tr.cell[live]
+        assert len(set(cells.tolist())) == len(cells)
+        assert np.all(tr.tbl_id[cells] == live)
+        reached = tr.tbl_id >= 0
+        owners = tr.tbl_id[reached]
+        assert np.all(tr.status[owners] != T)
+        assert np.all(tr.tbl_cost[reached] == tr.cost[owners])
+        # region costs and the solution never increase
+        assert np.all(tr.tbl_cost <= prev_tbl)
+        prev_tbl = tr.tbl_cost.copy()
+        assert tr.c.sol_cost <= prev_sol
+        prev_sol = tr.c.sol_cost
+        if tr.c.sol_id >= 0:
+            sols.append(int(tr.c.sol_id))
+            assert ora.goal_test(P, tr.x[tr.c.sol_id, : P.d])[0]
+    return P, tr, sols
+
+
+@pytest.mark.parametrize("cost", ["TIME", "PATH_LENGTH"])
+def test_full_run_invariants_double_integrator(ora, cost):
+    w = W.make_workload("di6", 1, iterations=80, cost=cost)
+    P, tr, sols = _run_with_invariants(ora, w, 80)
+    assert tr.n_tree > 1000
+    assert sols, "no solution in 80 iterations"
+    # the returned trajectory re-verifies
+    ctrl, steps, states = tr.path_to(tr.c.sol_id)
+    rep = ora.verify(P, ctrl, steps, states, tr.c.sol_cost)
+    assert rep["ok"], rep
+    assert rep["max_gap"] < 1e-6  # stored states are passed as float32
+
+
+def test_full_run_invariants_quadrotor_small(ora):
+    w = W.make_workload("quad12", 2, n_select=48, samples=6, grid=(8, 8, 8), tree_cap=1 << 15)
+    _run_with_invariants(ora, w, 40)
+
+
+def test_full_run_invariants_dubins_small(ora):
+    w = W.make_workload("dubins6", 3, n_select=48, samples=6, grid=(16, 16, 8), tree_cap=1 << 15)
+    _run_with_invariants(ora, w, 40)
+
+
+def test_coarse_grid_double_integrator_cannot_leave_the_start_region(ora):
+    """With 8^3 regions an edge from rest moves at most 0.045 (< 0.075 to the
+    face) and every arrival in the start region costs more than the root."""
+    w = W.make_workload("di6", 0, grid=(8, 8, 8))
+    P = ora.Problem(w.problem, w.params)
+    tr = ora.Tree(P)
+    tr.init()
+    for _ in range(20):
+        tr.step()
+    assert tr.n_tree == 1
+
+
+def test_capacity_precheck_stops_cleanly(ora):
+    w = W.make_workload("di6", 0, n_select=16, samples=4, tree_cap=1 + 64 + 30)
+    P = ora.Problem(w.problem, w.params)
+    tr = ora.Tree(P)
+    assert tr.init() == ora.OK
+    rcs = [tr.step() for _ in range(50)]
+    assert ora.FULL in rcs
+    k = rcs.index(ora.FULL)
+    n = tr.n_tree
+    assert n + 64 > tr.c.cap
+    assert all(rc == ora.FULL for rc in rcs[k:])
+    assert tr.n_tree == n
+
+
+def test_init_rejects_bad_problems(ora):
+    w = W.make_workload("di6", 0)
+    w.problem.x_init[:3] = w.problem.boxes[0, :3] + 1e-3  # inside a box
+    P = ora.Problem(w.problem, w.params)
+    assert ora.Tree(P).init() == ora.ERR_INVALID_START
+    w = W.make_workload("di6", 0)
+    w.params.steps_min = 0
+    assert ora.Tree(ora.Problem(w.problem, w.params)).init() == ora.ERR_ARG
+    w = W.make_workload("dubins6", 0)
+    w.params.vel_sign_bins = 1
+    assert ora.Tree(ora.Problem(w.problem, w.params)).init() == ora.ERR_ARG
