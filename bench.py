@@ -1,0 +1,177 @@
+"""Benchmark: propagated edges/s of the Kino-PAX+ iteration on one MI355X.
+
+A step is one planner iteration (select -> propagate -> prune -> insert) of one
+query on the 12D quadrotor workload (4096 nodes x 32 samples per iteration,
+64-box wall with two slots, 16^3 x 2^3 regions, tree capacity 2^21).  Inputs
+live in HBM before timing starts; every count stays on the device.
+
+Prints one JSON line.  `roofline` covers the dominant kernel (propagate, bound
+by float32 ALU work); `cpu_baseline` is the float64 oracle replaying the same
+workload on the host from the GPU tree at the start of the timed region.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic float32 FLOPs of one RK4 substep (FMA = 2, each transcendental,
+# reciprocal or square root = 1): 13 per integrated component for the stage
+# and combination updates plus four evaluations of f.
+#   DI6      6 components, f has no arithmetic                  -> 78
+#   QUAD12  12 components, f = 6 sin/cos + 1 rcp + 35 mul/FMA   -> 156 + 4 * 42 = 324
+#   DUBINS6  6 components, f = 4 sin/cos + 4 mul                 -> 78 + 4 * 8 = 110
+# The path-length cost integrates one more component and its rate
+# (speed: 3 FMA-equivalents + sqrt for DI6/QUAD12, none for DUBINS6).
+FLOPS_PER_SUBSTEP = {
+    ("DI6", "TIME"): 78, ("DI6", "PATH_LENGTH"): 78 + 13 + 4 * 6,
+    ("QUAD12", "TIME"): 324, ("QUAD12", "PATH_LENGTH"): 324 + 13 + 4 * 6,
+    ("DUBINS6", "TIME"): 110, ("DUBINS6", "PATH_LENGTH"): 110 + 13,
+}
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 FLOP/clk)
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=150)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="quad12", choices=["di6", "quad12", "dubins6"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="bound on the oracle CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {a.gpus} is not supported "
+              "(the planner query runs on a single device)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2602_02846_amd as K
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    K.lib()  # fails loudly when the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = W.make_workload(a.workload, a.seed)
+    prob, prm = w.problem, w.params
+
+    planner = K.Planner(prob, prm, device="cuda:0")
+    print(f"[bench] {a.workload}: {prm.n_select} x {prm.samples_per_node} slots, "
+          f"{prm.n_cells} regions, cap {prm.tree_cap}; warmup {a.warmup}", file=sys.stderr,
+          flush=True)
+    planner.iterate(a.warmup)
+    planner.sync()
+    snap_start = planner.snapshot() if not a.no_cpu_baseline else None
+    c0 = planner.counters()
+    if not a.no_timing:
+        planner.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    planner.iterate(a.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc = planner.sync()
+    c1 = planner.counters()
+    done = int(c1["iteration"] - c0["iteration"])
+    st = planner.stats(int(c0["iteration"]), done) if done > 0 else None
+    edges = int((st["n_select"].astype(np.int64) * prm.samples_per_node).sum()) if done else 0
+    substeps = int(st["substeps"].sum()) if done else 0
+    elapsed = t1 - t0
+    value = edges / elapsed if elapsed > 0 else 0.0
+    print(f"[bench] timed {done} iterations in {elapsed * 1e3:.2f} ms, {edges} edges, "
+          f"status {rc}", file=sys.stderr, flush=True)
+
+    roofline = None
+    kernel_ms = None
+    if not a.no_timing:
+        ms, launches = planner.read_timing()
+        kernel_ms = {name: (ms[i] / launches[i] if launches[i] else None)
+                     for i, name in enumerate(["propagate", "prune_flags", "insert",
+                                               "finalize_select"])}
+        if launches[0]:
+            fl = FLOPS_PER_SUBSTEP[(prob.dynamics, prob.cost)] * substeps / launches[0]
+            avg_s = ms[0] / launches[0] / 1e3
+            achieved = fl / avg_s / 1e12
+            roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                        "traffic": None}
+
+    # time to first solution and cost, from device timestamps of this query
+    it_done = int(c1["iteration"])
+    all_st = planner.stats(max(0, it_done - 65536), min(it_done, 65536))
+    rate = planner.clock_rate_khz() * 1e3
+    first_it = int(c1["first_solution_iteration"])
+    sol = planner.solution()
+    t_first = None
+    if first_it >= 0 and all_st.size and all_st["iteration"][0] == 0:
+        t_first = float((int(all_st["t_end"][first_it]) - int(all_st["t_begin"][0])) / rate * 1e3)
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(w, snap_start, a.cpu_seconds)
+
+    planner.close()
+    out = {
+        "metric": "propagated edges/s", "value": round(value, 1), "unit": "edges/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(elapsed * 1e3 / max(done, 1), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {prob.dynamics} {prob.n_boxes} boxes, "
+                   f"{prm.n_select}x{prm.samples_per_node} expansions/iteration, "
+                   f"{prm.n_cells} regions, cap {prm.tree_cap}",
+                   "seed": a.seed, "iterations_timed": done, "edges_timed": edges,
+                   "substeps_timed": substeps, "cost": prob.cost},
+        "roofline": roofline,
+        "kernel_ms": kernel_ms,
+        "time_to_first_solution_ms": t_first,
+        "first_solution_iteration": first_it,
+        "solution_cost": sol["cost"] if sol["found"] else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(w, snap, seconds):
+    """The float64 oracle (single thread, as written) stepping the same tree."""
+    from oracle import oracle as O
+    from oracle import parity
+
+    P = O.Problem(w.problem, w.params)
+    tr = parity.oracle_tree_from_snapshot(O, P, snap)
+    edges = 0
+    iters = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        rc = tr.step()
+        if rc != O.OK:
+            break
+        edges += tr.cands.n_slots
+        iters += 1
+    el = time.perf_counter() - t0
+    return {"value": round(edges / el, 1) if el > 0 else None, "unit": "edges/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{iters} iterations of the same query from the GPU tree at the start of "
+                      f"the timed region ({edges} expansions, {el:.1f} s, float64, one thread)"}
+
+
+if __name__ == "__main__":
+    main()

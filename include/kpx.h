@@ -1,0 +1,288 @@
+/*
+ * kpx.h -- C ABI of the Kino-PAX+ planner hot path on AMD Instinct MI355X
+ * (gfx950): the per-iteration select -> propagate -> prune -> insert cycle of
+ * "Kino-PAX+: Near-Optimal Massively Parallel Kinodynamic Sampling-based
+ * Motion Planner" (arXiv 2602.02846), Alg. 1-4 and App. A.
+ *
+ * Conventions
+ *   - Plain C types only.  "host" pointers are CPU memory owned by the caller
+ *     and only read or written during the call; "device" pointers are GPU
+ *     memory.  No call keeps a pointer the caller passed in, except the
+ *     optional workspace given to kpx_create (used until kpx_destroy).
+ *   - Every call returns a status: 0 = KPX_OK, > 0 informational, < 0 error.
+ *     No exception or abort crosses this boundary.  kpx_last_error() gives a
+ *     message for the last failing call on a handle.
+ *   - A handle is not thread-safe; all its GPU work runs in order on one HIP
+ *     stream (the caller's, or the default stream when NULL is passed).
+ *   - Node status codes: 0 = active (V_A), 1 = inactive (V_I),
+ *     2 = terminal (V_T); V_U is the per-iteration survivor mask (Sec. IV).
+ */
+#ifndef KPX_H
+#define KPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KPX_MAX_STATE 12
+#define KPX_MAX_CONTROL 4
+#define KPX_MAX_BOXES 2048
+
+/* status codes */
+#define KPX_OK 0
+#define KPX_FULL 1               /* the tree cannot take another iteration (App. A, t_e) */
+#define KPX_ERR_ARG (-1)         /* invalid argument, size or NULL pointer */
+#define KPX_ERR_INVALID_START (-2) /* x_init is not in the (planning) valid set */
+#define KPX_ERR_OOM (-3)         /* device memory or workspace too small */
+#define KPX_ERR_DEVICE (-4)      /* a HIP runtime call failed */
+#define KPX_ERR_BUFFER (-5)      /* a caller buffer is too small */
+#define KPX_ERR_STATE (-6)       /* call not valid in the handle's current state */
+
+/* robot models (Sec. V): double integrator, nonlinear quadrotor, Dubins airplane */
+#define KPX_DI6 0
+#define KPX_QUAD12 1
+#define KPX_DUBINS6 2
+
+/* trajectory cost satisfying Assumption 1 */
+#define KPX_COST_TIME 0          /* duration; stored as the total integer RK4 step count */
+#define KPX_COST_PATH_LENGTH 1   /* length of the position path; stored as float32 bits */
+
+#define KPX_ACTIVE 0
+#define KPX_INACTIVE 1
+#define KPX_TERMINAL 2
+
+/*
+ * Problem 1 (Sec. III): dynamics x' = f(x, u) (Eq. 1), compact state and
+ * control sets, the valid set (workspace, state bounds, box obstacles),
+ * x_init in the valid set, a goal set inside it, and the cost.
+ *
+ *   state layouts    DI6     p(3) v(3)
+ *                    QUAD12  p(3) roll pitch yaw  v(3, world frame)  body rates(3)
+ *                    DUBINS6 x y z yaw pitch speed
+ *   control layouts  DI6 acceleration(3); QUAD12 thrust, torque(3);
+ *                    DUBINS6 yaw rate, pitch rate, acceleration
+ *   dyn_params       QUAD12: mass, Ixx, Iyy, Izz, gravity; unused otherwise
+ *   boxes            host, n_boxes x 6 floats (lo x y z, hi x y z); copied
+ *   margin           planning clearance: boxes grow and workspace, state
+ *                    bounds and goal radius shrink by it (0 allowed)
+ *   goal             closed ball over the position coordinates
+ * Unused trailing entries of the fixed-size arrays are ignored.  State bounds
+ * may be +-INFINITY.
+ */
+typedef struct kpx_problem {
+    int32_t dynamics;
+    int32_t cost;
+    float dyn_params[8];
+    float x_init[KPX_MAX_STATE];
+    float x_lo[KPX_MAX_STATE];
+    float x_hi[KPX_MAX_STATE];
+    float u_lo[KPX_MAX_CONTROL];
+    float u_hi[KPX_MAX_CONTROL];
+    float ws_lo[3];
+    float ws_hi[3];
+    const float* boxes;
+    int32_t n_boxes;
+    float margin;
+    float goal_center[3];
+    float goal_radius;
+} kpx_problem;
+
+/*
+ * Algorithm parameters (Alg. 1 inputs, App. A sizing).
+ *   dt, steps_min..steps_max  one expansion integrates n RK4 steps of size dt,
+ *                             n uniform in [steps_min, steps_max] (duration in (0, T_prop])
+ *   grid, vel_sign_bins       region decomposition R: grid[a] cells per
+ *                             position axis over the workspace, times 8
+ *                             velocity-sign classes when vel_sign_bins = 1
+ *                             (DI6 and QUAD12 only)
+ *   n_select                  at most this many active nodes are expanded per
+ *                             iteration, taken in region order from a rotating cursor
+ *   samples_per_node          K (the branching factor lambda)
+ *   tree_cap                  t_e: capacity of the tree
+ *   i_max                     inactivity threshold I_max (0..254)
+ *   seed, query_id            Philox4x32-10 key and counter field
+ */
+typedef struct kpx_params {
+    float dt;
+    int32_t steps_min;
+    int32_t steps_max;
+    int32_t grid[3];
+    int32_t vel_sign_bins;
+    int32_t n_select;
+    int32_t samples_per_node;
+    int32_t i_max;
+    int64_t tree_cap;
+    uint64_t seed;
+    uint32_t query_id;
+    uint32_t reserved;
+} kpx_params;
+
+typedef struct kpx_handle kpx_handle;
+
+/* Device counters after the last completed iteration. */
+typedef struct kpx_counters {
+    int64_t n_tree;                    /* nodes in T */
+    int64_t iteration;                 /* completed iterations */
+    int64_t cursor;                    /* region the next selection starts from */
+    int64_t n_select;                  /* nodes expanded in the last iteration */
+    int64_t n_valid;                   /* valid expansions in the last iteration */
+    int64_t n_survivors;               /* nodes added in the last iteration */
+    int64_t substeps;                  /* RK4 substeps integrated in the last iteration */
+    int64_t first_solution_iteration;  /* -1 until a goal node exists */
+    uint64_t solution_key;             /* (cost field << 32) | tree index; all ones = none */
+    int32_t full;                      /* 1 once the capacity pre-check failed */
+    int32_t reserved;
+} kpx_counters;
+
+typedef struct kpx_solution_info {
+    int32_t found;
+    int32_t n_edges;
+    int64_t tree_index;
+    uint32_t cost_field;               /* TIME: steps; PATH_LENGTH: float32 bits */
+    uint32_t reserved;
+    double cost;                       /* TIME: steps * dt seconds; PATH_LENGTH: length */
+    int64_t first_solution_iteration;
+    int64_t n_tree;
+    int64_t iteration;
+} kpx_solution_info;
+
+/* Host buffers for kpx_snapshot; any pointer may be NULL (not copied).
+ * Per-node arrays hold at least `capacity` entries; state and control are
+ * component-major: state[k * capacity + i] is component k of node i. */
+typedef struct kpx_tree_view {
+    int64_t capacity;
+    float* state;        /* KPX_MAX_STATE x capacity */
+    float* control;      /* KPX_MAX_CONTROL x capacity */
+    int32_t* steps;
+    int32_t* parent;     /* -1 for the root */
+    uint32_t* cost;      /* cost field */
+    int32_t* cell;
+    uint8_t* status;
+    uint8_t* icount;
+    uint64_t* cell_table;  /* n_cells keys: (cost field << 32) | owner; all ones = never reached */
+    int64_t cell_table_len;
+} kpx_tree_view;
+
+/* Host buffers for kpx_read_dump: the last iteration's expansions, one entry
+ * per slot s = r * K + j (r-th selected node, j-th sample).  Any pointer may be
+ * NULL.  state and control are component-major with leading dimension `capacity`. */
+typedef struct kpx_dump_view {
+    int64_t capacity;
+    int32_t* parent;
+    float* control;        /* KPX_MAX_CONTROL x capacity */
+    int32_t* steps;
+    float* state;          /* end state, KPX_MAX_STATE x capacity (valid slots) */
+    int32_t* first_invalid;/* 0 when valid, else the first invalid substep (1-based) */
+    int32_t* cell;         /* -1 when invalid */
+    uint64_t* key;         /* (cost field << 32) | (n_tree + s); all ones when invalid */
+    uint8_t* goal;
+    uint8_t* survivor;
+} kpx_dump_view;
+
+/* One record per completed iteration (ring of kpx_stats_capacity entries). */
+typedef struct kpx_iter_stats {
+    int64_t iteration;
+    int64_t n_tree;           /* after the iteration */
+    int32_t n_select;
+    int32_t n_valid;
+    int32_t n_survivors;
+    int32_t reserved;
+    int64_t substeps;
+    uint64_t solution_key;
+    uint64_t t_begin;         /* device wall clock ticks (kpx_clock_rate_khz) */
+    uint64_t t_end;
+} kpx_iter_stats;
+
+/* Bytes of device workspace kpx_create needs for this problem.  Pure host
+ * computation.  Returns KPX_ERR_ARG for invalid sizes. */
+int kpx_workspace_bytes(const kpx_problem* prob, const kpx_params* prm, size_t* out_bytes);
+
+/* Validates the problem and parameters (Problem 1; capacity >= 1 + the most
+ * survivors one iteration can add), copies them, allocates the tree, region
+ * table and per-iteration buffers on the device (or carves them from
+ * `workspace`, a device buffer of `workspace_bytes` >= kpx_workspace_bytes,
+ * which the caller keeps alive until kpx_destroy), and runs Alg. 1 lines 1-5:
+ * root = x_init (active), every region at infinite cost except the root's,
+ * which holds (0, root), no solution.  hip_stream: a hipStream_t or NULL.
+ * Errors: KPX_ERR_ARG, KPX_ERR_INVALID_START (checked on the host before any
+ * GPU call), KPX_ERR_OOM, KPX_ERR_DEVICE.  *out is NULL on error. */
+int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream, void* workspace,
+               size_t workspace_bytes, kpx_handle** out);
+
+/* Enqueues n_iters iterations of Alg. 1's loop body (Propagate, PruneNodes,
+ * UpdateTree, each preceded by the selection of the nodes to expand) on the
+ * handle's stream and returns without waiting.  Counts stay on the device.
+ * Once the capacity pre-check fails the iterations do nothing; the host
+ * learns this at the next kpx_sync / kpx_counters / kpx_solution, after
+ * which kpx_iterate returns KPX_FULL.  n_iters >= 0. */
+int kpx_iterate(kpx_handle* h, int32_t n_iters);
+
+/* Waits for the handle's stream; returns KPX_FULL if the tree is full, else KPX_OK. */
+int kpx_sync(kpx_handle* h);
+
+/* Waits and copies the device counters to *out (host). */
+int kpx_counters_read(kpx_handle* h, kpx_counters* out);
+
+/* Waits, then returns the best goal node's trajectory (Alg. 4 lines 5-7):
+ * states (n_edges + 1) x KPX_MAX_STATE row-major starting at x_init,
+ * controls n_edges x KPX_MAX_CONTROL, steps n_edges (host buffers, may be NULL).
+ * If capacity_edges < n_edges only *info is filled and KPX_ERR_BUFFER is returned. */
+int kpx_solution(kpx_handle* h, kpx_solution_info* info, float* states, float* controls,
+                 int32_t* steps, int32_t capacity_edges);
+
+/* Waits and copies the tree, region table and counters to host buffers.
+ * KPX_ERR_BUFFER when view->capacity < n_tree or cell_table_len < n_cells. */
+int kpx_snapshot(kpx_handle* h, kpx_tree_view* view, kpx_counters* counters);
+
+/* Records every expansion of the following iterations for kpx_read_dump
+ * (enable = 1) or stops recording (0).  Recording costs extra stores only. */
+int kpx_set_dump(kpx_handle* h, int32_t enable);
+
+/* Waits and copies the last recorded iteration's expansions; *n_slots gets the
+ * slot count (n_select * K).  KPX_ERR_STATE when recording is off;
+ * KPX_ERR_BUFFER when view->capacity < n_slots. */
+int kpx_read_dump(kpx_handle* h, kpx_dump_view* view, int64_t* n_slots);
+
+/* Brackets each of the four kernels of every following iteration with HIP
+ * events on the handle's stream (enable = 1), or stops (0).  Enabling also
+ * clears the accumulated times. */
+int kpx_set_timing(kpx_handle* h, int32_t enable);
+
+/* Waits and returns, per kernel (0 propagate, 1 prune + survivor flags,
+ * 2 insert, 3 finalize + select), the summed milliseconds and the number of
+ * launches timed since timing was enabled. */
+int kpx_read_timing(kpx_handle* h, double ms[4], int64_t launches[4]);
+
+/* Number of per-iteration records kept (a ring indexed by iteration). */
+int kpx_stats_capacity(const kpx_handle* h, int64_t* out);
+
+/* Waits and copies the records of iterations first .. first + count - 1
+ * (each must be among the last kpx_stats_capacity iterations) to out (host). */
+int kpx_read_stats(kpx_handle* h, int64_t first, int64_t count, kpx_iter_stats* out);
+
+/* Device wall-clock rate for kpx_iter_stats timestamps, in kHz. */
+int kpx_clock_rate_khz(kpx_handle* h, int64_t* out);
+
+/* Diagnostic: evaluates the device Philox4x32-10 block function (the one the
+ * expansions use) on n host (counter, key) records of 6 words
+ * (c0 c1 c2 c3 k0 k1) and writes 4 words per record to host out. Runs on the
+ * current device with its own short-lived buffers. */
+int kpx_philox(const uint32_t* counter_key, int64_t n, uint32_t* out);
+
+/* Releases what the library allocated (not a caller workspace).  NULL is ok. */
+int kpx_destroy(kpx_handle* h);
+
+/* Static message for a status code. */
+const char* kpx_status_string(int status);
+
+/* Message for the last failing call on h (empty string if none). */
+const char* kpx_last_error(const kpx_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KPX_H */

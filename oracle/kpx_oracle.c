@@ -67,6 +67,13 @@ void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* rows of (c0, c1, c2, c3, k0, k1) -> rows of 4 output words */
+void ora_philox_many(const uint32_t* counter_key, int64_t n, uint32_t* out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        ora_philox4x32_10(&counter_key[6 * i], &counter_key[6 * i + 4], &out[4 * i]);
+}
+
 /* Random control and duration of one expansion (Alg. 2 line 3; Alg. 6 line 4).
  * Reading: counter = (iteration, slot, query, block), key = (seed low, seed
  * high).  Block b yields words 4b..4b+3.  Control i takes word i; the step

@@ -149,6 +149,7 @@ int ora_state_dim(int32_t dynamics);
 int ora_control_dim(int32_t dynamics);
 
 void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void ora_philox_many(const uint32_t* counter_key, int64_t n, uint32_t* out);
 void ora_sample(const ora_problem* P, uint32_t iter, uint32_t slot, float u[ORA_MAX_CONTROL],
                 int32_t* n);
 

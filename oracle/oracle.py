@@ -108,6 +108,7 @@ def lib():
         build()
         L = C.CDLL(LIB)
         L.ora_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.ora_philox_many.argtypes = [_u32p, C.c_int64, _u32p]
         L.ora_sample.argtypes = [C.POINTER(ProblemC), C.c_uint32, C.c_uint32, _f32p, _i32p]
         L.ora_deriv.argtypes = [C.POINTER(ProblemC), _f64p, _f64p, _f64p]
         L.ora_rk4_step.argtypes = [C.POINTER(ProblemC), _f64p, _f64p, C.c_double]
@@ -184,6 +185,13 @@ def philox(ctr, key) -> np.ndarray:
     k = np.asarray(key, dtype=np.uint32)
     out = np.zeros(4, dtype=np.uint32)
     lib().ora_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p))
+    return out
+
+
+def philox_many(counter_key) -> np.ndarray:
+    ck = np.ascontiguousarray(counter_key, dtype=np.uint32).reshape(-1, 6)
+    out = np.zeros((ck.shape[0], 4), dtype=np.uint32)
+    lib().ora_philox_many(_ptr(ck, _u32p), ck.shape[0], _ptr(out, _u32p))
     return out
 
 

@@ -1,0 +1,10 @@
+"""Kino-PAX+ planner hot path on AMD Instinct MI355X.
+
+The planner runs in libkpx.so (HIP kernels for gfx950 behind the C ABI in
+include/kpx.h); this package only marshals arguments to it.
+"""
+
+from .kpx import (  # noqa: F401
+    ACTIVE, INACTIVE, TERMINAL, KPXError, Planner, lib, philox, workspace_bytes,
+    status_string, OK, FULL,
+)

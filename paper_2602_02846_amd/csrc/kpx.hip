@@ -1,0 +1,1281 @@
+// kpx.hip -- Kino-PAX+ hot path on AMD Instinct MI355X (gfx950): kernels and
+// the C ABI declared in include/kpx.h.
+//
+// One iteration (Alg. 1 loop body) is four kernels on one stream, with every
+// count kept in device memory so that nothing waits for the host:
+//   1. propagate   one lane per expansion slot: Philox sample, RK4 substeps
+//                  with the valid-set test after each, region map, additive
+//                  cost, packed (cost | id) 64-bit atomicMin on the region
+//                  table (Alg. 2, Alg. 6); the lane that takes a region from
+//                  a tree node marks that node terminal (Alg. 3 lines 10-12).
+//   2. prune+flags blocks [0, P): Alg. 3 for each region's owner (the live
+//                  nodes are exactly the region owners, so prune walks the
+//                  region table instead of the whole tree); blocks [P, P+Q):
+//                  survivor mask V_U = valid and still the region minimum
+//                  (the U-filter of App. A) with per-tile counts.
+//   3. insert      App. A UpdateTree: rank = exclusive scan of the mask, the
+//                  survivor is appended at |T| + rank, its region is re-keyed
+//                  to the new tree index, goal nodes atomicMin the solution.
+//   4. finalize+select  one workgroup: counters, statistics, capacity check,
+//                  then the next iteration's selection (active region owners
+//                  in region order from a rotating cursor, at most n_select).
+#include "../../include/kpx.h"
+#include "kpx_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace kpx;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 8;                 // survivor slots per thread
+constexpr int kTile = kBlock * kItems;    // survivor slots per tile
+constexpr int kSelectThreads = 1024;
+constexpr int kStatsCap = 1 << 16;
+constexpr int kMaxPath = 1 << 16;
+
+struct DevState {
+    long long n_tree;
+    long long it;
+    long long first_sol_it;
+    unsigned long long sol;
+    unsigned long long substeps_acc;
+    long long last_substeps;
+    int n_valid_acc;
+    int last_n_valid;
+    int n_sel;
+    int last_n_sel;
+    int last_n_surv;
+    int cursor;
+    int cursor_next;
+    int full;
+};
+
+struct DevPtrs {
+    float* x;            // D x cap
+    float* u;            // M x cap
+    uint16_t* steps;
+    int* parent;
+    uint32_t* cost;
+    int* cell;
+    uint8_t* status;
+    uint8_t* icount;
+    uint8_t* dead;       // terminal, or some ancestor was beaten (monotone)
+    unsigned long long* tbl;
+    int* sel;
+    unsigned long long* ckey;
+    int* ccell;
+    float* cx;           // D x s_max
+    uint8_t* cflag;      // bit 0 valid, bit 1 goal
+    uint8_t* csurv;
+    int* tile_count;
+    float* boxes;        // n_boxes x 6, grown by the margin
+    DevState* st;
+    kpx_iter_stats* stats;
+    int* d_parent;       // dump (may be null)
+    float* d_u;
+    int* d_n;
+    int* d_fi;
+    int* path;           // solution extraction
+    float* path_x;
+    float* path_u;
+    int* path_n;
+    int* path_len;
+    float* x_init;
+};
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Exclusive scan of one int per thread over the block; *total gets the sum.
+// `lds` holds blockDim/64 + 1 ints.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int* total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int t = lds[w];
+            lds[w] = acc;
+            acc += t;
+        }
+        lds[nw] = acc;
+    }
+    __syncthreads();
+    const int excl = x - v + lds[wid];
+    *total = lds[nw];
+    __syncthreads();
+    return excl;
+}
+
+__device__ __forceinline__ int block_sum(int v, int* lds)
+{
+    int total;
+    block_exclusive_scan(v, lds, &total);
+    return total;
+}
+
+// ------------------------------------------------------------------ init
+
+__global__ void k_fill_table(unsigned long long* tbl, int n)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
+        tbl[c] = kEmpty;
+}
+
+// Alg. 1 lines 1-5: the root is x_init, active; its region holds (0, root).
+template <int DYN>
+__global__ void k_init_root(DevProblem P, DevPtrs T, const float* x_init)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
+    float x[D];
+    for (int k = 0; k < D; ++k) {
+        x[k] = x_init[k];
+        T.x[(long long)k * P.cap] = x[k];
+    }
+    for (int k = 0; k < M; ++k) T.u[(long long)k * P.cap] = 0.f;
+    T.steps[0] = 0;
+    T.parent[0] = -1;
+    T.cost[0] = 0u;
+    const int c = cell_of(P, x);
+    T.cell[0] = c;
+    T.status[0] = kActive;
+    T.icount[0] = 0;
+    T.dead[0] = 0;
+    T.tbl[c] = 0ull;  // cost 0, id 0
+    DevState* st = T.st;
+    st->n_tree = 1;
+    st->it = 0;
+    st->first_sol_it = -1;
+    st->sol = kEmpty;
+    st->substeps_acc = 0;
+    st->last_substeps = 0;
+    st->n_valid_acc = 0;
+    st->last_n_valid = 0;
+    st->n_sel = 0;
+    st->last_n_sel = 0;
+    st->last_n_surv = 0;
+    st->cursor = 0;
+    st->cursor_next = 0;
+    st->full = 0;
+}
+
+// ------------------------------------------------------------------ propagate
+
+// Alg. 2 / Alg. 6: slot s = r * K + j expands the r-th selected node with the
+// j-th sample.  Integration stops at the first invalid substep.
+template <int DYN, int COST>
+__global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
+{
+    constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
+    extern __shared__ float sbox[];
+    for (int i = threadIdx.x; i < P.n_boxes * 6; i += blockDim.x) sbox[i] = T.boxes[i];
+    __syncthreads();
+    DevState* st = T.st;
+    if (st->full) return;
+    const int n_sel = st->n_sel;
+    const long long n_tree = st->n_tree;
+    const uint32_t it = (uint32_t)st->it;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int S = n_sel * P.K;
+    if (blockIdx.x == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
+    if ((int)(blockIdx.x * blockDim.x) >= S) return;  // whole block idle
+
+    int my_valid = 0, my_steps = 0;
+    if (s < S) {
+        const int parent = T.sel[s / P.K];
+        float u[M];
+        int n;
+        sample<DYN>(P, it, (uint32_t)s, u, n);
+        float x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = T.x[(long long)k * P.cap + parent];
+        float len = 0.f;
+        int fi = 0;
+        for (int k = 1; k <= n; ++k) {
+            rk4<DYN, COST>(P, x, u, len);
+            bool ok = in_bounds<DYN>(P, x);
+            for (int b = 0; b < P.n_boxes; ++b) ok &= !in_box(&sbox[6 * b], x[0], x[1], x[2]);
+            if (!ok) {
+                fi = k;
+                break;
+            }
+        }
+        my_steps = fi ? fi : n;
+        if (fi == 0) {
+            my_valid = 1;
+            const int c = cell_of(P, x);
+            uint32_t cf;
+            if constexpr (COST == kTIME) {
+                cf = T.cost[parent] + (uint32_t)n;
+            } else {
+                cf = __float_as_uint(__uint_as_float(T.cost[parent]) + len);
+            }
+            const unsigned long long key =
+                ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)(n_tree + s);
+            const unsigned long long old = atomicMin(&T.tbl[c], key);
+            if (key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
+                // this lane took the region from a tree node: it is beaten (V_T)
+                const uint32_t o = (uint32_t)old;
+                T.status[o] = kTerminal;
+                T.dead[o] = 1;
+            }
+            T.ckey[s] = key;
+            T.ccell[s] = c;
+#pragma unroll
+            for (int k = 0; k < D; ++k) T.cx[(long long)k * P.s_max + s] = x[k];
+            T.cflag[s] = (uint8_t)(1 | (in_goal(P, x) ? 2 : 0));
+        } else {
+            T.ckey[s] = kEmpty;
+            T.ccell[s] = -1;
+            T.cflag[s] = 0;
+        }
+        if (T.d_parent) {
+            T.d_parent[s] = parent;
+#pragma unroll
+            for (int k = 0; k < M; ++k) T.d_u[(long long)k * P.s_max + s] = u[k];
+            T.d_n[s] = n;
+            T.d_fi[s] = fi;
+        }
+    }
+    const int wv = wave_sum(my_valid);
+    const int ws = wave_sum(my_steps);
+    if ((threadIdx.x & 63) == 0) {
+        if (wv) atomicAdd(&st->n_valid_acc, wv);
+        if (ws) atomicAdd(&st->substeps_acc, (unsigned long long)ws);
+    }
+}
+
+// ------------------------------------------------------------------ prune + survivor flags
+
+__global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T, int n_prune_blocks)
+{
+    __shared__ int lds[kBlock / 64 + 1];
+    DevState* st = T.st;
+    if (st->full) return;
+    const long long n_tree = st->n_tree;
+    if ((int)blockIdx.x < n_prune_blocks) {
+        // Alg. 3 for the owner of region c (every live node owns its region)
+        const int c = blockIdx.x * blockDim.x + threadIdx.x;
+        if (c >= P.n_cells) return;
+        const unsigned long long key = T.tbl[c];
+        if (key == kEmpty) return;
+        const uint32_t o = (uint32_t)key;
+        if ((long long)o >= n_tree) return;  // an arrival of this iteration owns it
+        const uint8_t s0 = T.status[o];
+        if (s0 == kInactive) {  // lines 3-7
+            const int ic = T.icount[o] + 1;
+            T.icount[o] = (uint8_t)ic;
+            if (ic > P.i_max) T.status[o] = kActive;
+            return;
+        }
+        if (s0 != kActive) return;
+        if (T.icount[o] > P.i_max) return;  // lines 8-9
+        // lines 13-15: any ancestor beaten in its region (or below such a one)
+        for (int q = T.parent[o]; q >= 0; q = T.parent[q]) {
+            if (T.dead[q]) {
+                T.status[o] = kInactive;
+                T.dead[o] = 1;
+                return;
+            }
+        }
+        return;
+    }
+    // survivor mask and per-tile counts
+    const int tile = blockIdx.x - n_prune_blocks;
+    const int S = st->n_sel * P.K;
+    const int base = tile * kTile + threadIdx.x * kItems;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int s = base + k;
+        if (s < S) {
+            int f = 0;
+            if (T.cflag[s] & 1) f = T.ckey[s] == T.tbl[T.ccell[s]];
+            T.csurv[s] = (uint8_t)f;
+            cnt += f;
+        }
+    }
+    const int total = block_sum(cnt, lds);
+    if (threadIdx.x == 0) T.tile_count[tile] = total;
+}
+
+// ------------------------------------------------------------------ insert
+
+template <int DYN>
+__global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
+{
+    constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
+    __shared__ int lds[kBlock / 64 + 1];
+    DevState* st = T.st;
+    if (st->full) return;
+    const int S = st->n_sel * P.K;
+    const int tile = blockIdx.x;
+    if (tile * kTile >= S) return;
+    int pre = 0;
+    for (int j = threadIdx.x; j < tile; j += blockDim.x) pre += T.tile_count[j];
+    pre = block_sum(pre, lds);
+    const int base = tile * kTile + threadIdx.x * kItems;
+    int f[kItems];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int s = base + k;
+        f[k] = s < S ? T.csurv[s] : 0;
+        cnt += f[k];
+    }
+    int total;
+    int rank = pre + block_exclusive_scan(cnt, lds, &total);
+    const long long n_tree = st->n_tree;
+    const uint32_t it = (uint32_t)st->it;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (!f[k]) continue;
+        const int s = base + k;
+        const long long i = n_tree + rank++;
+        float u[M];
+        int n;
+        sample<DYN>(P, it, (uint32_t)s, u, n);
+#pragma unroll
+        for (int q = 0; q < D; ++q) T.x[(long long)q * P.cap + i] = T.cx[(long long)q * P.s_max + s];
+#pragma unroll
+        for (int q = 0; q < M; ++q) T.u[(long long)q * P.cap + i] = u[q];
+        const unsigned long long key = T.ckey[s];
+        const uint32_t cf = (uint32_t)(key >> 32);
+        const int c = T.ccell[s];
+        T.steps[i] = (uint16_t)n;
+        T.parent[i] = T.sel[s / P.K];
+        T.cost[i] = cf;
+        T.cell[i] = c;
+        T.status[i] = kActive;
+        T.icount[i] = 0;
+        T.dead[i] = 0;
+        const unsigned long long nk = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)i;
+        T.tbl[c] = nk;
+        if (T.cflag[s] & 2) atomicMin(&st->sol, nk);  // Alg. 4 lines 5-7
+    }
+}
+
+// ------------------------------------------------------------------ finalize + select
+
+__global__ __launch_bounds__(kSelectThreads) void k_finalize_select(DevProblem P, DevPtrs T,
+                                                                    int do_finalize)
+{
+    __shared__ int lds[kSelectThreads / 64 + 1];
+    __shared__ int s_full, s_cursor;
+    __shared__ long long s_n_tree;
+    DevState* st = T.st;
+    if (do_finalize) {
+        const int was_full = st->full;
+        if (!was_full) {
+            const int S = st->n_sel * P.K;
+            const int tiles = (S + kTile - 1) / kTile;
+            int v = 0;
+            for (int j = threadIdx.x; j < tiles; j += blockDim.x) v += T.tile_count[j];
+            const int n_surv = block_sum(v, lds);
+            if (threadIdx.x == 0) {
+                const long long it = st->it;
+                const long long n_tree = st->n_tree + n_surv;
+                kpx_iter_stats* r = &T.stats[it & (kStatsCap - 1)];
+                r->iteration = it;
+                r->n_tree = n_tree;
+                r->n_select = st->n_sel;
+                r->n_valid = st->n_valid_acc;
+                r->n_survivors = n_surv;
+                r->reserved = 0;
+                r->substeps = (long long)st->substeps_acc;
+                r->solution_key = st->sol;
+                r->t_end = wall_clock64();
+                st->last_n_sel = st->n_sel;
+                st->last_n_valid = st->n_valid_acc;
+                st->last_n_surv = n_surv;
+                st->last_substeps = (long long)st->substeps_acc;
+                st->n_valid_acc = 0;
+                st->substeps_acc = 0;
+                if (st->sol != kEmpty && st->first_sol_it < 0) st->first_sol_it = it;
+                st->it = it + 1;
+                st->n_tree = n_tree;
+                st->cursor = st->cursor_next;
+                st->full = (n_tree + P.surv_max > P.cap) ? 1 : 0;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        s_full = st->full;
+        s_cursor = st->cursor;
+        s_n_tree = st->n_tree;
+    }
+    __syncthreads();
+    if (s_full) {
+        if (threadIdx.x == 0) st->n_sel = 0;
+        return;
+    }
+    // selection: active region owners in region order starting at the cursor
+    const int nc = P.n_cells;
+    const int cur = s_cursor;
+    const long long n_tree = s_n_tree;
+    const int per = (nc + blockDim.x - 1) / blockDim.x;
+    const int j0 = threadIdx.x * per;
+    const int j1 = min(j0 + per, nc);
+    int cnt = 0;
+    for (int j = j0; j < j1; ++j) {
+        int c = cur + j;
+        if (c >= nc) c -= nc;
+        const unsigned long long key = T.tbl[c];
+        if (key != kEmpty && (long long)(uint32_t)key < n_tree && T.status[(uint32_t)key] == kActive) ++cnt;
+    }
+    int total;
+    int rank = block_exclusive_scan(cnt, lds, &total);
+    const int nsel = min(total, P.n_select);
+    for (int j = j0; j < j1 && rank < nsel; ++j) {
+        int c = cur + j;
+        if (c >= nc) c -= nc;
+        const unsigned long long key = T.tbl[c];
+        if (key != kEmpty && (long long)(uint32_t)key < n_tree && T.status[(uint32_t)key] == kActive) {
+            T.sel[rank] = (int)(uint32_t)key;
+            if (rank == nsel - 1) st->cursor_next = (c + 1 == nc) ? 0 : c + 1;
+            ++rank;
+        }
+    }
+    if (threadIdx.x == 0) {
+        st->n_sel = nsel;
+        if (nsel == 0) st->cursor_next = cur;
+    }
+}
+
+// ------------------------------------------------------------------ solution path
+
+template <int DYN>
+__global__ void k_extract_path(DevProblem P, DevPtrs T, int max_nodes)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
+    const unsigned long long sol = T.st->sol;
+    if (sol == kEmpty) {
+        *T.path_len = 0;
+        return;
+    }
+    int len = 0;
+    for (int q = (int)(uint32_t)sol; q >= 0; q = T.parent[q]) ++len;
+    if (len > max_nodes) {
+        *T.path_len = -len;
+        return;
+    }
+    int q = (int)(uint32_t)sol;
+    for (int j = len - 1; j >= 0; --j, q = T.parent[q]) T.path[j] = q;
+    for (int j = 0; j < len; ++j) {
+        const int i = T.path[j];
+        for (int k = 0; k < KPX_MAX_STATE; ++k)
+            T.path_x[j * KPX_MAX_STATE + k] = k < D ? T.x[(long long)k * P.cap + i] : 0.f;
+        for (int k = 0; k < KPX_MAX_CONTROL; ++k)
+            T.path_u[j * KPX_MAX_CONTROL + k] = k < M ? T.u[(long long)k * P.cap + i] : 0.f;
+        T.path_n[j] = T.steps[i];
+    }
+    *T.path_len = len;
+}
+
+__global__ void k_philox_eval(const uint32_t* in, long long n, uint32_t* out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[4] = {in[6 * i], in[6 * i + 1], in[6 * i + 2], in[6 * i + 3]};
+    philox10(c, in[6 * i + 4], in[6 * i + 5]);
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = c[k];
+}
+
+// ------------------------------------------------------------------ host side
+
+int dims_of(int dyn, int* d, int* m)
+{
+    switch (dyn) {
+    case KPX_DI6: *d = 6; *m = 3; return 0;
+    case KPX_QUAD12: *d = 12; *m = 4; return 0;
+    case KPX_DUBINS6: *d = 6; *m = 3; return 0;
+    default: return -1;
+    }
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Sizes {
+    int d, m;
+    long long cap;
+    int n_cells, s_max, n_tiles, n_boxes;
+};
+
+// all device arrays, in order; the same function sizes and carves them
+template <typename F>
+void for_each_array(const Sizes& z, F&& f)
+{
+    const size_t cap = (size_t)z.cap, S = (size_t)z.s_max;
+    f("x", sizeof(float) * z.d * cap);
+    f("u", sizeof(float) * z.m * cap);
+    f("steps", sizeof(uint16_t) * cap);
+    f("parent", sizeof(int) * cap);
+    f("cost", sizeof(uint32_t) * cap);
+    f("cell", sizeof(int) * cap);
+    f("status", cap);
+    f("icount", cap);
+    f("dead", cap);
+    f("tbl", sizeof(unsigned long long) * (size_t)z.n_cells);
+    f("sel", sizeof(int) * S);
+    f("ckey", sizeof(unsigned long long) * S);
+    f("ccell", sizeof(int) * S);
+    f("cx", sizeof(float) * z.d * S);
+    f("cflag", S);
+    f("csurv", S);
+    f("tile_count", sizeof(int) * (size_t)z.n_tiles);
+    f("boxes", sizeof(float) * 6 * (size_t)(z.n_boxes > 0 ? z.n_boxes : 1));
+    f("st", sizeof(DevState));
+    f("stats", sizeof(kpx_iter_stats) * kStatsCap);
+    f("d_parent", sizeof(int) * S);
+    f("d_u", sizeof(float) * z.m * S);
+    f("d_n", sizeof(int) * S);
+    f("d_fi", sizeof(int) * S);
+    f("path", sizeof(int) * kMaxPath);
+    f("path_x", sizeof(float) * KPX_MAX_STATE * kMaxPath);
+    f("path_u", sizeof(float) * KPX_MAX_CONTROL * kMaxPath);
+    f("path_n", sizeof(int) * kMaxPath);
+    f("path_len", sizeof(int));
+    f("x_init", sizeof(float) * KPX_MAX_STATE);
+}
+
+bool finite(float v) { return std::isfinite(v); }
+
+// Host-side validation of Problem 1 and the parameters; no GPU call.
+int validate(const kpx_problem* p, const kpx_params* q, Sizes* z, std::string* why)
+{
+    auto bad = [&](const char* msg) {
+        if (why) *why = msg;
+        return KPX_ERR_ARG;
+    };
+    if (!p || !q) return bad("NULL problem or params");
+    int d, m;
+    if (dims_of(p->dynamics, &d, &m)) return bad("unknown dynamics");
+    if (p->cost != KPX_COST_TIME && p->cost != KPX_COST_PATH_LENGTH) return bad("unknown cost");
+    if (p->n_boxes < 0 || p->n_boxes > KPX_MAX_BOXES) return bad("n_boxes out of range");
+    if (p->n_boxes > 0 && !p->boxes) return bad("boxes is NULL");
+    for (int b = 0; b < p->n_boxes; ++b)
+        for (int a = 0; a < 3; ++a) {
+            const float lo = p->boxes[6 * b + a], hi = p->boxes[6 * b + 3 + a];
+            if (!finite(lo) || !finite(hi) || lo > hi) return bad("box with lo > hi or non-finite");
+        }
+    for (int a = 0; a < 3; ++a)
+        if (!finite(p->ws_lo[a]) || !finite(p->ws_hi[a]) || !(p->ws_lo[a] < p->ws_hi[a]))
+            return bad("workspace bounds");
+    for (int i = 0; i < m; ++i)
+        if (!finite(p->u_lo[i]) || !finite(p->u_hi[i]) || p->u_lo[i] > p->u_hi[i])
+            return bad("control bounds");
+    for (int i = 0; i < d; ++i) {
+        if (std::isnan(p->x_lo[i]) || std::isnan(p->x_hi[i]) || p->x_lo[i] > p->x_hi[i])
+            return bad("state bounds");
+        if (!finite(p->x_init[i])) return bad("x_init not finite");
+    }
+    if (!finite(p->margin) || p->margin < 0.f) return bad("margin");
+    if (!finite(p->goal_radius) || !(p->goal_radius > p->margin)) return bad("goal radius must exceed margin");
+    for (int a = 0; a < 3; ++a)
+        if (!finite(p->goal_center[a])) return bad("goal center");
+    if (p->dynamics == KPX_QUAD12)
+        for (int k = 0; k < 5; ++k)
+            if (!finite(p->dyn_params[k]) || !(p->dyn_params[k] > 0.f)) return bad("quadrotor parameters");
+    if (!finite(q->dt) || !(q->dt > 0.f)) return bad("dt");
+    if (q->steps_min < 1 || q->steps_max < q->steps_min || q->steps_max > 65535) return bad("steps range");
+    long long nc = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (q->grid[a] < 1 || q->grid[a] > (1 << 20)) return bad("grid");
+        nc *= q->grid[a];
+    }
+    if (q->vel_sign_bins != 0 && q->vel_sign_bins != 1) return bad("vel_sign_bins");
+    if (q->vel_sign_bins && p->dynamics == KPX_DUBINS6) return bad("sign bins need a velocity state");
+    if (q->vel_sign_bins) nc *= 8;
+    if (nc > (1ll << 30)) return bad("too many regions");
+    if (q->n_select < 1 || q->samples_per_node < 1) return bad("n_select / samples_per_node");
+    const long long S = (long long)q->n_select * q->samples_per_node;
+    if (S > (1ll << 28)) return bad("n_select * samples_per_node too large");
+    if (q->i_max < 0 || q->i_max > 254) return bad("i_max out of 0..254");
+    const long long surv = std::min(nc, S);
+    if (q->tree_cap < 1 + surv) return bad("tree_cap < 1 + most survivors of one iteration");
+    if (q->tree_cap + S > (1ll << 31) - 1) return bad("tree_cap too large");
+    if (z) {
+        z->d = d;
+        z->m = m;
+        z->cap = q->tree_cap;
+        z->n_cells = (int)nc;
+        z->s_max = (int)S;
+        z->n_tiles = (int)((S + kTile - 1) / kTile);
+        z->n_boxes = p->n_boxes;
+    }
+    return KPX_OK;
+}
+
+DevProblem make_dev_problem(const kpx_problem* p, const kpx_params* q, const Sizes& z)
+{
+    DevProblem P;
+    std::memset(&P, 0, sizeof(P));
+    const float m = p->margin;
+    P.dyn = p->dynamics;
+    P.cost = p->cost;
+    P.d = z.d;
+    P.m = z.m;
+    P.dt = q->dt;
+    P.h2 = 0.5f * q->dt;
+    P.h6 = q->dt / 6.0f;
+    P.steps_min = q->steps_min;
+    P.steps_range = q->steps_max - q->steps_min + 1;
+    for (int i = 0; i < 4; ++i) {
+        P.u_lo[i] = i < z.m ? p->u_lo[i] : 0.f;
+        P.u_span[i] = i < z.m ? p->u_hi[i] - p->u_lo[i] : 0.f;
+    }
+    for (int i = 0; i < 12; ++i) {
+        P.x_lo[i] = i < z.d ? p->x_lo[i] + m : -INFINITY;
+        P.x_hi[i] = i < z.d ? p->x_hi[i] - m : INFINITY;
+    }
+    for (int a = 0; a < 3; ++a) {
+        P.ws_lo[a] = p->ws_lo[a] + m;
+        P.ws_hi[a] = p->ws_hi[a] - m;
+        P.cell_lo[a] = p->ws_lo[a];
+        P.cell_scale[a] = (float)q->grid[a] / (p->ws_hi[a] - p->ws_lo[a]);
+        P.grid[a] = q->grid[a];
+        P.goal_c[a] = p->goal_center[a];
+    }
+    P.vel_sign_bins = q->vel_sign_bins;
+    P.vel_idx = p->dynamics == KPX_QUAD12 ? 6 : 3;
+    const float r = p->goal_radius - m;
+    P.goal_r2 = r * r;
+    if (p->dynamics == KPX_QUAD12) {
+        const float mass = p->dyn_params[0], jx = p->dyn_params[1], jy = p->dyn_params[2],
+                    jz = p->dyn_params[3];
+        P.inv_mass = 1.0f / mass;
+        P.inv_j[0] = 1.0f / jx;
+        P.inv_j[1] = 1.0f / jy;
+        P.inv_j[2] = 1.0f / jz;
+        P.gyro[0] = jz - jy;
+        P.gyro[1] = jx - jz;
+        P.gyro[2] = jy - jx;
+        P.grav = p->dyn_params[4];
+    }
+    P.n_boxes = p->n_boxes;
+    P.n_cells = z.n_cells;
+    P.K = q->samples_per_node;
+    P.n_select = q->n_select;
+    P.s_max = z.s_max;
+    P.i_max = q->i_max;
+    P.surv_max = (int)std::min<long long>(z.n_cells, z.s_max);
+    P.cap = z.cap;
+    P.seed_lo = (uint32_t)(q->seed & 0xFFFFFFFFull);
+    P.seed_hi = (uint32_t)(q->seed >> 32);
+    P.query = q->query_id;
+    P.n_tiles = z.n_tiles;
+    return P;
+}
+
+// planning valid set on the host (float32, same tests as the device)
+bool start_is_valid(const kpx_problem* p, int d)
+{
+    const float m = p->margin;
+    const float* x = p->x_init;
+    for (int a = 0; a < 3; ++a)
+        if (!(x[a] >= p->ws_lo[a] + m && x[a] <= p->ws_hi[a] - m)) return false;
+    for (int i = 0; i < d; ++i)
+        if (!(x[i] >= p->x_lo[i] + m && x[i] <= p->x_hi[i] - m)) return false;
+    for (int b = 0; b < p->n_boxes; ++b) {
+        const float* bx = p->boxes + 6 * b;
+        bool in = true;
+        for (int a = 0; a < 3; ++a) in = in && x[a] >= bx[a] - m && x[a] <= bx[3 + a] + m;
+        if (in) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+struct kpx_handle {
+    kpx_problem prob;
+    kpx_params prm;
+    Sizes z;
+    DevProblem P;
+    DevPtrs T;
+    hipStream_t stream = nullptr;
+    void* base = nullptr;
+    size_t bytes = 0;
+    bool owns = false;
+    bool dump_on = false;
+    bool timing_on = false;
+    std::vector<hipEvent_t> events;  // 5 per timed iteration
+    std::vector<hipEvent_t> spare;
+    int full_cached = 0;
+    int n_prune_blocks = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(kpx_handle* h, int code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+#define KPX_HIP(h, expr)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((h), KPX_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void carve(kpx_handle* h)
+{
+    char* b = (char*)h->base;
+    size_t o = 0;
+    DevPtrs& T = h->T;
+    std::memset(&T, 0, sizeof(T));
+    void* ptrs[40];
+    int k = 0;
+    for_each_array(h->z, [&](const char*, size_t bytes) {
+        ptrs[k++] = b + o;
+        o = align_up(o + (bytes ? bytes : 1));
+    });
+    k = 0;
+    T.x = (float*)ptrs[k++];
+    T.u = (float*)ptrs[k++];
+    T.steps = (uint16_t*)ptrs[k++];
+    T.parent = (int*)ptrs[k++];
+    T.cost = (uint32_t*)ptrs[k++];
+    T.cell = (int*)ptrs[k++];
+    T.status = (uint8_t*)ptrs[k++];
+    T.icount = (uint8_t*)ptrs[k++];
+    T.dead = (uint8_t*)ptrs[k++];
+    T.tbl = (unsigned long long*)ptrs[k++];
+    T.sel = (int*)ptrs[k++];
+    T.ckey = (unsigned long long*)ptrs[k++];
+    T.ccell = (int*)ptrs[k++];
+    T.cx = (float*)ptrs[k++];
+    T.cflag = (uint8_t*)ptrs[k++];
+    T.csurv = (uint8_t*)ptrs[k++];
+    T.tile_count = (int*)ptrs[k++];
+    T.boxes = (float*)ptrs[k++];
+    T.st = (DevState*)ptrs[k++];
+    T.stats = (kpx_iter_stats*)ptrs[k++];
+    T.d_parent = (int*)ptrs[k++];
+    T.d_u = (float*)ptrs[k++];
+    T.d_n = (int*)ptrs[k++];
+    T.d_fi = (int*)ptrs[k++];
+    T.path = (int*)ptrs[k++];
+    T.path_x = (float*)ptrs[k++];
+    T.path_u = (float*)ptrs[k++];
+    T.path_n = (int*)ptrs[k++];
+    T.path_len = (int*)ptrs[k++];
+    T.x_init = (float*)ptrs[k++];
+}
+
+size_t total_bytes(const Sizes& z)
+{
+    size_t o = 0;
+    for_each_array(z, [&](const char*, size_t bytes) { o = align_up(o + (bytes ? bytes : 1)); });
+    return o;
+}
+
+DevPtrs kernel_ptrs(const kpx_handle* h)
+{
+    DevPtrs T = h->T;
+    if (!h->dump_on) {
+        T.d_parent = nullptr;
+        T.d_u = nullptr;
+        T.d_n = nullptr;
+        T.d_fi = nullptr;
+    }
+    return T;
+}
+
+template <int DYN, int COST>
+void launch_propagate(kpx_handle* h, const DevPtrs& T)
+{
+    const int grid = (h->z.s_max + kBlock - 1) / kBlock;
+    const size_t lds = sizeof(float) * 6 * (size_t)h->z.n_boxes;
+    k_propagate<DYN, COST><<<grid, kBlock, lds, h->stream>>>(h->P, T);
+}
+
+void propagate(kpx_handle* h, const DevPtrs& T)
+{
+    const int key = h->P.dyn * 2 + h->P.cost;
+    switch (key) {
+    case 0: launch_propagate<kDI6, kTIME>(h, T); break;
+    case 1: launch_propagate<kDI6, kPATH>(h, T); break;
+    case 2: launch_propagate<kQUAD12, kTIME>(h, T); break;
+    case 3: launch_propagate<kQUAD12, kPATH>(h, T); break;
+    case 4: launch_propagate<kDUBINS6, kTIME>(h, T); break;
+    default: launch_propagate<kDUBINS6, kPATH>(h, T); break;
+    }
+}
+
+void insert(kpx_handle* h, const DevPtrs& T)
+{
+    const int grid = h->z.n_tiles;
+    switch (h->P.dyn) {
+    case kDI6: k_insert<kDI6><<<grid, kBlock, 0, h->stream>>>(h->P, T); break;
+    case kQUAD12: k_insert<kQUAD12><<<grid, kBlock, 0, h->stream>>>(h->P, T); break;
+    default: k_insert<kDUBINS6><<<grid, kBlock, 0, h->stream>>>(h->P, T); break;
+    }
+}
+
+hipEvent_t take_event(kpx_handle* h)
+{
+    if (!h->spare.empty()) {
+        hipEvent_t e = h->spare.back();
+        h->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int record(kpx_handle* h)
+{
+    hipEvent_t e = take_event(h);
+    if (!e) return fail(h, KPX_ERR_DEVICE, "hipEventCreate failed");
+    KPX_HIP(h, hipEventRecord(e, h->stream));
+    h->events.push_back(e);
+    return KPX_OK;
+}
+
+int refresh_full(kpx_handle* h)
+{
+    int full = 0;
+    KPX_HIP(h, hipMemcpyAsync(&full, &h->T.st->full, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    h->full_cached = full;
+    return KPX_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+int kpx_workspace_bytes(const kpx_problem* prob, const kpx_params* prm, size_t* out_bytes)
+{
+    if (!out_bytes) return KPX_ERR_ARG;
+    Sizes z;
+    const int rc = validate(prob, prm, &z, nullptr);
+    if (rc != KPX_OK) return rc;
+    *out_bytes = total_bytes(z);
+    return KPX_OK;
+}
+
+int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream, void* workspace,
+               size_t workspace_bytes, kpx_handle** out)
+{
+    if (!out) return KPX_ERR_ARG;
+    *out = nullptr;
+    Sizes z;
+    std::string why;
+    int rc = validate(prob, prm, &z, &why);
+    if (rc != KPX_OK) return rc;
+    if (!start_is_valid(prob, z.d)) return KPX_ERR_INVALID_START;
+    const size_t need = total_bytes(z);
+    if (workspace && workspace_bytes < need) return KPX_ERR_OOM;
+
+    kpx_handle* h = new (std::nothrow) kpx_handle();
+    if (!h) return KPX_ERR_OOM;
+    h->prob = *prob;
+    h->prob.boxes = nullptr;
+    h->prm = *prm;
+    h->z = z;
+    h->P = make_dev_problem(prob, prm, z);
+    h->stream = (hipStream_t)hip_stream;
+    h->bytes = need;
+    if (workspace) {
+        h->base = workspace;
+    } else {
+        hipError_t e = hipMalloc(&h->base, need);
+        if (e != hipSuccess) {
+            delete h;
+            return e == hipErrorOutOfMemory ? KPX_ERR_OOM : KPX_ERR_DEVICE;
+        }
+        h->owns = true;
+    }
+    carve(h);
+    h->n_prune_blocks = (z.n_cells + kBlock - 1) / kBlock;
+
+    // boxes grown by the margin, x_init
+    std::vector<float> boxes((size_t)6 * (z.n_boxes > 0 ? z.n_boxes : 1), 0.f);
+    for (int b = 0; b < z.n_boxes; ++b)
+        for (int a = 0; a < 3; ++a) {
+            boxes[6 * b + a] = prob->boxes[6 * b + a] - prob->margin;
+            boxes[6 * b + 3 + a] = prob->boxes[6 * b + 3 + a] + prob->margin;
+        }
+    auto cleanup = [&](int code) {
+        kpx_destroy(h);
+        return code;
+    };
+    if (hipMemcpyAsync(h->T.boxes, boxes.data(), sizeof(float) * boxes.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess)
+        return cleanup(KPX_ERR_DEVICE);
+    float* xi = h->T.x_init;
+    if (hipMemcpyAsync(xi, prob->x_init, sizeof(float) * KPX_MAX_STATE, hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess)
+        return cleanup(KPX_ERR_DEVICE);
+    k_fill_table<<<std::min(1024, (z.n_cells + kBlock - 1) / kBlock), kBlock, 0, h->stream>>>(h->T.tbl,
+                                                                                              z.n_cells);
+    switch (h->P.dyn) {
+    case kDI6: k_init_root<kDI6><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
+    case kQUAD12: k_init_root<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
+    default: k_init_root<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
+    }
+    k_finalize_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, h->T, 0);
+    if (hipGetLastError() != hipSuccess) return cleanup(KPX_ERR_DEVICE);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(KPX_ERR_DEVICE);
+    *out = h;
+    return KPX_OK;
+}
+
+int kpx_iterate(kpx_handle* h, int32_t n_iters)
+{
+    if (!h || n_iters < 0) return KPX_ERR_ARG;
+    if (h->full_cached) return KPX_FULL;
+    const DevPtrs T = kernel_ptrs(h);
+    for (int i = 0; i < n_iters; ++i) {
+        int rc;
+        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
+        propagate(h, T);
+        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
+        k_prune_flags<<<h->n_prune_blocks + h->z.n_tiles, kBlock, 0, h->stream>>>(h->P, T,
+                                                                                 h->n_prune_blocks);
+        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
+        insert(h, T);
+        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
+        k_finalize_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, T, 1);
+        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
+    }
+    KPX_HIP(h, hipGetLastError());
+    return KPX_OK;
+}
+
+int kpx_sync(kpx_handle* h)
+{
+    if (!h) return KPX_ERR_ARG;
+    const int rc = refresh_full(h);
+    if (rc != KPX_OK) return rc;
+    return h->full_cached ? KPX_FULL : KPX_OK;
+}
+
+int kpx_counters_read(kpx_handle* h, kpx_counters* out)
+{
+    if (!h || !out) return KPX_ERR_ARG;
+    DevState s;
+    KPX_HIP(h, hipMemcpyAsync(&s, h->T.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    h->full_cached = s.full;
+    out->n_tree = s.n_tree;
+    out->iteration = s.it;
+    out->cursor = s.cursor;
+    out->n_select = s.last_n_sel;
+    out->n_valid = s.last_n_valid;
+    out->n_survivors = s.last_n_surv;
+    out->substeps = s.last_substeps;
+    out->first_solution_iteration = s.first_sol_it;
+    out->solution_key = s.sol;
+    out->full = s.full;
+    out->reserved = 0;
+    return KPX_OK;
+}
+
+int kpx_solution(kpx_handle* h, kpx_solution_info* info, float* states, float* controls,
+                 int32_t* steps, int32_t capacity_edges)
+{
+    if (!h || !info) return KPX_ERR_ARG;
+    kpx_counters c;
+    int rc = kpx_counters_read(h, &c);
+    if (rc != KPX_OK) return rc;
+    std::memset(info, 0, sizeof(*info));
+    info->first_solution_iteration = c.first_solution_iteration;
+    info->n_tree = c.n_tree;
+    info->iteration = c.iteration;
+    info->tree_index = -1;
+    if (c.solution_key == kEmpty) return KPX_OK;
+    switch (h->P.dyn) {
+    case kDI6: k_extract_path<kDI6><<<1, 64, 0, h->stream>>>(h->P, h->T, kMaxPath); break;
+    case kQUAD12: k_extract_path<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, h->T, kMaxPath); break;
+    default: k_extract_path<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, h->T, kMaxPath); break;
+    }
+    KPX_HIP(h, hipGetLastError());
+    int len = 0;
+    KPX_HIP(h, hipMemcpyAsync(&len, h->T.path_len, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    info->found = 1;
+    info->tree_index = (int64_t)(uint32_t)c.solution_key;
+    info->cost_field = (uint32_t)(c.solution_key >> 32);
+    if (h->prob.cost == KPX_COST_TIME) {
+        info->cost = (double)info->cost_field * (double)h->prm.dt;
+    } else {
+        float f;
+        std::memcpy(&f, &info->cost_field, sizeof(f));
+        info->cost = f;
+    }
+    if (len < 0) {
+        info->n_edges = -len - 1;
+        return fail(h, KPX_ERR_BUFFER, "solution path longer than the extraction buffer");
+    }
+    info->n_edges = len - 1;
+    if (!states && !controls && !steps) return KPX_OK;
+    if (capacity_edges < info->n_edges) return fail(h, KPX_ERR_BUFFER, "capacity_edges < n_edges");
+    std::vector<float> px((size_t)len * KPX_MAX_STATE), pu((size_t)len * KPX_MAX_CONTROL);
+    std::vector<int> pn((size_t)len);
+    KPX_HIP(h, hipMemcpyAsync(px.data(), h->T.path_x, sizeof(float) * px.size(), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipMemcpyAsync(pu.data(), h->T.path_u, sizeof(float) * pu.size(), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipMemcpyAsync(pn.data(), h->T.path_n, sizeof(int) * pn.size(), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    if (states) std::memcpy(states, px.data(), sizeof(float) * px.size());
+    for (int e = 0; e < info->n_edges; ++e) {
+        if (controls)
+            for (int k = 0; k < KPX_MAX_CONTROL; ++k)
+                controls[e * KPX_MAX_CONTROL + k] = pu[(size_t)(e + 1) * KPX_MAX_CONTROL + k];
+        if (steps) steps[e] = pn[e + 1];
+    }
+    return KPX_OK;
+}
+
+int kpx_snapshot(kpx_handle* h, kpx_tree_view* v, kpx_counters* counters)
+{
+    if (!h || !v) return KPX_ERR_ARG;
+    kpx_counters c;
+    int rc = kpx_counters_read(h, &c);
+    if (rc != KPX_OK) return rc;
+    if (counters) *counters = c;
+    const size_t n = (size_t)c.n_tree;
+    if (v->capacity < (int64_t)n) return fail(h, KPX_ERR_BUFFER, "view capacity < n_tree");
+    const size_t cap = (size_t)h->z.cap, ld = (size_t)v->capacity;
+    if (v->state)
+        for (int k = 0; k < KPX_MAX_STATE; ++k) {
+            if (k < h->z.d)
+                KPX_HIP(h, hipMemcpyAsync(v->state + k * ld, h->T.x + k * cap, sizeof(float) * n,
+                                          hipMemcpyDeviceToHost, h->stream));
+            else
+                std::memset(v->state + k * ld, 0, sizeof(float) * n);
+        }
+    if (v->control)
+        for (int k = 0; k < KPX_MAX_CONTROL; ++k) {
+            if (k < h->z.m)
+                KPX_HIP(h, hipMemcpyAsync(v->control + k * ld, h->T.u + k * cap, sizeof(float) * n,
+                                          hipMemcpyDeviceToHost, h->stream));
+            else
+                std::memset(v->control + k * ld, 0, sizeof(float) * n);
+        }
+    std::vector<uint16_t> st16;
+    if (v->steps) {
+        st16.resize(n ? n : 1);
+        KPX_HIP(h, hipMemcpyAsync(st16.data(), h->T.steps, sizeof(uint16_t) * n, hipMemcpyDeviceToHost, h->stream));
+    }
+    if (v->parent) KPX_HIP(h, hipMemcpyAsync(v->parent, h->T.parent, sizeof(int) * n, hipMemcpyDeviceToHost, h->stream));
+    if (v->cost) KPX_HIP(h, hipMemcpyAsync(v->cost, h->T.cost, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, h->stream));
+    if (v->cell) KPX_HIP(h, hipMemcpyAsync(v->cell, h->T.cell, sizeof(int) * n, hipMemcpyDeviceToHost, h->stream));
+    if (v->status) KPX_HIP(h, hipMemcpyAsync(v->status, h->T.status, n, hipMemcpyDeviceToHost, h->stream));
+    if (v->icount) KPX_HIP(h, hipMemcpyAsync(v->icount, h->T.icount, n, hipMemcpyDeviceToHost, h->stream));
+    if (v->cell_table) {
+        if (v->cell_table_len < h->z.n_cells) return fail(h, KPX_ERR_BUFFER, "cell_table_len < n_cells");
+        KPX_HIP(h, hipMemcpyAsync(v->cell_table, h->T.tbl, sizeof(unsigned long long) * h->z.n_cells,
+                                  hipMemcpyDeviceToHost, h->stream));
+    }
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    if (v->steps)
+        for (size_t i = 0; i < n; ++i) v->steps[i] = st16[i];
+    return KPX_OK;
+}
+
+int kpx_set_dump(kpx_handle* h, int32_t enable)
+{
+    if (!h || (enable != 0 && enable != 1)) return KPX_ERR_ARG;
+    h->dump_on = enable == 1;
+    return KPX_OK;
+}
+
+int kpx_read_dump(kpx_handle* h, kpx_dump_view* v, int64_t* n_slots)
+{
+    if (!h || !v || !n_slots) return KPX_ERR_ARG;
+    if (!h->dump_on) return fail(h, KPX_ERR_STATE, "dump recording is off");
+    kpx_counters c;
+    int rc = kpx_counters_read(h, &c);
+    if (rc != KPX_OK) return rc;
+    const size_t S = (size_t)c.n_select * (size_t)h->prm.samples_per_node;
+    *n_slots = (int64_t)S;
+    if (v->capacity < (int64_t)S) return fail(h, KPX_ERR_BUFFER, "dump capacity < slots");
+    if (S == 0) return KPX_OK;
+    const size_t sm = (size_t)h->z.s_max, ld = (size_t)v->capacity;
+    auto get = [&](void* dst, const void* src, size_t bytes) -> int {
+        KPX_HIP(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+        return KPX_OK;
+    };
+    if (v->parent && (rc = get(v->parent, h->T.d_parent, sizeof(int) * S))) return rc;
+    if (v->steps && (rc = get(v->steps, h->T.d_n, sizeof(int) * S))) return rc;
+    if (v->first_invalid && (rc = get(v->first_invalid, h->T.d_fi, sizeof(int) * S))) return rc;
+    if (v->cell && (rc = get(v->cell, h->T.ccell, sizeof(int) * S))) return rc;
+    if (v->key && (rc = get(v->key, h->T.ckey, sizeof(unsigned long long) * S))) return rc;
+    if (v->survivor && (rc = get(v->survivor, h->T.csurv, S))) return rc;
+    if (v->control)
+        for (int k = 0; k < KPX_MAX_CONTROL; ++k) {
+            if (k < h->z.m) {
+                if ((rc = get(v->control + k * ld, h->T.d_u + k * sm, sizeof(float) * S))) return rc;
+            } else {
+                std::memset(v->control + k * ld, 0, sizeof(float) * S);
+            }
+        }
+    if (v->state)
+        for (int k = 0; k < KPX_MAX_STATE; ++k) {
+            if (k < h->z.d) {
+                if ((rc = get(v->state + k * ld, h->T.cx + k * sm, sizeof(float) * S))) return rc;
+            } else {
+                std::memset(v->state + k * ld, 0, sizeof(float) * S);
+            }
+        }
+    std::vector<uint8_t> flag(S);
+    if ((rc = get(flag.data(), h->T.cflag, S))) return rc;
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    if (v->goal)
+        for (size_t s = 0; s < S; ++s) v->goal[s] = (flag[s] >> 1) & 1;
+    return KPX_OK;
+}
+
+int kpx_set_timing(kpx_handle* h, int32_t enable)
+{
+    if (!h || (enable != 0 && enable != 1)) return KPX_ERR_ARG;
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    for (hipEvent_t e : h->events) h->spare.push_back(e);
+    h->events.clear();
+    h->timing_on = enable == 1;
+    return KPX_OK;
+}
+
+int kpx_read_timing(kpx_handle* h, double ms[4], int64_t launches[4])
+{
+    if (!h || !ms || !launches) return KPX_ERR_ARG;
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    const size_t n = h->events.size() / 5;
+    for (size_t i = 0; i < n; ++i)
+        for (int k = 0; k < 4; ++k) {
+            float t = 0.f;
+            KPX_HIP(h, hipEventElapsedTime(&t, h->events[5 * i + k], h->events[5 * i + k + 1]));
+            ms[k] += t;
+            launches[k] += 1;
+        }
+    return KPX_OK;
+}
+
+int kpx_stats_capacity(const kpx_handle* h, int64_t* out)
+{
+    if (!h || !out) return KPX_ERR_ARG;
+    *out = kStatsCap;
+    return KPX_OK;
+}
+
+int kpx_read_stats(kpx_handle* h, int64_t first, int64_t count, kpx_iter_stats* out)
+{
+    if (!h || !out || first < 0 || count < 0 || count > kStatsCap) return KPX_ERR_ARG;
+    kpx_counters c;
+    int rc = kpx_counters_read(h, &c);
+    if (rc != KPX_OK) return rc;
+    if (first + count > c.iteration || first < c.iteration - kStatsCap)
+        return fail(h, KPX_ERR_ARG, "iterations not in the statistics ring");
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t it = first + i;
+        KPX_HIP(h, hipMemcpyAsync(out + i, h->T.stats + (it & (kStatsCap - 1)), sizeof(kpx_iter_stats),
+                                  hipMemcpyDeviceToHost, h->stream));
+    }
+    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    return KPX_OK;
+}
+
+int kpx_clock_rate_khz(kpx_handle* h, int64_t* out)
+{
+    if (!h || !out) return KPX_ERR_ARG;
+    int dev = 0, rate = 0;
+    KPX_HIP(h, hipGetDevice(&dev));
+    KPX_HIP(h, hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev));
+    *out = rate;
+    return KPX_OK;
+}
+
+int kpx_philox(const uint32_t* counter_key, int64_t n, uint32_t* out)
+{
+    if (n < 0 || (n > 0 && (!counter_key || !out))) return KPX_ERR_ARG;
+    if (n == 0) return KPX_OK;
+    uint32_t *din = nullptr, *dout = nullptr;
+    int rc = KPX_OK;
+    if (hipMalloc(&din, sizeof(uint32_t) * 6 * n) != hipSuccess) return KPX_ERR_OOM;
+    if (hipMalloc(&dout, sizeof(uint32_t) * 4 * n) != hipSuccess) {
+        (void)hipFree(din);
+        return KPX_ERR_OOM;
+    }
+    if (hipMemcpy(din, counter_key, sizeof(uint32_t) * 6 * n, hipMemcpyHostToDevice) != hipSuccess) rc = KPX_ERR_DEVICE;
+    if (rc == KPX_OK) {
+        k_philox_eval<<<(unsigned)((n + 255) / 256), 256>>>(din, n, dout);
+        if (hipGetLastError() != hipSuccess) rc = KPX_ERR_DEVICE;
+    }
+    if (rc == KPX_OK && hipMemcpy(out, dout, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = KPX_ERR_DEVICE;
+    (void)hipFree(din);
+    (void)hipFree(dout);
+    return rc;
+}
+
+int kpx_destroy(kpx_handle* h)
+{
+    if (!h) return KPX_OK;
+    if (h->stream || h->base) (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->spare) (void)hipEventDestroy(e);
+    if (h->owns && h->base) (void)hipFree(h->base);
+    delete h;
+    return KPX_OK;
+}
+
+const char* kpx_status_string(int status)
+{
+    switch (status) {
+    case KPX_OK: return "ok";
+    case KPX_FULL: return "tree full (capacity pre-check failed)";
+    case KPX_ERR_ARG: return "invalid argument";
+    case KPX_ERR_INVALID_START: return "x_init is not in the valid set";
+    case KPX_ERR_OOM: return "out of device memory or workspace too small";
+    case KPX_ERR_DEVICE: return "HIP runtime error";
+    case KPX_ERR_BUFFER: return "caller buffer too small";
+    case KPX_ERR_STATE: return "call not valid in the current state";
+    default: return "unknown status";
+    }
+}
+
+const char* kpx_last_error(const kpx_handle* h)
+{
+    return h ? h->err.c_str() : "";
+}
+
+}  // extern "C"

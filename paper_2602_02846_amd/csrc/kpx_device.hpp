@@ -1,0 +1,232 @@
+// kpx_device.hpp -- float32 device math of one Kino-PAX+ expansion on gfx950:
+// the Philox4x32-10 sample map, the three robot models, the RK4 step, the
+// valid-set test and the region map.  Header-only; included by kpx.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kpx {
+
+constexpr int kDI6 = 0;
+constexpr int kQUAD12 = 1;
+constexpr int kDUBINS6 = 2;
+constexpr int kTIME = 0;
+constexpr int kPATH = 1;
+
+constexpr uint8_t kActive = 0;
+constexpr uint8_t kInactive = 1;
+constexpr uint8_t kTerminal = 2;
+
+constexpr uint64_t kEmpty = ~0ull;
+
+template <int DYN>
+struct Dims;
+template <>
+struct Dims<kDI6> {
+    static constexpr int D = 6, M = 3;
+};
+template <>
+struct Dims<kQUAD12> {
+    static constexpr int D = 12, M = 4;
+};
+template <>
+struct Dims<kDUBINS6> {
+    static constexpr int D = 6, M = 3;
+};
+
+// Problem constants in the form the kernels use them (prepared on the host in
+// float32): planning bounds already shrunk by the clearance margin, boxes grown
+// by it, region scales and reciprocal inertias precomputed.
+struct DevProblem {
+    int dyn, cost, d, m;
+    float dt, h2, h6;
+    int steps_min, steps_range;
+    float u_lo[4], u_span[4];
+    float x_lo[12], x_hi[12];      // planning state bounds (+-inf when unbounded)
+    float ws_lo[3], ws_hi[3];      // planning workspace
+    float cell_lo[3], cell_scale[3];
+    int grid[3];
+    int vel_sign_bins, vel_idx;
+    float goal_c[3], goal_r2;      // (goal radius - margin)^2
+    float inv_mass, inv_j[3], gyro[3], grav;
+    int n_boxes;
+    int n_cells;
+    int K, n_select, s_max;
+    int i_max;
+    int surv_max;
+    long long cap;
+    uint32_t seed_lo, seed_hi, query;
+    int n_tiles;                   // survivor-count tiles covering s_max slots
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// with the published multipliers, the key advancing by the published Weyl
+// increments between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = c[0], b = c[2];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Control and step count of expansion `slot` in iteration `it`: counter
+// (it, slot, query, block), word i -> control i, word m -> step count.
+template <int DYN>
+__device__ __forceinline__ void sample(const DevProblem& P, uint32_t it, uint32_t slot,
+                                       float* u, int& n)
+{
+    constexpr int M = Dims<DYN>::M;
+    uint32_t w[8];
+    uint32_t c0[4] = {it, slot, P.query, 0u};
+    philox10(c0, P.seed_lo, P.seed_hi);
+    w[0] = c0[0]; w[1] = c0[1]; w[2] = c0[2]; w[3] = c0[3];
+    if (M >= 4) {
+        uint32_t c1[4] = {it, slot, P.query, 1u};
+        philox10(c1, P.seed_lo, P.seed_hi);
+        w[4] = c1[0]; w[5] = c1[1]; w[6] = c1[2]; w[7] = c1[3];
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const float unit = (float)(w[i] >> 8) * 0x1p-24f;
+        u[i] = __builtin_fmaf(unit, P.u_span[i], P.u_lo[i]);
+    }
+    n = P.steps_min + (int)__umulhi(w[M], (uint32_t)P.steps_range);
+}
+
+// ---------------------------------------------------------------------------
+// Dynamics f(x, u) and, for the path-length cost, the speed |p'|.
+// ---------------------------------------------------------------------------
+template <int DYN, int COST>
+__device__ __forceinline__ void deriv(const DevProblem& P, const float* x, const float* u,
+                                      float* xd, float& ld)
+{
+    if constexpr (DYN == kDI6) {
+        xd[0] = x[3]; xd[1] = x[4]; xd[2] = x[5];
+        xd[3] = u[0]; xd[4] = u[1]; xd[5] = u[2];
+        if constexpr (COST == kPATH) ld = __builtin_sqrtf(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
+    } else if constexpr (DYN == kQUAD12) {
+        const float sph = __sinf(x[3]), cph = __cosf(x[3]);
+        const float sth = __sinf(x[4]), cth = __cosf(x[4]);
+        const float sps = __sinf(x[5]), cps = __cosf(x[5]);
+        const float rc = __builtin_amdgcn_rcpf(cth);
+        const float wp = x[9], wq = x[10], wr = x[11];
+        const float a = sph * wq + cph * wr;
+        xd[0] = x[6]; xd[1] = x[7]; xd[2] = x[8];
+        xd[3] = __builtin_fmaf(a * sth, rc, wp);
+        xd[4] = cph * wq - sph * wr;
+        xd[5] = a * rc;
+        const float acc = u[0] * P.inv_mass;
+        const float sc = sth * cph;
+        xd[6] = acc * __builtin_fmaf(cps, sc, sps * sph);
+        xd[7] = acc * __builtin_fmaf(sps, sc, -(cps * sph));
+        xd[8] = __builtin_fmaf(acc, cth * cph, -P.grav);
+        xd[9] = (u[1] - P.gyro[0] * wq * wr) * P.inv_j[0];
+        xd[10] = (u[2] - P.gyro[1] * wp * wr) * P.inv_j[1];
+        xd[11] = (u[3] - P.gyro[2] * wp * wq) * P.inv_j[2];
+        if constexpr (COST == kPATH) ld = __builtin_sqrtf(x[6] * x[6] + x[7] * x[7] + x[8] * x[8]);
+    } else {
+        const float cg = __cosf(x[4]), sg = __sinf(x[4]);
+        const float v = x[5];
+        const float vc = v * cg;
+        xd[0] = vc * __cosf(x[3]);
+        xd[1] = vc * __sinf(x[3]);
+        xd[2] = v * sg;
+        xd[3] = u[0]; xd[4] = u[1]; xd[5] = u[2];
+        if constexpr (COST == kPATH) ld = v;
+    }
+}
+
+// Classical RK4 step of size dt on the state (and the path length).
+template <int DYN, int COST>
+__device__ __forceinline__ void rk4(const DevProblem& P, float* x, const float* u, float& len)
+{
+    constexpr int D = Dims<DYN>::D;
+    float k[D], acc[D], t[D];
+    float lk = 0.f, lacc = 0.f;
+    deriv<DYN, COST>(P, x, u, k, lk);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        acc[i] = k[i];
+        t[i] = __builtin_fmaf(P.h2, k[i], x[i]);
+    }
+    lacc = lk;
+    deriv<DYN, COST>(P, t, u, k, lk);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        acc[i] = __builtin_fmaf(2.f, k[i], acc[i]);
+        t[i] = __builtin_fmaf(P.h2, k[i], x[i]);
+    }
+    lacc = __builtin_fmaf(2.f, lk, lacc);
+    deriv<DYN, COST>(P, t, u, k, lk);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        acc[i] = __builtin_fmaf(2.f, k[i], acc[i]);
+        t[i] = __builtin_fmaf(P.dt, k[i], x[i]);
+    }
+    lacc = __builtin_fmaf(2.f, lk, lacc);
+    deriv<DYN, COST>(P, t, u, k, lk);
+#pragma unroll
+    for (int i = 0; i < D; ++i) x[i] = __builtin_fmaf(P.h6, acc[i] + k[i], x[i]);
+    if constexpr (COST == kPATH) len = __builtin_fmaf(P.h6, lacc + lk, len);
+}
+
+// Workspace and state bounds (closed; bounds may be infinite).
+template <int DYN>
+__device__ __forceinline__ bool in_bounds(const DevProblem& P, const float* x)
+{
+    constexpr int D = Dims<DYN>::D;
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok &= (x[a] >= P.ws_lo[a]) & (x[a] <= P.ws_hi[a]);
+#pragma unroll
+    for (int i = 0; i < D; ++i) ok &= (x[i] >= P.x_lo[i]) & (x[i] <= P.x_hi[i]);
+    return ok;
+}
+
+// Point inside a closed box (grown by the margin): a collision.
+__device__ __forceinline__ bool in_box(const float* b, float px, float py, float pz)
+{
+    return (px >= b[0]) & (px <= b[3]) & (py >= b[1]) & (py <= b[4]) & (pz >= b[2]) & (pz <= b[5]);
+}
+
+// Region index: grid over the workspace (clamped), row-major (x, y, z), then
+// optionally three velocity-sign bits (velocity >= 0).
+__device__ __forceinline__ int cell_of(const DevProblem& P, const float* x)
+{
+    int idx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int i = (int)__builtin_floorf((x[a] - P.cell_lo[a]) * P.cell_scale[a]);
+        i = i < 0 ? 0 : i;
+        i = i > P.grid[a] - 1 ? P.grid[a] - 1 : i;
+        idx[a] = i;
+    }
+    int c = (idx[0] * P.grid[1] + idx[1]) * P.grid[2] + idx[2];
+    if (P.vel_sign_bins) {
+        const int v = P.vel_idx;
+        c = c * 8 + ((x[v] >= 0.f) << 2) + ((x[v + 1] >= 0.f) << 1) + (x[v + 2] >= 0.f);
+    }
+    return c;
+}
+
+__device__ __forceinline__ bool in_goal(const DevProblem& P, const float* x)
+{
+    const float dx = x[0] - P.goal_c[0], dy = x[1] - P.goal_c[1], dz = x[2] - P.goal_c[2];
+    return __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)) <= P.goal_r2;
+}
+
+}  // namespace kpx

@@ -1,0 +1,376 @@
+"""ctypes binding of libkpx.so (include/kpx.h): argument marshalling only.
+
+Every step of the planner runs in the library's HIP kernels.  PyTorch supplies
+the device workspace and the stream; nothing here computes the method.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkpx.so")
+
+MAX_STATE = 12
+MAX_CONTROL = 4
+OK, FULL = 0, 1
+ERR_ARG, ERR_INVALID_START, ERR_OOM, ERR_DEVICE, ERR_BUFFER, ERR_STATE = -1, -2, -3, -4, -5, -6
+ACTIVE, INACTIVE, TERMINAL = 0, 1, 2
+DYNAMICS = {"DI6": 0, "QUAD12": 1, "DUBINS6": 2}
+COSTS = {"TIME": 0, "PATH_LENGTH": 1}
+EMPTY_KEY = (1 << 64) - 1
+
+_vp = C.c_void_p
+
+
+class KPXError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"kpx error {code}: {status_string(code)}" + (f" ({msg})" if msg else ""))
+        self.code = code
+
+
+class ProblemC(C.Structure):
+    _fields_ = [
+        ("dynamics", C.c_int32), ("cost", C.c_int32), ("dyn_params", C.c_float * 8),
+        ("x_init", C.c_float * MAX_STATE), ("x_lo", C.c_float * MAX_STATE),
+        ("x_hi", C.c_float * MAX_STATE), ("u_lo", C.c_float * MAX_CONTROL),
+        ("u_hi", C.c_float * MAX_CONTROL), ("ws_lo", C.c_float * 3), ("ws_hi", C.c_float * 3),
+        ("boxes", C.POINTER(C.c_float)), ("n_boxes", C.c_int32), ("margin", C.c_float),
+        ("goal_center", C.c_float * 3), ("goal_radius", C.c_float),
+    ]
+
+
+class ParamsC(C.Structure):
+    _fields_ = [
+        ("dt", C.c_float), ("steps_min", C.c_int32), ("steps_max", C.c_int32),
+        ("grid", C.c_int32 * 3), ("vel_sign_bins", C.c_int32), ("n_select", C.c_int32),
+        ("samples_per_node", C.c_int32), ("i_max", C.c_int32), ("tree_cap", C.c_int64),
+        ("seed", C.c_uint64), ("query_id", C.c_uint32), ("reserved", C.c_uint32),
+    ]
+
+
+class CountersC(C.Structure):
+    _fields_ = [
+        ("n_tree", C.c_int64), ("iteration", C.c_int64), ("cursor", C.c_int64),
+        ("n_select", C.c_int64), ("n_valid", C.c_int64), ("n_survivors", C.c_int64),
+        ("substeps", C.c_int64), ("first_solution_iteration", C.c_int64),
+        ("solution_key", C.c_uint64), ("full", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class SolutionInfoC(C.Structure):
+    _fields_ = [
+        ("found", C.c_int32), ("n_edges", C.c_int32), ("tree_index", C.c_int64),
+        ("cost_field", C.c_uint32), ("reserved", C.c_uint32), ("cost", C.c_double),
+        ("first_solution_iteration", C.c_int64), ("n_tree", C.c_int64), ("iteration", C.c_int64),
+    ]
+
+
+class TreeViewC(C.Structure):
+    _fields_ = [
+        ("capacity", C.c_int64), ("state", _vp), ("control", _vp), ("steps", _vp),
+        ("parent", _vp), ("cost", _vp), ("cell", _vp), ("status", _vp), ("icount", _vp),
+        ("cell_table", _vp), ("cell_table_len", C.c_int64),
+    ]
+
+
+class DumpViewC(C.Structure):
+    _fields_ = [
+        ("capacity", C.c_int64), ("parent", _vp), ("control", _vp), ("steps", _vp),
+        ("state", _vp), ("first_invalid", _vp), ("cell", _vp), ("key", _vp), ("goal", _vp),
+        ("survivor", _vp),
+    ]
+
+
+class IterStatsC(C.Structure):
+    _fields_ = [
+        ("iteration", C.c_int64), ("n_tree", C.c_int64), ("n_select", C.c_int32),
+        ("n_valid", C.c_int32), ("n_survivors", C.c_int32), ("reserved", C.c_int32),
+        ("substeps", C.c_int64), ("solution_key", C.c_uint64), ("t_begin", C.c_uint64),
+        ("t_end", C.c_uint64),
+    ]
+
+
+STATS_DTYPE = np.dtype([
+    ("iteration", np.int64), ("n_tree", np.int64), ("n_select", np.int32),
+    ("n_valid", np.int32), ("n_survivors", np.int32), ("reserved", np.int32),
+    ("substeps", np.int64), ("solution_key", np.uint64), ("t_begin", np.uint64),
+    ("t_end", np.uint64)])
+
+_lib = None
+
+
+def lib():
+    """Load libkpx.so; fails loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise KPXError(ERR_STATE, f"{LIB_PATH} is missing; build it with "
+                                      "paper_2602_02846_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        i32, i64, sz = C.c_int32, C.c_int64, C.c_size_t
+        L.kpx_workspace_bytes.argtypes = [C.POINTER(ProblemC), C.POINTER(ParamsC), C.POINTER(sz)]
+        L.kpx_create.argtypes = [C.POINTER(ProblemC), C.POINTER(ParamsC), _vp, _vp, sz,
+                                 C.POINTER(_vp)]
+        L.kpx_iterate.argtypes = [_vp, i32]
+        L.kpx_sync.argtypes = [_vp]
+        L.kpx_counters_read.argtypes = [_vp, C.POINTER(CountersC)]
+        L.kpx_solution.argtypes = [_vp, C.POINTER(SolutionInfoC), _vp, _vp, _vp, i32]
+        L.kpx_snapshot.argtypes = [_vp, C.POINTER(TreeViewC), C.POINTER(CountersC)]
+        L.kpx_set_dump.argtypes = [_vp, i32]
+        L.kpx_read_dump.argtypes = [_vp, C.POINTER(DumpViewC), C.POINTER(i64)]
+        L.kpx_set_timing.argtypes = [_vp, i32]
+        L.kpx_read_timing.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(i64)]
+        L.kpx_stats_capacity.argtypes = [_vp, C.POINTER(i64)]
+        L.kpx_read_stats.argtypes = [_vp, i64, i64, C.POINTER(IterStatsC)]
+        L.kpx_clock_rate_khz.argtypes = [_vp, C.POINTER(i64)]
+        L.kpx_philox.argtypes = [_vp, i64, _vp]
+        L.kpx_destroy.argtypes = [_vp]
+        L.kpx_status_string.argtypes = [C.c_int]
+        L.kpx_status_string.restype = C.c_char_p
+        L.kpx_last_error.argtypes = [_vp]
+        L.kpx_last_error.restype = C.c_char_p
+        for name in ("kpx_workspace_bytes", "kpx_create", "kpx_iterate", "kpx_sync",
+                     "kpx_counters_read", "kpx_solution", "kpx_snapshot", "kpx_set_dump",
+                     "kpx_read_dump", "kpx_set_timing", "kpx_read_timing", "kpx_stats_capacity",
+                     "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().kpx_status_string(code).decode()
+
+
+def _f(arr, n):
+    a = np.zeros(n, dtype=np.float32)
+    v = np.asarray(arr, dtype=np.float32).ravel()[:n]
+    a[: v.size] = v
+    return (C.c_float * n)(*a.tolist())
+
+
+def problem_struct(problem):
+    """kpx_problem from a workloads.Problem; returns (struct, kept-alive boxes)."""
+    boxes = np.ascontiguousarray(problem.boxes, dtype=np.float32).reshape(-1, 6)
+    s = ProblemC()
+    s.dynamics = DYNAMICS[problem.dynamics]
+    s.cost = COSTS[problem.cost]
+    s.dyn_params = _f(problem.dyn_params, 8)
+    s.x_init = _f(problem.x_init, MAX_STATE)
+    s.x_lo = _f(problem.x_lo, MAX_STATE)
+    s.x_hi = _f(problem.x_hi, MAX_STATE)
+    s.u_lo = _f(problem.u_lo, MAX_CONTROL)
+    s.u_hi = _f(problem.u_hi, MAX_CONTROL)
+    s.ws_lo = _f(problem.ws_lo, 3)
+    s.ws_hi = _f(problem.ws_hi, 3)
+    s.boxes = boxes.ctypes.data_as(C.POINTER(C.c_float)) if boxes.size else None
+    s.n_boxes = boxes.shape[0]
+    s.margin = problem.margin
+    s.goal_center = _f(problem.goal_center, 3)
+    s.goal_radius = problem.goal_radius
+    return s, boxes
+
+
+def params_struct(params):
+    s = ParamsC()
+    s.dt = params.dt
+    s.steps_min, s.steps_max = params.steps_min, params.steps_max
+    s.grid = (C.c_int32 * 3)(*[int(g) for g in params.grid])
+    s.vel_sign_bins = params.vel_sign_bins
+    s.n_select = params.n_select
+    s.samples_per_node = params.samples_per_node
+    s.i_max = params.i_max
+    s.tree_cap = params.tree_cap
+    s.seed = params.seed
+    s.query_id = params.query_id
+    return s
+
+
+def workspace_bytes(problem, params) -> int:
+    ps, keep = problem_struct(problem)
+    qs = params_struct(params)
+    out = C.c_size_t(0)
+    rc = lib().kpx_workspace_bytes(C.byref(ps), C.byref(qs), C.byref(out))
+    if rc != OK:
+        raise KPXError(rc)
+    return int(out.value)
+
+
+def create_status(problem, params) -> int:
+    """Status of kpx_create for arguments that fail host-side validation
+    (no GPU call is made on those paths); used by the argument tests."""
+    ps, keep = problem_struct(problem)
+    qs = params_struct(params)
+    h = _vp()
+    rc = lib().kpx_create(C.byref(ps), C.byref(qs), None, None, 0, C.byref(h))
+    if rc == OK:
+        lib().kpx_destroy(h)
+    return rc
+
+
+def philox(counter_key: np.ndarray) -> np.ndarray:
+    """Device Philox4x32-10 on rows (c0, c1, c2, c3, k0, k1)."""
+    ck = np.ascontiguousarray(counter_key, dtype=np.uint32).reshape(-1, 6)
+    out = np.zeros((ck.shape[0], 4), dtype=np.uint32)
+    rc = lib().kpx_philox(ck.ctypes.data, ck.shape[0], out.ctypes.data)
+    if rc != OK:
+        raise KPXError(rc)
+    return out
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class Planner:
+    """One planning query on the current GPU (a kpx_handle)."""
+
+    def __init__(self, problem, params, device: str = "cuda", stream=None,
+                 torch_workspace: bool = True):
+        import torch
+
+        self.problem, self.params = problem, params
+        self.d = {"DI6": 6, "QUAD12": 12, "DUBINS6": 6}[problem.dynamics]
+        self.m = {"DI6": 3, "QUAD12": 4, "DUBINS6": 3}[problem.dynamics]
+        self.n_cells = params.n_cells
+        self._ps, self._boxes = problem_struct(problem)
+        self._qs = params_struct(params)
+        self.device = torch.device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.workspace = None
+        ws_ptr, ws_bytes = None, 0
+        if torch_workspace:
+            ws_bytes = workspace_bytes(problem, params)
+            self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+            ws_ptr = self.workspace.data_ptr()
+        h = _vp()
+        rc = lib().kpx_create(C.byref(self._ps), C.byref(self._qs), _vp(stream.cuda_stream),
+                              ws_ptr, ws_bytes, C.byref(h))
+        if rc != OK:
+            raise KPXError(rc)
+        self.h = h
+
+    # -- error handling
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            msg = lib().kpx_last_error(self.h).decode() if getattr(self, "h", None) else ""
+            raise KPXError(rc, msg)
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().kpx_destroy(self.h)
+            self.h = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the cycle
+    def iterate(self, n: int = 1) -> int:
+        return self._check(lib().kpx_iterate(self.h, int(n)))
+
+    def sync(self) -> int:
+        return self._check(lib().kpx_sync(self.h))
+
+    def counters(self) -> dict:
+        c = CountersC()
+        self._check(lib().kpx_counters_read(self.h, C.byref(c)))
+        return {name: getattr(c, name) for name, _ in CountersC._fields_ if name != "reserved"}
+
+    def solution(self) -> dict:
+        info = SolutionInfoC()
+        self._check(lib().kpx_solution(self.h, C.byref(info), None, None, None, 0))
+        out = {name: getattr(info, name) for name, _ in SolutionInfoC._fields_ if name != "reserved"}
+        if info.found:
+            n = info.n_edges
+            states = np.zeros((n + 1, MAX_STATE), np.float32)
+            ctrl = np.zeros((max(n, 1), MAX_CONTROL), np.float32)
+            steps = np.zeros(max(n, 1), np.int32)
+            self._check(lib().kpx_solution(self.h, C.byref(info), states.ctypes.data,
+                                           ctrl.ctypes.data, steps.ctypes.data, n))
+            out.update(states=states[:, : self.d], controls=ctrl[:n, : self.m], steps=steps[:n])
+        return out
+
+    def snapshot(self) -> dict:
+        c = self.counters()
+        n = int(c["n_tree"])
+        cap = max(n, 1)
+        a = {
+            "state": np.zeros((MAX_STATE, cap), np.float32),
+            "control": np.zeros((MAX_CONTROL, cap), np.float32),
+            "steps": np.zeros(cap, np.int32), "parent": np.zeros(cap, np.int32),
+            "cost": np.zeros(cap, np.uint32), "cell": np.zeros(cap, np.int32),
+            "status": np.zeros(cap, np.uint8), "icount": np.zeros(cap, np.uint8),
+            "cell_table": np.zeros(self.n_cells, np.uint64),
+        }
+        v = TreeViewC()
+        v.capacity = cap
+        for k in ("state", "control", "steps", "parent", "cost", "cell", "status", "icount",
+                  "cell_table"):
+            setattr(v, k, a[k].ctypes.data)
+        v.cell_table_len = self.n_cells
+        cc = CountersC()
+        self._check(lib().kpx_snapshot(self.h, C.byref(v), C.byref(cc)))
+        out = {k: (arr[..., :n] if k != "cell_table" else arr) for k, arr in a.items()}
+        out["state"] = a["state"][: self.d, :n]
+        out["control"] = a["control"][: self.m, :n]
+        out["counters"] = {name: getattr(cc, name) for name, _ in CountersC._fields_
+                           if name != "reserved"}
+        return out
+
+    def set_dump(self, enable: bool = True):
+        self._check(lib().kpx_set_dump(self.h, 1 if enable else 0))
+
+    def read_dump(self) -> dict:
+        S = int(self.params.n_select) * int(self.params.samples_per_node)
+        cap = max(S, 1)
+        a = {
+            "parent": np.zeros(cap, np.int32), "control": np.zeros((MAX_CONTROL, cap), np.float32),
+            "steps": np.zeros(cap, np.int32), "state": np.zeros((MAX_STATE, cap), np.float32),
+            "first_invalid": np.zeros(cap, np.int32), "cell": np.zeros(cap, np.int32),
+            "key": np.zeros(cap, np.uint64), "goal": np.zeros(cap, np.uint8),
+            "survivor": np.zeros(cap, np.uint8),
+        }
+        v = DumpViewC()
+        v.capacity = cap
+        for k, arr in a.items():
+            setattr(v, k, arr.ctypes.data)
+        n = C.c_int64(0)
+        self._check(lib().kpx_read_dump(self.h, C.byref(v), C.byref(n)))
+        k = int(n.value)
+        out = {name: arr[..., :k] for name, arr in a.items()}
+        out["state"] = a["state"][: self.d, :k]
+        out["control"] = a["control"][: self.m, :k]
+        out["n_slots"] = k
+        return out
+
+    def set_timing(self, enable: bool = True):
+        self._check(lib().kpx_set_timing(self.h, 1 if enable else 0))
+
+    def read_timing(self):
+        ms = (C.c_double * 4)()
+        ln = (C.c_int64 * 4)()
+        self._check(lib().kpx_read_timing(self.h, ms, ln))
+        return list(ms), list(ln)
+
+    def stats(self, first: int, count: int) -> np.ndarray:
+        out = np.zeros(max(count, 1), dtype=STATS_DTYPE)
+        self._check(lib().kpx_read_stats(self.h, int(first), int(count), out.ctypes.data_as(
+            C.POINTER(IterStatsC))))
+        return out[:count]
+
+    def clock_rate_khz(self) -> int:
+        r = C.c_int64(0)
+        self._check(lib().kpx_clock_rate_khz(self.h, C.byref(r)))
+        return int(r.value)

@@ -1,0 +1,85 @@
+"""Edge cases of the HIP planner: capacity exhaustion, degenerate sizes, an
+unreachable goal, an obstacle-free scene, ragged slot counts."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+from oracle import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kpx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_02846_amd as K
+
+    K.lib()
+    return K
+
+
+def test_tiny_capacity_reports_full_and_stops(kpx, ora):
+    w = W.make_workload("di6", 0, n_select=32, samples=4, tree_cap=1 + 128 + 40)
+    P = ora.Problem(w.problem, w.params)
+    pl = kpx.Planner(w.problem, w.params)
+    rcs = []
+    for _ in range(60):
+        pl.iterate(1)
+        rcs.append(pl.sync())
+    assert kpx.FULL in rcs
+    c = pl.counters()
+    assert c["full"] == 1 and c["n_tree"] + 128 > w.params.tree_cap
+    assert pl.iterate(5) == kpx.FULL
+    assert pl.counters() == c
+    # the oracle agrees on when the tree fills
+    tr = ora.run(P, 60)
+    assert tr.c.full == 1 and tr.n_tree == c["n_tree"] and tr.c.iter == c["iteration"]
+    pl.close()
+
+
+@pytest.mark.parametrize("n_select,k", [(1, 1), (1, 33), (7, 1), (513, 3)])
+def test_degenerate_and_ragged_sizes_lockstep(kpx, ora, n_select, k):
+    w = W.make_workload("di6", 4, n_select=n_select, samples=k, tree_cap=1 << 15)
+    P = ora.Problem(w.problem, w.params)
+    pl = kpx.Planner(w.problem, w.params)
+    rep = parity.lockstep(ora, P, pl, 12)
+    assert rep["iterations"] == 12
+    pl.close()
+
+
+def test_unreachable_goal_has_no_solution(kpx):
+    w = W.make_workload("di6", 3)
+    c = w.problem.goal_center
+    w.problem.boxes = np.concatenate(
+        [w.problem.boxes, [[c[0] - 0.1, c[1] - 0.1, c[2] - 0.1, 1.0, 1.0, 1.0]]]).astype(np.float32)
+    pl = kpx.Planner(w.problem, w.params)
+    pl.iterate(120)
+    sol = pl.solution()
+    assert not sol["found"] and sol["tree_index"] == -1
+    assert pl.counters()["first_solution_iteration"] == -1
+    pl.close()
+
+
+def test_no_obstacles_lockstep(kpx, ora):
+    w = W.make_workload("quad12", 6, n_select=100, samples=5, grid=(8, 8, 8), tree_cap=1 << 15)
+    w.problem.boxes = np.zeros((0, 6), np.float32)
+    P = ora.Problem(w.problem, w.params)
+    pl = kpx.Planner(w.problem, w.params)
+    rep = parity.lockstep(ora, P, pl, 10)
+    assert rep["iterations"] == 10
+    pl.close()
+
+
+def test_dump_requires_recording(kpx):
+    w = W.make_workload("di6", 0, n_select=8, samples=2)
+    pl = kpx.Planner(w.problem, w.params)
+    pl.iterate(1)
+    with pytest.raises(kpx.KPXError) as e:
+        pl.read_dump()
+    assert e.value.code == -6
+    pl.close()

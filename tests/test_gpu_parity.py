@@ -1,0 +1,124 @@
+"""GPU parity of the HIP planner (through the C ABI) against the float64 oracle."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads.scenes import small_overrides
+
+from oracle import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kpx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_02846_amd as K
+
+    K.lib()
+    return K
+
+
+def _planner(kpx, w):
+    return kpx.Planner(w.problem, w.params)
+
+
+def test_device_philox_matches_oracle(kpx, ora):
+    rng = np.random.default_rng(3)
+    ck = rng.integers(0, 2**32, size=(1_000_000, 6), dtype=np.uint64).astype(np.uint32)
+    ck[:1000, 1] = np.arange(1000)  # the sample contract's counters: (it, slot, query, block)
+    ck[:1000, 0] = 7
+    ck[:1000, 2:4] = 0
+    dev = kpx.philox(ck)
+    ref = ora.philox_many(ck)
+    np.testing.assert_array_equal(dev, ref)
+
+
+# sizes the oracle replays in seconds that still span several survivor tiles
+# (2048 slots each) and several propagate blocks (256), with ragged tails
+LOCKSTEP = {
+    "di6": (dict(n_select=300, samples=9, tree_cap=1 << 16), 40),
+    "di6_path": (dict(n_select=300, samples=9, tree_cap=1 << 16, cost="PATH_LENGTH"), 30),
+    "quad12": (dict(n_select=260, samples=9, tree_cap=1 << 16, grid=(8, 8, 8)), 25),
+    "dubins6": (dict(n_select=230, samples=11, tree_cap=1 << 16, grid=(16, 16, 8)), 25),
+}
+
+
+@pytest.mark.parametrize("case", sorted(LOCKSTEP))
+def test_lockstep_iterations(kpx, ora, case):
+    kw, iters = LOCKSTEP[case]
+    name = case.split("_")[0]
+    w = W.make_workload(name, 5, **kw)
+    P = ora.Problem(w.problem, w.params)
+    pl = _planner(kpx, w)
+    rep = parity.lockstep(ora, P, pl, iters)
+    print(case, rep)
+    assert rep["iterations"] == iters
+    assert rep["valid"] > 0
+    pl.close()
+
+
+def test_lockstep_small_configs_from_later_iterations(kpx, ora):
+    """Run ahead without checking, then check: exercises larger trees, dormant
+    nodes, reactivation and a solution already present."""
+    w = W.make_workload("di6", 11, n_select=256, samples=8, i_max=2)
+    P = ora.Problem(w.problem, w.params)
+    pl = _planner(kpx, w)
+    pl.iterate(60)
+    pl.sync()
+    snap = pl.snapshot()
+    st = snap["status"]
+    assert (st == kpx.INACTIVE).any() and (st == kpx.TERMINAL).any()
+    rep = parity.lockstep(ora, P, pl, 15)
+    assert rep["iterations"] == 15
+    pl.close()
+
+
+@pytest.mark.parametrize("name", ["di6", "quad12", "dubins6"])
+def test_same_seed_same_tree(kpx, name):
+    kw = small_overrides(name)
+    trees = []
+    for _ in range(2):
+        w = W.make_workload(name, 2, **kw)
+        pl = _planner(kpx, w)
+        pl.iterate(30)
+        trees.append(pl.snapshot())
+        pl.close()
+    a, b = trees
+    for k in ("state", "control", "steps", "parent", "cost", "cell", "status", "icount", "cell_table"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert a["counters"] == b["counters"]
+
+
+def test_double_integrator_solution_verifies(kpx, ora):
+    w = W.make_workload("di6", 0)  # full size: 256 nodes x 8 samples
+    P = ora.Problem(w.problem, w.params)
+    pl = _planner(kpx, w)
+    pl.iterate(w.iterations)
+    sol = pl.solution()
+    assert sol["found"], pl.counters()
+    rep = ora.verify(P, sol["controls"], sol["steps"], sol["states"], float(sol["cost_field"]))
+    assert rep["ok"], rep
+    assert abs(sol["cost"] - sol["cost_field"] * w.params.dt) < 1e-9
+    pl.close()
+
+
+def test_stats_ring_and_timing(kpx):
+    w = W.make_workload("di6", 1, **small_overrides("di6"))
+    pl = _planner(kpx, w)
+    pl.set_timing(True)
+    pl.iterate(20)
+    ms, launches = pl.read_timing()
+    assert launches == [20, 20, 20, 20] and all(t > 0 for t in ms)
+    st = pl.stats(0, 20)
+    c = pl.counters()
+    assert st["iteration"].tolist() == list(range(20))
+    assert st["n_tree"][-1] == c["n_tree"]
+    assert np.all(np.diff(st["n_tree"]) == st["n_survivors"][1:])
+    assert np.all(st["t_end"] >= st["t_begin"])
+    assert pl.clock_rate_khz() > 0
+    pl.close()
