@@ -51,6 +51,8 @@ def parse():
                     help="bound on the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one device-to-device copy of this size (counter calibration)")
     return ap.parse_args()
 
 
@@ -71,6 +73,12 @@ def main():
     K.lib()  # fails loudly when the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.copy_bytes > 0:
+        src = torch.ones(a.copy_bytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.make_workload(a.workload, a.seed)
     prob, prm = w.problem, w.params
 

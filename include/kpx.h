@@ -29,7 +29,7 @@ extern "C" {
 
 #define KPX_MAX_STATE 12
 #define KPX_MAX_CONTROL 4
-#define KPX_MAX_BOXES 2048
+#define KPX_MAX_BOXES 1024
 
 /* status codes */
 #define KPX_OK 0
@@ -252,8 +252,8 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* view, int64_t* n_slots);
 int kpx_set_timing(kpx_handle* h, int32_t enable);
 
 /* Waits and returns, per kernel (0 propagate, 1 prune + survivor flags,
- * 2 insert, 3 finalize + select), the summed milliseconds and the number of
- * launches timed since timing was enabled. */
+ * 2 insert, 3 close of the iteration + next selection), the summed
+ * milliseconds and the number of launches timed since timing was enabled. */
 int kpx_read_timing(kpx_handle* h, double ms[4], int64_t launches[4]);
 
 /* Number of per-iteration records kept (a ring indexed by iteration). */

@@ -37,9 +37,15 @@ using namespace kpx;
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kItems = 8;                 // survivor slots per thread
-constexpr int kTile = kBlock * kItems;    // survivor slots per tile
+constexpr int kTile = kBlock;             // survivor slots per tile (one per thread)
 constexpr int kSelectThreads = 1024;
+constexpr int kSortBins = 64;             // step-count bins of the in-block sort
+constexpr int kBoxGridMax = 16;           // box-grid cells per workspace axis (at most)
+constexpr int kBoxGridBytes = 16 * 1024;  // LDS budget of the box grid and its lists
+constexpr int kChunkMax = 1024;           // expansion slots per propagate chunk (at most)
+constexpr int kChunkMin = 64;
+constexpr int kParMax = 256;              // parent states staged per chunk (at most)
+constexpr int kPerThread = kChunkMax / kBlock;
 constexpr int kStatsCap = 1 << 16;
 constexpr int kMaxPath = 1 << 16;
 
@@ -70,6 +76,7 @@ struct DevPtrs {
     uint8_t* status;
     uint8_t* icount;
     uint8_t* dead;       // terminal, or some ancestor was beaten (monotone)
+    int4* anc;           // 2 per node: the 8 nearest proper ancestors (-1 past the root)
     unsigned long long* tbl;
     int* sel;
     unsigned long long* ckey;
@@ -78,7 +85,10 @@ struct DevPtrs {
     uint8_t* cflag;      // bit 0 valid, bit 1 goal
     uint8_t* csurv;
     int* tile_count;
-    float* boxes;        // n_boxes x 6, grown by the margin
+    uint8_t* act;        // region will be expanded next (owner active after this iteration)
+    float4* boxes;       // 2 per box: lo, hi (grown by the margin)
+    int* gcell;          // box grid: first list entry | count << 20, per grid cell
+    uint16_t* glist;     // box grid: box indices
     DevState* st;
     kpx_iter_stats* stats;
     int* d_parent;       // dump (may be null)
@@ -140,10 +150,12 @@ __device__ __forceinline__ int block_sum(int v, int* lds)
 
 // ------------------------------------------------------------------ init
 
-__global__ void k_fill_table(unsigned long long* tbl, int n)
+__global__ void k_fill_table(unsigned long long* tbl, uint8_t* act, int n, int n_act)
 {
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
         tbl[c] = kEmpty;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_act; c += gridDim.x * blockDim.x)
+        act[c] = 0;
 }
 
 // Alg. 1 lines 1-5: the root is x_init, active; its region holds (0, root).
@@ -166,7 +178,10 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, const float* x_init)
     T.status[0] = kActive;
     T.icount[0] = 0;
     T.dead[0] = 0;
+    T.anc[0] = make_int4(-1, -1, -1, -1);
+    T.anc[1] = make_int4(-1, -1, -1, -1);
     T.tbl[c] = 0ull;  // cost 0, id 0
+    T.act[c] = 1;
     DevState* st = T.st;
     st->n_tree = 1;
     st->it = 0;
@@ -188,83 +203,214 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, const float* x_init)
 
 // Alg. 2 / Alg. 6: slot s = r * K + j expands the r-th selected node with the
 // j-th sample.  Integration stops at the first invalid substep.
+//
+// Most expansions end within a few substeps (an invalid state) while a few
+// run their whole duration, and a wave runs as long as its busiest lane.  So
+// each block (one per compute unit) takes chunks of slots and works through
+// each chunk as a queue:
+//   1. draw the chunk's samples, sort them by step count (longest first, a
+//      counting sort in LDS) and stage the chunk's parent states in LDS;
+//   2. every lane integrates one slot at a time and, when it finishes, takes
+//      the next slot of the queue (one LDS atomic per wave and refill);
+//   3. all lanes together bin the end states, take region minima and store.
+// The obstacle boxes and a uniform grid listing the boxes near each grid cell
+// live in LDS, so a substep touches no global memory.  Which lane integrates
+// which slot changes no result.
 template <int DYN, int COST>
 __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
-    extern __shared__ float sbox[];
-    for (int i = threadIdx.x; i < P.n_boxes * 6; i += blockDim.x) sbox[i] = T.boxes[i];
-    __syncthreads();
+    extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | grid lists
+    __shared__ float s_u[M][kChunkMax];
+    __shared__ unsigned short s_n[kChunkMax];
+    __shared__ unsigned short s_order[kChunkMax];
+    __shared__ short s_fi[kChunkMax];
+    __shared__ float s_len[COST == kPATH ? kChunkMax : 1];
+    __shared__ int s_bin[kSortBins];
+    __shared__ int s_next;
+    float4* sbox = dyn_lds;
+    float* spx = reinterpret_cast<float*>(dyn_lds + 2 * P.n_boxes);
+    int* sgc = reinterpret_cast<int*>(spx + D * kParMax);
+    uint16_t* sgl = reinterpret_cast<uint16_t*>(sgc + P.gb_cells);
+
     DevState* st = T.st;
-    if (st->full) return;
-    const int n_sel = st->n_sel;
+    const int S = st->n_sel * P.K;
+    if (st->full || S == 0) return;  // kernel-uniform
+    int chunk = max(kChunkMin, (S + (int)gridDim.x - 1) / (int)gridDim.x);
+    chunk = min(chunk, min(kChunkMax, (kParMax - 1) * P.K));
+    if ((int)blockIdx.x * chunk >= S) return;  // block-uniform
+    if (blockIdx.x == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const int S = n_sel * P.K;
-    if (blockIdx.x == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
-    if ((int)(blockIdx.x * blockDim.x) >= S) return;  // whole block idle
-
+    for (int i = threadIdx.x; i < 2 * P.n_boxes; i += blockDim.x) sbox[i] = T.boxes[i];
+    for (int i = threadIdx.x; i < P.gb_cells; i += blockDim.x) sgc[i] = T.gcell[i];
+    for (int i = threadIdx.x; i < P.gb_entries; i += blockDim.x) sgl[i] = T.glist[i];
+    const Hot<DYN> H = make_hot<DYN>(P);
+    const int lane = threadIdx.x & 63;
     int my_valid = 0, my_steps = 0;
-    if (s < S) {
-        const int parent = T.sel[s / P.K];
-        float u[M];
-        int n;
-        sample<DYN>(P, it, (uint32_t)s, u, n);
-        float x[D];
+
+    for (int base = blockIdx.x * chunk; base < S; base += gridDim.x * chunk) {
+        const int cnt = min(chunk, S - base);
+        const int r0 = base / P.K;
+        const int npar = (base + cnt - 1) / P.K - r0 + 1;
+        __syncthreads();  // LDS of the previous chunk is free
+        if (threadIdx.x < kSortBins) s_bin[threadIdx.x] = 0;
+        if (threadIdx.x == 0) s_next = 0;
+        // 1. parents, samples, sort by step count (longest first)
+        for (int idx = threadIdx.x; idx < npar * D; idx += blockDim.x) {
+            const int j = idx % npar, k = idx / npar;
+            spx[k * kParMax + j] = T.x[(long long)k * P.cap + T.sel[r0 + j]];
+        }
+        __syncthreads();
+        int bins[kPerThread];
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = T.x[(long long)k * P.cap + parent];
+        for (int r = 0; r < kPerThread; ++r) {
+            const int li = threadIdx.x + r * kBlock;
+            bins[r] = -1;
+            if (li < cnt) {
+                float u[M];
+                int n;
+                sample<DYN>(P, it, (uint32_t)(base + li), u, n);
+#pragma unroll
+                for (int k = 0; k < M; ++k) s_u[k][li] = u[k];
+                s_n[li] = (unsigned short)n;
+                bins[r] = (kSortBins - 1) - min(kSortBins - 1, (n - P.steps_min) >> P.sort_shift);
+                atomicAdd(&s_bin[bins[r]], 1);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {  // exclusive prefix over the 64 bins in one wave
+            const int v = s_bin[threadIdx.x];
+            int x = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o);
+                if ((int)threadIdx.x >= o) x += y;
+            }
+            s_bin[threadIdx.x] = x - v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r)
+            if (bins[r] >= 0)
+                s_order[atomicAdd(&s_bin[bins[r]], 1)] = (unsigned short)(threadIdx.x + r * kBlock);
+        __syncthreads();
+
+        // 2. integrate, each lane refilling from the queue
+        float x[D], u[M];
         float len = 0.f;
-        int fi = 0;
-        for (int k = 1; k <= n; ++k) {
-            rk4<DYN, COST>(P, x, u, len);
-            bool ok = in_bounds<DYN>(P, x);
-            for (int b = 0; b < P.n_boxes; ++b) ok &= !in_box(&sbox[6 * b], x[0], x[1], x[2]);
-            if (!ok) {
-                fi = k;
-                break;
+        int li = -1, n = 0, k = 0;
+        int gcur = -1, gstart = 0, gcount = 0;
+        bool drained = false;
+        while (true) {
+            const bool want = li < 0 && !drained;
+            const unsigned long long m = __ballot(want);
+            if (m) {
+                const int leader = __ffsll((long long)m) - 1;
+                int first = 0;
+                if (lane == leader) first = atomicAdd(&s_next, __popcll(m));
+                first = __shfl(first, leader);
+                if (want) {
+                    const int q = first + __popcll(m & __lanemask_lt());
+                    if (q < cnt) {
+                        li = s_order[q];
+                        n = s_n[li];
+                        const int pj = (base + li) / P.K - r0;
+#pragma unroll
+                        for (int c = 0; c < M; ++c) u[c] = s_u[c][li];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) x[c] = spx[c * kParMax + pj];
+                        k = 0;
+                        len = 0.f;
+                        gcur = -1;
+                    } else {
+                        drained = true;
+                    }
+                }
+            }
+            if (!__any(li >= 0)) break;
+            if (li >= 0) {
+                rk4<DYN, COST>(H, x, u, len);
+                ++k;
+                bool ok = in_bounds<DYN>(H, x);
+                if (ok) {
+                    const int g = box_grid_cell(H, x);
+                    if (g != gcur) {
+                        const int e = sgc[g];
+                        gstart = e & 0xFFFFF;
+                        gcount = e >> 20;
+                        gcur = g;
+                    }
+                    for (int j = 0; j < gcount; ++j)
+                        if (in_box(&sbox[2 * sgl[gstart + j]], x[0], x[1], x[2])) {
+                            ok = false;
+                            break;
+                        }
+                }
+                if (!ok || k == n) {
+                    s_fi[li] = (short)(ok ? 0 : k);
+                    if (ok) {
+                        if constexpr (COST == kPATH) s_len[li] = len;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) T.cx[(long long)c * P.s_max + base + li] = x[c];
+                    }
+                    li = -1;
+                }
             }
         }
-        my_steps = fi ? fi : n;
-        if (fi == 0) {
-            my_valid = 1;
-            const int c = cell_of(P, x);
-            uint32_t cf;
-            if constexpr (COST == kTIME) {
-                cf = T.cost[parent] + (uint32_t)n;
+        __syncthreads();
+
+        // 3. region map, cost, region minimum, candidate records
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) {
+            const int lj = threadIdx.x + r * kBlock;
+            if (lj >= cnt) continue;
+            const int s = base + lj;
+            const int fi = s_fi[lj];
+            const int nn = s_n[lj];
+            const int parent = T.sel[s / P.K];
+            my_steps += fi ? fi : nn;
+            if (fi == 0) {
+                ++my_valid;
+                float xe[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) xe[c] = T.cx[(long long)c * P.s_max + s];
+                const int c = cell_of(P, xe);
+                uint32_t cf;
+                if constexpr (COST == kTIME) {
+                    cf = T.cost[parent] + (uint32_t)nn;
+                } else {
+                    cf = __float_as_uint(__uint_as_float(T.cost[parent]) + s_len[lj]);
+                }
+                const unsigned long long key =
+                    ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)(n_tree + s);
+                const unsigned long long old = atomicMin(&T.tbl[c], key);
+                if (key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
+                    // this lane took the region from a tree node: it is beaten (V_T)
+                    const uint32_t o = (uint32_t)old;
+                    T.status[o] = kTerminal;
+                    T.dead[o] = 1;
+                }
+                T.ckey[s] = key;
+                T.ccell[s] = c;
+                T.cflag[s] = (uint8_t)(1 | (in_goal(P, xe) ? 2 : 0));
             } else {
-                cf = __float_as_uint(__uint_as_float(T.cost[parent]) + len);
+                T.ckey[s] = kEmpty;
+                T.ccell[s] = -1;
+                T.cflag[s] = 0;
             }
-            const unsigned long long key =
-                ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)(n_tree + s);
-            const unsigned long long old = atomicMin(&T.tbl[c], key);
-            if (key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
-                // this lane took the region from a tree node: it is beaten (V_T)
-                const uint32_t o = (uint32_t)old;
-                T.status[o] = kTerminal;
-                T.dead[o] = 1;
+            if (T.d_parent) {
+                T.d_parent[s] = parent;
+#pragma unroll
+                for (int q = 0; q < M; ++q) T.d_u[(long long)q * P.s_max + s] = s_u[q][lj];
+                T.d_n[s] = nn;
+                T.d_fi[s] = fi;
             }
-            T.ckey[s] = key;
-            T.ccell[s] = c;
-#pragma unroll
-            for (int k = 0; k < D; ++k) T.cx[(long long)k * P.s_max + s] = x[k];
-            T.cflag[s] = (uint8_t)(1 | (in_goal(P, x) ? 2 : 0));
-        } else {
-            T.ckey[s] = kEmpty;
-            T.ccell[s] = -1;
-            T.cflag[s] = 0;
-        }
-        if (T.d_parent) {
-            T.d_parent[s] = parent;
-#pragma unroll
-            for (int k = 0; k < M; ++k) T.d_u[(long long)k * P.s_max + s] = u[k];
-            T.d_n[s] = n;
-            T.d_fi[s] = fi;
         }
     }
     const int wv = wave_sum(my_valid);
     const int ws = wave_sum(my_steps);
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         if (wv) atomicAdd(&st->n_valid_acc, wv);
         if (ws) atomicAdd(&st->substeps_acc, (unsigned long long)ws);
     }
@@ -279,192 +425,238 @@ __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T,
     if (st->full) return;
     const long long n_tree = st->n_tree;
     if ((int)blockIdx.x < n_prune_blocks) {
-        // Alg. 3 for the owner of region c (every live node owns its region)
+        // Alg. 3 for the owner of region c (every live node owns its region);
+        // also records whether the region's node is active after this iteration
         const int c = blockIdx.x * blockDim.x + threadIdx.x;
         if (c >= P.n_cells) return;
         const unsigned long long key = T.tbl[c];
-        if (key == kEmpty) return;
-        const uint32_t o = (uint32_t)key;
-        if ((long long)o >= n_tree) return;  // an arrival of this iteration owns it
-        const uint8_t s0 = T.status[o];
-        if (s0 == kInactive) {  // lines 3-7
-            const int ic = T.icount[o] + 1;
-            T.icount[o] = (uint8_t)ic;
-            if (ic > P.i_max) T.status[o] = kActive;
-            return;
-        }
-        if (s0 != kActive) return;
-        if (T.icount[o] > P.i_max) return;  // lines 8-9
-        // lines 13-15: any ancestor beaten in its region (or below such a one)
-        for (int q = T.parent[o]; q >= 0; q = T.parent[q]) {
-            if (T.dead[q]) {
-                T.status[o] = kInactive;
-                T.dead[o] = 1;
-                return;
+        uint8_t a = 0;
+        if (key != kEmpty) {
+            const uint32_t o = (uint32_t)key;
+            if ((long long)o >= n_tree) {
+                a = 1;  // an arrival of this iteration owns it; it is inserted active
+            } else {
+                uint8_t s = T.status[o];
+                if (s == kInactive) {  // lines 3-7
+                    const int ic = T.icount[o] + 1;
+                    T.icount[o] = (uint8_t)ic;
+                    if (ic > P.i_max) {
+                        s = kActive;
+                        T.status[o] = kActive;
+                    }
+                } else if (s == kActive && T.icount[o] <= P.i_max) {
+                    // lines 13-15: any ancestor beaten in its region (or below
+                    // one); eight ancestors per step from the stored lists
+                    int q = o;
+                    bool beaten = false;
+                    while (q >= 0) {
+                        const int4 a = T.anc[2 * q], b = T.anc[2 * q + 1];
+                        const int ids[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+                        uint8_t d[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) d[j] = ids[j] >= 0 ? T.dead[ids[j]] : 0;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) beaten |= d[j] != 0;
+                        if (beaten) break;
+                        q = ids[7];
+                    }
+                    if (beaten) {
+                        s = kInactive;
+                        T.status[o] = kInactive;
+                        T.dead[o] = 1;
+                    }
+                }  // lines 8-9: a woken region-best node is left alone
+                a = s == kActive;
             }
         }
+        T.act[c] = a;
         return;
     }
-    // survivor mask and per-tile counts
+    // survivor mask V_U (App. A U-filter) and per-tile counts
     const int tile = blockIdx.x - n_prune_blocks;
     const int S = st->n_sel * P.K;
-    const int base = tile * kTile + threadIdx.x * kItems;
-    int cnt = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int s = base + k;
-        if (s < S) {
-            int f = 0;
-            if (T.cflag[s] & 1) f = T.ckey[s] == T.tbl[T.ccell[s]];
-            T.csurv[s] = (uint8_t)f;
-            cnt += f;
+    const int s = tile * kTile + threadIdx.x;
+    int f = 0;
+    if (s < S) {
+        if (T.cflag[s] & 1) f = T.ckey[s] == T.tbl[T.ccell[s]];
+        T.csurv[s] = (uint8_t)f;
+    }
+    const int total = block_sum(f, lds);
+    if (threadIdx.x == 0) T.tile_count[tile] = total;
+}
+
+// ------------------------------------------------------------------ finalize + select (one block)
+
+// Finishes an iteration: counters, statistics, capacity check.  Runs in one
+// block on the state copy in LDS.
+__device__ void finalize_iteration(const DevProblem& P, const DevPtrs& T, DevState& q, int* lds)
+{
+    const int S = q.n_sel * P.K;
+    const int tiles = (S + kTile - 1) / kTile;
+    int v = 0;
+    for (int j = threadIdx.x; j < tiles; j += blockDim.x) v += T.tile_count[j];
+    const int n_surv = block_sum(v, lds);
+    if (threadIdx.x == 0) {
+        const long long it = q.it;
+        const long long n_tree = q.n_tree + n_surv;
+        kpx_iter_stats* r = &T.stats[it & (kStatsCap - 1)];
+        r->iteration = it;
+        r->n_tree = n_tree;
+        r->n_select = q.n_sel;
+        r->n_valid = q.n_valid_acc;
+        r->n_survivors = n_surv;
+        r->reserved = 0;
+        r->substeps = (long long)q.substeps_acc;
+        r->solution_key = q.sol;
+        r->t_end = wall_clock64();
+        q.last_n_sel = q.n_sel;
+        q.last_n_valid = q.n_valid_acc;
+        q.last_n_surv = n_surv;
+        q.last_substeps = (long long)q.substeps_acc;
+        q.n_valid_acc = 0;
+        q.substeps_acc = 0;
+        if (q.sol != kEmpty && q.first_sol_it < 0) q.first_sol_it = it;
+        q.it = it + 1;
+        q.n_tree = n_tree;
+        q.cursor = q.cursor_next;
+        q.full = (n_tree + P.surv_max > P.cap) ? 1 : 0;
+    }
+    __syncthreads();
+}
+
+// Selects the next iteration's nodes: regions whose owner is active, in
+// region order rotated to start at the cursor, at most n_select.  One block;
+// each thread owns a run of whole 4-region words of the activity bytes (0/1,
+// zero-padded past the last region).
+__device__ void select_nodes(const DevProblem& P, const DevPtrs& T, DevState& q, int* lds)
+{
+    if (q.full) {
+        if (threadIdx.x == 0) q.n_sel = 0;
+        __syncthreads();
+        return;
+    }
+    const int nc = P.n_cells;
+    const int cur = q.cursor;
+    const int nwords = (nc + 3) >> 2;
+    const int per = (nwords + blockDim.x - 1) / blockDim.x;
+    const int w0 = threadIdx.x * per;
+    const int w1 = min(w0 + per, nwords);
+    const uint32_t* act = reinterpret_cast<const uint32_t*>(T.act);
+    int hi = 0, lo = 0;
+    for (int w = w0; w < w1; ++w) {
+        uint32_t wd = act[w] & 0x01010101u;
+        const int c0 = 4 * w;
+        if (c0 >= cur) {
+            hi += __popc(wd);
+        } else if (c0 + 4 <= cur) {
+            lo += __popc(wd);
+        } else {  // the cursor falls inside this word
+            const uint32_t below = (1u << (8 * (cur - c0))) - 1u;
+            lo += __popc(wd & below);
+            hi += __popc(wd & ~below);
         }
     }
-    const int total = block_sum(cnt, lds);
-    if (threadIdx.x == 0) T.tile_count[tile] = total;
+    int total_hi, total_lo;
+    const int ex_hi = block_exclusive_scan(hi, lds, &total_hi);
+    const int ex_lo = block_exclusive_scan(lo, lds, &total_lo);
+    const int nsel = min(total_hi + total_lo, P.n_select);
+    int r_hi = ex_hi, r_lo = total_hi + ex_lo;
+    for (int w = w0; w < w1; ++w) {
+        uint32_t wd = act[w] & 0x01010101u;
+        while (wd) {
+            const int bit = __ffs(wd) - 1;
+            wd &= wd - 1;
+            const int c = 4 * w + (bit >> 3);
+            const int rank = c >= cur ? r_hi++ : r_lo++;
+            if (rank < nsel) {
+                T.sel[rank] = c;  // region for now; owner filled in below
+                if (rank == nsel - 1) q.cursor_next = (c + 1 == nc) ? 0 : c + 1;
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nsel; r += blockDim.x) T.sel[r] = (int)(uint32_t)T.tbl[T.sel[r]];
+    if (threadIdx.x == 0) {
+        q.n_sel = nsel;
+        if (nsel == 0) q.cursor_next = cur;
+    }
+    __syncthreads();
+}
+
+// Selection alone (after create).
+__global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs T)
+{
+    __shared__ int lds[kSelectThreads / 64 + 1];
+    __shared__ DevState s_st;
+    if (threadIdx.x == 0) s_st = *T.st;
+    __syncthreads();
+    select_nodes(P, T, s_st, lds);
+    if (threadIdx.x == 0) *T.st = s_st;
 }
 
 // ------------------------------------------------------------------ insert
 
+// App. A UpdateTree: survivors appended at |T| + rank (exclusive scan of V_U).
 template <int DYN>
 __global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
     __shared__ int lds[kBlock / 64 + 1];
     DevState* st = T.st;
-    if (st->full) return;
+    if (st->full) return;  // kernel-uniform: nothing happens in a full tree
     const int S = st->n_sel * P.K;
     const int tile = blockIdx.x;
-    if (tile * kTile >= S) return;
-    int pre = 0;
-    for (int j = threadIdx.x; j < tile; j += blockDim.x) pre += T.tile_count[j];
-    pre = block_sum(pre, lds);
-    const int base = tile * kTile + threadIdx.x * kItems;
-    int f[kItems];
-    int cnt = 0;
+    if (tile * kTile < S) {
+        int pre = 0;
+        for (int j = threadIdx.x; j < tile; j += blockDim.x) pre += T.tile_count[j];
+        pre = block_sum(pre, lds);
+        const int s = tile * kTile + threadIdx.x;
+        const int f = s < S ? T.csurv[s] : 0;
+        int total;
+        const int rank = pre + block_exclusive_scan(f, lds, &total);
+        if (f) {
+            const long long i = st->n_tree + rank;
+            const uint32_t it = (uint32_t)st->it;
+            float u[M];
+            int n;
+            sample<DYN>(P, it, (uint32_t)s, u, n);
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int s = base + k;
-        f[k] = s < S ? T.csurv[s] : 0;
-        cnt += f[k];
-    }
-    int total;
-    int rank = pre + block_exclusive_scan(cnt, lds, &total);
-    const long long n_tree = st->n_tree;
-    const uint32_t it = (uint32_t)st->it;
+            for (int q = 0; q < D; ++q) T.x[(long long)q * P.cap + i] = T.cx[(long long)q * P.s_max + s];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        if (!f[k]) continue;
-        const int s = base + k;
-        const long long i = n_tree + rank++;
-        float u[M];
-        int n;
-        sample<DYN>(P, it, (uint32_t)s, u, n);
-#pragma unroll
-        for (int q = 0; q < D; ++q) T.x[(long long)q * P.cap + i] = T.cx[(long long)q * P.s_max + s];
-#pragma unroll
-        for (int q = 0; q < M; ++q) T.u[(long long)q * P.cap + i] = u[q];
-        const unsigned long long key = T.ckey[s];
-        const uint32_t cf = (uint32_t)(key >> 32);
-        const int c = T.ccell[s];
-        T.steps[i] = (uint16_t)n;
-        T.parent[i] = T.sel[s / P.K];
-        T.cost[i] = cf;
-        T.cell[i] = c;
-        T.status[i] = kActive;
-        T.icount[i] = 0;
-        T.dead[i] = 0;
-        const unsigned long long nk = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)i;
-        T.tbl[c] = nk;
-        if (T.cflag[s] & 2) atomicMin(&st->sol, nk);  // Alg. 4 lines 5-7
+            for (int q = 0; q < M; ++q) T.u[(long long)q * P.cap + i] = u[q];
+            const unsigned long long key = T.ckey[s];
+            const uint32_t cf = (uint32_t)(key >> 32);
+            const int c = T.ccell[s];
+            const int par = T.sel[s / P.K];
+            const int4 pa = T.anc[2 * par], pb = T.anc[2 * par + 1];
+            T.anc[2 * i] = make_int4(par, pa.x, pa.y, pa.z);
+            T.anc[2 * i + 1] = make_int4(pa.w, pb.x, pb.y, pb.z);
+            T.steps[i] = (uint16_t)n;
+            T.parent[i] = par;
+            T.cost[i] = cf;
+            T.cell[i] = c;
+            T.status[i] = kActive;
+            T.icount[i] = 0;
+            T.dead[i] = 0;
+            const unsigned long long nk = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)i;
+            T.tbl[c] = nk;
+            if (T.cflag[s] & 2) atomicMin(&st->sol, nk);  // Alg. 4 lines 5-7
+        }
     }
 }
 
-// ------------------------------------------------------------------ finalize + select
-
-__global__ __launch_bounds__(kSelectThreads) void k_finalize_select(DevProblem P, DevPtrs T,
-                                                                    int do_finalize)
+// Closes the iteration (counters, statistics, capacity check) and selects the
+// next iteration's nodes.  One block; the device state is read once into LDS
+// and written back once.
+__global__ __launch_bounds__(kSelectThreads) void k_finalize_select(DevProblem P, DevPtrs T)
 {
     __shared__ int lds[kSelectThreads / 64 + 1];
-    __shared__ int s_full, s_cursor;
-    __shared__ long long s_n_tree;
-    DevState* st = T.st;
-    if (do_finalize) {
-        const int was_full = st->full;
-        if (!was_full) {
-            const int S = st->n_sel * P.K;
-            const int tiles = (S + kTile - 1) / kTile;
-            int v = 0;
-            for (int j = threadIdx.x; j < tiles; j += blockDim.x) v += T.tile_count[j];
-            const int n_surv = block_sum(v, lds);
-            if (threadIdx.x == 0) {
-                const long long it = st->it;
-                const long long n_tree = st->n_tree + n_surv;
-                kpx_iter_stats* r = &T.stats[it & (kStatsCap - 1)];
-                r->iteration = it;
-                r->n_tree = n_tree;
-                r->n_select = st->n_sel;
-                r->n_valid = st->n_valid_acc;
-                r->n_survivors = n_surv;
-                r->reserved = 0;
-                r->substeps = (long long)st->substeps_acc;
-                r->solution_key = st->sol;
-                r->t_end = wall_clock64();
-                st->last_n_sel = st->n_sel;
-                st->last_n_valid = st->n_valid_acc;
-                st->last_n_surv = n_surv;
-                st->last_substeps = (long long)st->substeps_acc;
-                st->n_valid_acc = 0;
-                st->substeps_acc = 0;
-                if (st->sol != kEmpty && st->first_sol_it < 0) st->first_sol_it = it;
-                st->it = it + 1;
-                st->n_tree = n_tree;
-                st->cursor = st->cursor_next;
-                st->full = (n_tree + P.surv_max > P.cap) ? 1 : 0;
-            }
-        }
-    }
-    if (threadIdx.x == 0) {
-        s_full = st->full;
-        s_cursor = st->cursor;
-        s_n_tree = st->n_tree;
-    }
+    __shared__ DevState s_st;
+    if (threadIdx.x == 0) s_st = *T.st;
     __syncthreads();
-    if (s_full) {
-        if (threadIdx.x == 0) st->n_sel = 0;
-        return;
-    }
-    // selection: active region owners in region order starting at the cursor
-    const int nc = P.n_cells;
-    const int cur = s_cursor;
-    const long long n_tree = s_n_tree;
-    const int per = (nc + blockDim.x - 1) / blockDim.x;
-    const int j0 = threadIdx.x * per;
-    const int j1 = min(j0 + per, nc);
-    int cnt = 0;
-    for (int j = j0; j < j1; ++j) {
-        int c = cur + j;
-        if (c >= nc) c -= nc;
-        const unsigned long long key = T.tbl[c];
-        if (key != kEmpty && (long long)(uint32_t)key < n_tree && T.status[(uint32_t)key] == kActive) ++cnt;
-    }
-    int total;
-    int rank = block_exclusive_scan(cnt, lds, &total);
-    const int nsel = min(total, P.n_select);
-    for (int j = j0; j < j1 && rank < nsel; ++j) {
-        int c = cur + j;
-        if (c >= nc) c -= nc;
-        const unsigned long long key = T.tbl[c];
-        if (key != kEmpty && (long long)(uint32_t)key < n_tree && T.status[(uint32_t)key] == kActive) {
-            T.sel[rank] = (int)(uint32_t)key;
-            if (rank == nsel - 1) st->cursor_next = (c + 1 == nc) ? 0 : c + 1;
-            ++rank;
-        }
-    }
-    if (threadIdx.x == 0) {
-        st->n_sel = nsel;
-        if (nsel == 0) st->cursor_next = cur;
-    }
+    if (!s_st.full) finalize_iteration(P, T, s_st, lds);
+    select_nodes(P, T, s_st, lds);
+    if (threadIdx.x == 0) *T.st = s_st;
 }
 
 // ------------------------------------------------------------------ solution path
@@ -525,6 +717,9 @@ struct Sizes {
     int d, m;
     long long cap;
     int n_cells, s_max, n_tiles, n_boxes;
+    int n_act;            // activity bytes, padded to whole words
+    int gb_n[3];          // box grid cells per axis
+    int gb_entries;       // total list entries of the box grid
 };
 
 // all device arrays, in order; the same function sizes and carves them
@@ -541,6 +736,7 @@ void for_each_array(const Sizes& z, F&& f)
     f("status", cap);
     f("icount", cap);
     f("dead", cap);
+    f("anc", sizeof(int4) * 2 * cap);
     f("tbl", sizeof(unsigned long long) * (size_t)z.n_cells);
     f("sel", sizeof(int) * S);
     f("ckey", sizeof(unsigned long long) * S);
@@ -549,7 +745,10 @@ void for_each_array(const Sizes& z, F&& f)
     f("cflag", S);
     f("csurv", S);
     f("tile_count", sizeof(int) * (size_t)z.n_tiles);
-    f("boxes", sizeof(float) * 6 * (size_t)(z.n_boxes > 0 ? z.n_boxes : 1));
+    f("act", (size_t)z.n_act);
+    f("boxes", sizeof(float4) * 2 * (size_t)(z.n_boxes > 0 ? z.n_boxes : 1));
+    f("gcell", sizeof(int) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2]);
+    f("glist", sizeof(uint16_t) * (size_t)(z.gb_entries > 0 ? z.gb_entries : 1));
     f("st", sizeof(DevState));
     f("stats", sizeof(kpx_iter_stats) * kStatsCap);
     f("d_parent", sizeof(int) * S);
@@ -565,6 +764,61 @@ void for_each_array(const Sizes& z, F&& f)
 }
 
 bool finite(float v) { return std::isfinite(v); }
+
+// Box grid: a uniform G^3 grid over the workspace; each grid cell lists the
+// boxes (grown by the margin) that overlap it, grown by a small slack so that
+// rounding in the device's float32 cell index can never miss a box.  G is the
+// finest resolution whose cells and lists fit the LDS budget.
+struct BoxGrid {
+    int n[3];
+    std::vector<int> cells;  // first entry | count << 20
+    std::vector<uint16_t> list;
+};
+
+void build_box_grid_at(const kpx_problem* p, int G, BoxGrid* g)
+{
+    for (int a = 0; a < 3; ++a) g->n[a] = G;
+    const size_t nc = (size_t)G * G * G;
+    std::vector<std::vector<uint16_t>> per(nc);
+    for (int b = 0; b < p->n_boxes; ++b) {
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            const double w0 = p->ws_lo[a], w1 = p->ws_hi[a];
+            const double slack = 1e-4 * (w1 - w0);
+            const double scale = G / (w1 - w0);
+            const double blo = (double)p->boxes[6 * b + a] - p->margin - slack;
+            const double bhi = (double)p->boxes[6 * b + 3 + a] + p->margin + slack;
+            lo[a] = std::max(0, std::min(G - 1, (int)std::floor((blo - w0) * scale)));
+            hi[a] = std::max(0, std::min(G - 1, (int)std::floor((bhi - w0) * scale)));
+        }
+        for (int i = lo[0]; i <= hi[0]; ++i)
+            for (int j = lo[1]; j <= hi[1]; ++j)
+                for (int k = lo[2]; k <= hi[2]; ++k) per[((size_t)i * G + j) * G + k].push_back((uint16_t)b);
+    }
+    g->cells.resize(nc);
+    g->list.clear();
+    for (size_t c = 0; c < nc; ++c) {
+        g->cells[c] = (int)g->list.size() | ((int)per[c].size() << 20);
+        g->list.insert(g->list.end(), per[c].begin(), per[c].end());
+    }
+}
+
+size_t box_grid_bytes(const BoxGrid& g)
+{
+    return sizeof(int) * g.cells.size() + sizeof(uint16_t) * g.list.size();
+}
+
+void build_box_grid(const kpx_problem* p, BoxGrid* g)
+{
+    if (p->n_boxes == 0) {
+        build_box_grid_at(p, 1, g);
+        return;
+    }
+    for (int G = kBoxGridMax; G >= 1; --G) {
+        build_box_grid_at(p, G, g);
+        if (box_grid_bytes(*g) <= (size_t)kBoxGridBytes || G == 1) return;
+    }
+}
 
 // Host-side validation of Problem 1 and the parameters; no GPU call.
 int validate(const kpx_problem* p, const kpx_params* q, Sizes* z, std::string* why)
@@ -628,6 +882,11 @@ int validate(const kpx_problem* p, const kpx_params* q, Sizes* z, std::string* w
         z->s_max = (int)S;
         z->n_tiles = (int)((S + kTile - 1) / kTile);
         z->n_boxes = p->n_boxes;
+        z->n_act = (int)((nc + 4095) & ~4095ll);
+        BoxGrid g;
+        build_box_grid(p, &g);
+        for (int a = 0; a < 3; ++a) z->gb_n[a] = g.n[a];
+        z->gb_entries = (int)g.list.size();
     }
     return KPX_OK;
 }
@@ -678,7 +937,20 @@ DevProblem make_dev_problem(const kpx_problem* p, const kpx_params* q, const Siz
         P.gyro[2] = jy - jx;
         P.grav = p->dyn_params[4];
     }
+    P.bound_mask = 0;
+    for (int i = 0; i < z.d; ++i)
+        if (std::isfinite(p->x_lo[i]) || std::isfinite(p->x_hi[i])) P.bound_mask |= 1u << i;
     P.n_boxes = p->n_boxes;
+    for (int a = 0; a < 3; ++a) {
+        P.gb_lo[a] = p->ws_lo[a];
+        P.gb_scale[a] = (float)z.gb_n[a] / (p->ws_hi[a] - p->ws_lo[a]);
+        P.gb_n[a] = z.gb_n[a];
+    }
+    P.gb_cells = z.gb_n[0] * z.gb_n[1] * z.gb_n[2];
+    P.gb_entries = z.gb_entries;
+    P.n_cu = 1;
+    P.sort_shift = 0;
+    while (((q->steps_max - q->steps_min) >> P.sort_shift) >= kSortBins) ++P.sort_shift;
     P.n_cells = z.n_cells;
     P.K = q->samples_per_node;
     P.n_select = q->n_select;
@@ -769,6 +1041,7 @@ void carve(kpx_handle* h)
     T.status = (uint8_t*)ptrs[k++];
     T.icount = (uint8_t*)ptrs[k++];
     T.dead = (uint8_t*)ptrs[k++];
+    T.anc = (int4*)ptrs[k++];
     T.tbl = (unsigned long long*)ptrs[k++];
     T.sel = (int*)ptrs[k++];
     T.ckey = (unsigned long long*)ptrs[k++];
@@ -777,7 +1050,10 @@ void carve(kpx_handle* h)
     T.cflag = (uint8_t*)ptrs[k++];
     T.csurv = (uint8_t*)ptrs[k++];
     T.tile_count = (int*)ptrs[k++];
-    T.boxes = (float*)ptrs[k++];
+    T.act = (uint8_t*)ptrs[k++];
+    T.boxes = (float4*)ptrs[k++];
+    T.gcell = (int*)ptrs[k++];
+    T.glist = (uint16_t*)ptrs[k++];
     T.st = (DevState*)ptrs[k++];
     T.stats = (kpx_iter_stats*)ptrs[k++];
     T.d_parent = (int*)ptrs[k++];
@@ -811,12 +1087,38 @@ DevPtrs kernel_ptrs(const kpx_handle* h)
     return T;
 }
 
+size_t propagate_lds_bytes(const Sizes& z, int d)
+{
+    return sizeof(float4) * 2 * (size_t)z.n_boxes + sizeof(float) * (size_t)d * kParMax +
+           sizeof(int) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2] +
+           sizeof(uint16_t) * (size_t)z.gb_entries;
+}
+
 template <int DYN, int COST>
 void launch_propagate(kpx_handle* h, const DevPtrs& T)
 {
-    const int grid = (h->z.s_max + kBlock - 1) / kBlock;
-    const size_t lds = sizeof(float) * 6 * (size_t)h->z.n_boxes;
-    k_propagate<DYN, COST><<<grid, kBlock, lds, h->stream>>>(h->P, T);
+    k_propagate<DYN, COST><<<h->P.n_cu, kBlock, propagate_lds_bytes(h->z, Dims<DYN>::D), h->stream>>>(
+        h->P, T);
+}
+
+template <int DYN, int COST>
+hipError_t set_lds(kpx_handle* h)
+{
+    return hipFuncSetAttribute((const void*)k_propagate<DYN, COST>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)propagate_lds_bytes(h->z, Dims<DYN>::D));
+}
+
+hipError_t set_propagate_lds(kpx_handle* h)
+{
+    switch (h->P.dyn * 2 + h->P.cost) {
+    case 0: return set_lds<kDI6, kTIME>(h);
+    case 1: return set_lds<kDI6, kPATH>(h);
+    case 2: return set_lds<kQUAD12, kTIME>(h);
+    case 3: return set_lds<kQUAD12, kPATH>(h);
+    case 4: return set_lds<kDUBINS6, kTIME>(h);
+    default: return set_lds<kDUBINS6, kPATH>(h);
+    }
 }
 
 void propagate(kpx_handle* h, const DevPtrs& T)
@@ -910,6 +1212,26 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
     h->P = make_dev_problem(prob, prm, z);
     h->stream = (hipStream_t)hip_stream;
     h->bytes = need;
+    {
+        int dev = 0, n_cu = 0, lds_max = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            delete h;
+            return KPX_ERR_DEVICE;
+        }
+        h->P.n_cu = std::max(1, n_cu);
+        const size_t static_lds = sizeof(float) * KPX_MAX_CONTROL * kChunkMax + 3 * 2 * kChunkMax +
+                                  sizeof(float) * kChunkMax + sizeof(int) * (kSortBins + 1);
+        if (propagate_lds_bytes(z, z.d) + static_lds > (size_t)lds_max) {
+            delete h;
+            return KPX_ERR_ARG;
+        }
+        if (set_propagate_lds(h) != hipSuccess) {
+            delete h;
+            return KPX_ERR_DEVICE;
+        }
+    }
     if (workspace) {
         h->base = workspace;
     } else {
@@ -923,13 +1245,15 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
     carve(h);
     h->n_prune_blocks = (z.n_cells + kBlock - 1) / kBlock;
 
-    // boxes grown by the margin, x_init
-    std::vector<float> boxes((size_t)6 * (z.n_boxes > 0 ? z.n_boxes : 1), 0.f);
+    // boxes grown by the margin (two float4 each), the box grid, x_init
+    std::vector<float> boxes((size_t)8 * (z.n_boxes > 0 ? z.n_boxes : 1), 0.f);
     for (int b = 0; b < z.n_boxes; ++b)
         for (int a = 0; a < 3; ++a) {
-            boxes[6 * b + a] = prob->boxes[6 * b + a] - prob->margin;
-            boxes[6 * b + 3 + a] = prob->boxes[6 * b + 3 + a] + prob->margin;
+            boxes[8 * b + a] = prob->boxes[6 * b + a] - prob->margin;
+            boxes[8 * b + 4 + a] = prob->boxes[6 * b + 3 + a] + prob->margin;
         }
+    BoxGrid grid;
+    build_box_grid(prob, &grid);
     auto cleanup = [&](int code) {
         kpx_destroy(h);
         return code;
@@ -937,18 +1261,25 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
     if (hipMemcpyAsync(h->T.boxes, boxes.data(), sizeof(float) * boxes.size(), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess)
         return cleanup(KPX_ERR_DEVICE);
+    if (hipMemcpyAsync(h->T.gcell, grid.cells.data(), sizeof(int) * grid.cells.size(),
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return cleanup(KPX_ERR_DEVICE);
+    if (!grid.list.empty() &&
+        hipMemcpyAsync(h->T.glist, grid.list.data(), sizeof(uint16_t) * grid.list.size(),
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return cleanup(KPX_ERR_DEVICE);
     float* xi = h->T.x_init;
     if (hipMemcpyAsync(xi, prob->x_init, sizeof(float) * KPX_MAX_STATE, hipMemcpyHostToDevice,
                        h->stream) != hipSuccess)
         return cleanup(KPX_ERR_DEVICE);
-    k_fill_table<<<std::min(1024, (z.n_cells + kBlock - 1) / kBlock), kBlock, 0, h->stream>>>(h->T.tbl,
-                                                                                              z.n_cells);
+    k_fill_table<<<std::min(1024, (z.n_act + kBlock - 1) / kBlock), kBlock, 0, h->stream>>>(
+        h->T.tbl, h->T.act, z.n_cells, z.n_act);
     switch (h->P.dyn) {
     case kDI6: k_init_root<kDI6><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
     case kQUAD12: k_init_root<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
     default: k_init_root<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
     }
-    k_finalize_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, h->T, 0);
+    k_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, h->T);
     if (hipGetLastError() != hipSuccess) return cleanup(KPX_ERR_DEVICE);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(KPX_ERR_DEVICE);
     *out = h;
@@ -970,7 +1301,7 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
         if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
         insert(h, T);
         if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
-        k_finalize_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, T, 1);
+        k_finalize_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, T);
         if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
     }
     KPX_HIP(h, hipGetLastError());

@@ -50,7 +50,14 @@ struct DevProblem {
     int vel_sign_bins, vel_idx;
     float goal_c[3], goal_r2;      // (goal radius - margin)^2
     float inv_mass, inv_j[3], gyro[3], grav;
+    uint32_t bound_mask;           // bit i: component i has a finite bound
     int n_boxes;
+    // uniform grid over the workspace listing, per grid cell, the (grown)
+    // boxes that overlap it: a point is only tested against its cell's list
+    float gb_lo[3], gb_scale[3];
+    int gb_n[3];
+    int gb_cells, gb_entries;
+    int n_cu;                      // compute units: propagate runs one block per CU
     int n_cells;
     int K, n_select, s_max;
     int i_max;
@@ -58,6 +65,7 @@ struct DevProblem {
     long long cap;
     uint32_t seed_lo, seed_hi, query;
     int n_tiles;                   // survivor-count tiles covering s_max slots
+    int sort_shift;                // step-count sort: bin = (n - steps_min) >> sort_shift
 };
 
 // ---------------------------------------------------------------------------
@@ -107,11 +115,57 @@ __device__ __forceinline__ void sample(const DevProblem& P, uint32_t it, uint32_
     n = P.steps_min + (int)__umulhi(w[M], (uint32_t)P.steps_range);
 }
 
+// Constants the integration loop reads every substep, gathered into one small
+// struct: state bounds (the workspace folded into the position bounds; +-inf
+// where unbounded), step sizes and model constants.
+template <int DYN>
+struct Hot {
+    static constexpr int D = Dims<DYN>::D;
+    float dt, h2, h6;
+    float lo[D], hi[D];
+    float inv_mass, inv_j[3], gyro[3], grav;
+    float gb_lo[3], gb_scale[3];
+    int gb_n[3];
+};
+
+template <int DYN>
+__device__ __forceinline__ Hot<DYN> make_hot(const DevProblem& P)
+{
+    constexpr int D = Dims<DYN>::D;
+    Hot<DYN> H;
+    H.dt = P.dt;
+    H.h2 = P.h2;
+    H.h6 = P.h6;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        H.lo[i] = i < 3 ? __builtin_fmaxf(P.x_lo[i], P.ws_lo[i]) : P.x_lo[i];
+        H.hi[i] = i < 3 ? __builtin_fminf(P.x_hi[i], P.ws_hi[i]) : P.x_hi[i];
+        // keep the bounds in vector registers: the loop compares against them
+        // every substep and scalar registers are short
+        asm volatile("" : "+v"(H.lo[i]));
+        asm volatile("" : "+v"(H.hi[i]));
+    }
+    H.inv_mass = P.inv_mass;
+    H.grav = P.grav;
+    asm volatile("" : "+v"(H.dt), "+v"(H.h2), "+v"(H.h6), "+v"(H.inv_mass), "+v"(H.grav));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        H.inv_j[a] = P.inv_j[a];
+        H.gyro[a] = P.gyro[a];
+        H.gb_lo[a] = P.gb_lo[a];
+        H.gb_scale[a] = P.gb_scale[a];
+        H.gb_n[a] = P.gb_n[a];
+        asm volatile("" : "+v"(H.inv_j[a]), "+v"(H.gyro[a]), "+v"(H.gb_lo[a]), "+v"(H.gb_scale[a]),
+                     "+v"(H.gb_n[a]));
+    }
+    return H;
+}
+
 // ---------------------------------------------------------------------------
 // Dynamics f(x, u) and, for the path-length cost, the speed |p'|.
 // ---------------------------------------------------------------------------
 template <int DYN, int COST>
-__device__ __forceinline__ void deriv(const DevProblem& P, const float* x, const float* u,
+__device__ __forceinline__ void deriv(const Hot<DYN>& P, const float* x, const float* u,
                                       float* xd, float& ld)
 {
     if constexpr (DYN == kDI6) {
@@ -152,7 +206,7 @@ __device__ __forceinline__ void deriv(const DevProblem& P, const float* x, const
 
 // Classical RK4 step of size dt on the state (and the path length).
 template <int DYN, int COST>
-__device__ __forceinline__ void rk4(const DevProblem& P, float* x, const float* u, float& len)
+__device__ __forceinline__ void rk4(const Hot<DYN>& P, float* x, const float* u, float& len)
 {
     constexpr int D = Dims<DYN>::D;
     float k[D], acc[D], t[D];
@@ -184,23 +238,39 @@ __device__ __forceinline__ void rk4(const DevProblem& P, float* x, const float* 
     if constexpr (COST == kPATH) len = __builtin_fmaf(P.h6, lacc + lk, len);
 }
 
-// Workspace and state bounds (closed; bounds may be infinite).
+// Workspace and state bounds (closed; unbounded components compare against
+// +-inf and always pass).
 template <int DYN>
-__device__ __forceinline__ bool in_bounds(const DevProblem& P, const float* x)
+__device__ __forceinline__ bool in_bounds(const Hot<DYN>& H, const float* x)
 {
     constexpr int D = Dims<DYN>::D;
     bool ok = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) ok &= (x[a] >= P.ws_lo[a]) & (x[a] <= P.ws_hi[a]);
-#pragma unroll
-    for (int i = 0; i < D; ++i) ok &= (x[i] >= P.x_lo[i]) & (x[i] <= P.x_hi[i]);
+    for (int i = 0; i < D; ++i) ok &= (x[i] >= H.lo[i]) & (x[i] <= H.hi[i]);
     return ok;
 }
 
-// Point inside a closed box (grown by the margin): a collision.
-__device__ __forceinline__ bool in_box(const float* b, float px, float py, float pz)
+// Index of the box-grid cell holding position p (clamped).
+template <typename C>
+__device__ __forceinline__ int box_grid_cell(const C& P, const float* x)
 {
-    return (px >= b[0]) & (px <= b[3]) & (py >= b[1]) & (py <= b[4]) & (pz >= b[2]) & (pz <= b[5]);
+    int idx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int i = (int)__builtin_floorf((x[a] - P.gb_lo[a]) * P.gb_scale[a]);
+        i = i < 0 ? 0 : i;
+        i = i > P.gb_n[a] - 1 ? P.gb_n[a] - 1 : i;
+        idx[a] = i;
+    }
+    return (idx[0] * P.gb_n[1] + idx[1]) * P.gb_n[2] + idx[2];
+}
+
+// Point inside a closed box (grown by the margin): a collision.  The box is
+// stored as two float4: (lo x, lo y, lo z, -), (hi x, hi y, hi z, -).
+__device__ __forceinline__ bool in_box(const float4* b, float px, float py, float pz)
+{
+    const float4 lo = b[0], hi = b[1];
+    return (px >= lo.x) & (px <= hi.x) & (py >= lo.y) & (py <= hi.y) & (pz >= lo.z) & (pz <= hi.z);
 }
 
 // Region index: grid over the workspace (clamped), row-major (x, y, z), then

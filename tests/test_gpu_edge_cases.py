@@ -83,3 +83,25 @@ def test_dump_requires_recording(kpx):
         pl.read_dump()
     assert e.value.code == -6
     pl.close()
+
+
+def test_boxes_on_box_grid_faces_lockstep(kpx, ora):
+    """Box faces exactly on the planner's internal box-grid boundaries (multiples
+    of 1/16 of the workspace) and many overlapping boxes: the grid lookup must
+    agree with the oracle's test against every box."""
+    rng = np.random.default_rng(8)
+    boxes = []
+    while len(boxes) < 120:
+        lo = rng.integers(1, 14, size=3) / 16.0
+        ext = rng.integers(1, 3, size=3) / 16.0
+        b = np.concatenate([lo, lo + ext])
+        if np.all(b[:3] <= 0.1) or np.linalg.norm(np.clip([0.95] * 3, b[:3], b[3:]) - 0.95) < 0.08:
+            continue
+        boxes.append(b)
+    w = W.make_workload("di6", 7, n_select=300, samples=9, tree_cap=1 << 16, margin=0.0)
+    w.problem.boxes = np.asarray(boxes, np.float32)
+    P = ora.Problem(w.problem, w.params)
+    pl = kpx.Planner(w.problem, w.params)
+    rep = parity.lockstep(ora, P, pl, 25)
+    assert rep["iterations"] == 25 and rep["valid"] > 0
+    pl.close()
