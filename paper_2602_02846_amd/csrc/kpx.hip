@@ -39,9 +39,11 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kTile = kBlock;             // survivor slots per tile (one per thread)
 constexpr int kSelectThreads = 1024;
+constexpr int kSelWords = 8;            // activity words per select thread kept in registers
+constexpr int kSelLds = 8192;            // selections ranked in LDS (more go through global memory)
 constexpr int kSortBins = 64;             // step-count bins of the in-block sort
 constexpr int kBoxGridMax = 16;           // box-grid cells per workspace axis (at most)
-constexpr int kBoxGridBytes = 16 * 1024;  // LDS budget of the box grid and its lists
+constexpr int kBoxGridBytes = 48 * 1024;  // LDS budget of the box grid, its clearances and lists
 constexpr int kChunkMax = 1024;           // expansion slots per propagate chunk (at most)
 constexpr int kChunkMin = 64;
 constexpr int kParMax = 256;              // parent states staged per chunk (at most)
@@ -88,6 +90,7 @@ struct DevPtrs {
     uint8_t* act;        // region will be expanded next (owner active after this iteration)
     float4* boxes;       // 2 per box: lo, hi (grown by the margin)
     int* gcell;          // box grid: first list entry | count << 20, per grid cell
+    float* gclear;       // box grid: squared clearance radius per grid cell (see propagate)
     uint16_t* glist;     // box grid: box indices
     DevState* st;
     kpx_iter_stats* stats;
@@ -173,7 +176,7 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, const float* x_init)
     T.steps[0] = 0;
     T.parent[0] = -1;
     T.cost[0] = 0u;
-    const int c = cell_of(P, x);
+    const int c = cell_of(P, x, x + (DYN == kQUAD12 ? 6 : 3));
     T.cell[0] = c;
     T.status[0] = kActive;
     T.icount[0] = 0;
@@ -220,18 +223,24 @@ template <int DYN, int COST>
 __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
-    extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | grid lists
+    extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | clearances | grid lists
     __shared__ float s_u[M][kChunkMax];
     __shared__ unsigned short s_n[kChunkMax];
     __shared__ unsigned short s_order[kChunkMax];
     __shared__ short s_fi[kChunkMax];
     __shared__ float s_len[COST == kPATH ? kChunkMax : 1];
+    __shared__ float s_xe[6][kChunkMax];  // end position and velocity of valid slots
+    __shared__ int s_pid[kParMax];        // the chunk's parents: tree index
+    __shared__ uint32_t s_pcost[kParMax]; //                     cost field
+    constexpr int VI = DYN == kQUAD12 ? 6 : 3;  // first velocity component
     __shared__ int s_bin[kSortBins];
     __shared__ int s_next;
+    __shared__ float s_os[2][D];
     float4* sbox = dyn_lds;
     float* spx = reinterpret_cast<float*>(dyn_lds + 2 * P.n_boxes);
     int* sgc = reinterpret_cast<int*>(spx + D * kParMax);
-    uint16_t* sgl = reinterpret_cast<uint16_t*>(sgc + P.gb_cells);
+    float* sgr = reinterpret_cast<float*>(sgc + P.gb_cells);
+    uint16_t* sgl = reinterpret_cast<uint16_t*>(sgr + P.gb_cells);
 
     DevState* st = T.st;
     const int S = st->n_sel * P.K;
@@ -243,7 +252,14 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
     for (int i = threadIdx.x; i < 2 * P.n_boxes; i += blockDim.x) sbox[i] = T.boxes[i];
-    for (int i = threadIdx.x; i < P.gb_cells; i += blockDim.x) sgc[i] = T.gcell[i];
+    for (int i = threadIdx.x; i < P.gb_cells; i += blockDim.x) {
+        sgc[i] = T.gcell[i];
+        sgr[i] = T.gclear[i];
+    }
+    if (threadIdx.x < D) {
+        s_os[0][threadIdx.x] = P.os_lo[threadIdx.x];
+        s_os[1][threadIdx.x] = P.os_hi[threadIdx.x];
+    }
     for (int i = threadIdx.x; i < P.gb_entries; i += blockDim.x) sgl[i] = T.glist[i];
     const Hot<DYN> H = make_hot<DYN>(P);
     const int lane = threadIdx.x & 63;
@@ -253,15 +269,30 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
         const int cnt = min(chunk, S - base);
         const int r0 = base / P.K;
         const int npar = (base + cnt - 1) / P.K - r0 + 1;
-        __syncthreads();  // LDS of the previous chunk is free
+        // the sort bins and the queue head are free once the previous chunk
+        // has left its integration loop
         if (threadIdx.x < kSortBins) s_bin[threadIdx.x] = 0;
         if (threadIdx.x == 0) s_next = 0;
-        // 1. parents, samples, sort by step count (longest first)
-        for (int idx = threadIdx.x; idx < npar * D; idx += blockDim.x) {
-            const int j = idx % npar, k = idx / npar;
-            spx[k * kParMax + j] = T.x[(long long)k * P.cap + T.sel[r0 + j]];
+        __syncthreads();  // LDS of the previous chunk is free
+        // 1. parents (tree index, cost, state) into LDS, samples, sort by step
+        // count (longest first).  The parent loads are issued before the
+        // sampling so that their latency overlaps it.
+        constexpr int kStage = 4;
+        const int nstage = npar * D;
+        int prow[kStage];
+        float pv[kStage];
+#pragma unroll
+        for (int r = 0; r < kStage; ++r) {
+            const int idx = threadIdx.x + r * kBlock;
+            prow[r] = idx < nstage ? T.sel[r0 + idx % npar] : 0;
         }
-        __syncthreads();
+        const int my_pid = (int)threadIdx.x < npar ? T.sel[r0 + threadIdx.x] : 0;
+#pragma unroll
+        for (int r = 0; r < kStage; ++r) {
+            const int idx = threadIdx.x + r * kBlock;
+            pv[r] = idx < nstage ? T.x[(long long)(idx / npar) * P.cap + prow[r]] : 0.f;
+        }
+        const uint32_t my_pcost = (int)threadIdx.x < npar ? T.cost[my_pid] : 0u;
         int bins[kPerThread];
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
@@ -277,6 +308,17 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
                 bins[r] = (kSortBins - 1) - min(kSortBins - 1, (n - P.steps_min) >> P.sort_shift);
                 atomicAdd(&s_bin[bins[r]], 1);
             }
+        }
+#pragma unroll
+        for (int r = 0; r < kStage; ++r) {
+            const int idx = threadIdx.x + r * kBlock;
+            if (idx < nstage) spx[(idx / npar) * kParMax + idx % npar] = pv[r];
+        }
+        for (int idx = threadIdx.x + kStage * kBlock; idx < nstage; idx += kBlock)
+            spx[(idx / npar) * kParMax + idx % npar] = T.x[(long long)(idx / npar) * P.cap + T.sel[r0 + idx % npar]];
+        if ((int)threadIdx.x < npar) {
+            s_pid[threadIdx.x] = my_pid;
+            s_pcost[threadIdx.x] = my_pcost;
         }
         __syncthreads();
         if (threadIdx.x < 64) {  // exclusive prefix over the 64 bins in one wave
@@ -301,6 +343,9 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
         float len = 0.f;
         int li = -1, n = 0, k = 0;
         int gcur = -1, gstart = 0, gcount = 0;
+        // safe ball: no box is within sqrt(r2) of (rx, ry, rz), the last
+        // position whose grid cell was looked up
+        float rx = 0.f, ry = 0.f, rz = 0.f, r2 = -1.f;
         bool drained = false;
         while (true) {
             const bool want = li < 0 && !drained;
@@ -317,12 +362,13 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
                         n = s_n[li];
                         const int pj = (base + li) / P.K - r0;
 #pragma unroll
-                        for (int c = 0; c < M; ++c) u[c] = s_u[c][li];
+                        for (int c = 0; c < M; ++c) u[c] = s_u[c][li] * (rev_control(DYN, c) ? kInv2Pi : 1.f);
 #pragma unroll
-                        for (int c = 0; c < D; ++c) x[c] = spx[c * kParMax + pj];
+                        for (int c = 0; c < D; ++c) x[c] = spx[c * kParMax + pj] * (rev_state(DYN, c) ? kInv2Pi : 1.f);
                         k = 0;
                         len = 0.f;
                         gcur = -1;
+                        r2 = -1.f;
                     } else {
                         drained = true;
                     }
@@ -332,8 +378,9 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
             if (li >= 0) {
                 rk4<DYN, COST>(H, x, u, len);
                 ++k;
-                bool ok = in_bounds<DYN>(H, x);
-                if (ok) {
+                bool ok = in_bounds<DYN>(H, x, s_os[0], s_os[1]);
+                const float dx = x[0] - rx, dy = x[1] - ry, dz = x[2] - rz;
+                if (ok && __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)) >= r2) {
                     const int g = box_grid_cell(H, x);
                     if (g != gcur) {
                         const int e = sgc[g];
@@ -346,13 +393,23 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
                             ok = false;
                             break;
                         }
+                    rx = x[0];
+                    ry = x[1];
+                    rz = x[2];
+                    r2 = sgr[g];
                 }
                 if (!ok || k == n) {
                     s_fi[li] = (short)(ok ? 0 : k);
                     if (ok) {
                         if constexpr (COST == kPATH) s_len[li] = len;
 #pragma unroll
-                        for (int c = 0; c < D; ++c) T.cx[(long long)c * P.s_max + base + li] = x[c];
+                        for (int a = 0; a < 3; ++a) {
+                            s_xe[a][li] = x[a];
+                            s_xe[3 + a][li] = x[VI + a];
+                        }
+#pragma unroll
+                        for (int c = 0; c < D; ++c)
+                            T.cx[(long long)c * P.s_max + base + li] = x[c] * (rev_state(DYN, c) ? k2Pi : 1.f);
                     }
                     li = -1;
                 }
@@ -368,19 +425,19 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
             const int s = base + lj;
             const int fi = s_fi[lj];
             const int nn = s_n[lj];
-            const int parent = T.sel[s / P.K];
+            const int pj = s / P.K - r0;
+            const int parent = s_pid[pj];
             my_steps += fi ? fi : nn;
             if (fi == 0) {
                 ++my_valid;
-                float xe[D];
-#pragma unroll
-                for (int c = 0; c < D; ++c) xe[c] = T.cx[(long long)c * P.s_max + s];
-                const int c = cell_of(P, xe);
+                const float pe[3] = {s_xe[0][lj], s_xe[1][lj], s_xe[2][lj]};
+                const float ve[3] = {s_xe[3][lj], s_xe[4][lj], s_xe[5][lj]};
+                const int c = cell_of(P, pe, ve);
                 uint32_t cf;
                 if constexpr (COST == kTIME) {
-                    cf = T.cost[parent] + (uint32_t)nn;
+                    cf = s_pcost[pj] + (uint32_t)nn;
                 } else {
-                    cf = __float_as_uint(__uint_as_float(T.cost[parent]) + s_len[lj]);
+                    cf = __float_as_uint(__uint_as_float(s_pcost[pj]) + s_len[lj]);
                 }
                 const unsigned long long key =
                     ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)(n_tree + s);
@@ -393,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
                 }
                 T.ckey[s] = key;
                 T.ccell[s] = c;
-                T.cflag[s] = (uint8_t)(1 | (in_goal(P, xe) ? 2 : 0));
+                T.cflag[s] = (uint8_t)(1 | (in_goal(P, pe) ? 2 : 0));
             } else {
                 T.ckey[s] = kEmpty;
                 T.ccell[s] = -1;
@@ -487,14 +544,43 @@ __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T,
 
 // ------------------------------------------------------------------ finalize + select (one block)
 
+// The finalize/select workgroup issues every load it needs before its first
+// barrier (device state, survivor tile counts, the activity words it owns), so
+// that one memory round trip covers them; the owners of the selected regions
+// are then gathered in one more.
+struct SelectLoads {
+    int tile0;                  // tile_count[threadIdx.x] (0 past n_tiles)
+    int per, w0, w1;            // activity words [w0, w1) of this thread
+    uint32_t wd[kSelWords];     // their values, when per <= kSelWords
+};
+
+__device__ __forceinline__ void select_issue_loads(const DevProblem& P, const DevPtrs& T, SelectLoads& L)
+{
+    // unconditional loads from clamped (always valid) addresses, masked after,
+    // so that none of them waits for another
+    const int t0 = T.tile_count[min((int)threadIdx.x, P.n_tiles - 1)];
+    const int nwords = (P.n_cells + 3) >> 2;
+    L.per = (nwords + (int)blockDim.x - 1) / (int)blockDim.x;
+    L.w0 = min((int)threadIdx.x * L.per, nwords);
+    L.w1 = min(L.w0 + L.per, nwords);
+    const uint32_t* act = reinterpret_cast<const uint32_t*>(T.act);
+    uint32_t raw[kSelWords];
+#pragma unroll
+    for (int i = 0; i < kSelWords; ++i) raw[i] = act[min(L.w0 + i, nwords - 1)];
+    L.tile0 = (int)threadIdx.x < P.n_tiles ? t0 : 0;
+#pragma unroll
+    for (int i = 0; i < kSelWords; ++i) L.wd[i] = L.w0 + i < L.w1 ? raw[i] : 0u;
+}
+
 // Finishes an iteration: counters, statistics, capacity check.  Runs in one
 // block on the state copy in LDS.
-__device__ void finalize_iteration(const DevProblem& P, const DevPtrs& T, DevState& q, int* lds)
+__device__ void finalize_iteration(const DevProblem& P, const DevPtrs& T, DevState& q,
+                                   const SelectLoads& L, int* lds)
 {
     const int S = q.n_sel * P.K;
     const int tiles = (S + kTile - 1) / kTile;
-    int v = 0;
-    for (int j = threadIdx.x; j < tiles; j += blockDim.x) v += T.tile_count[j];
+    int v = (int)threadIdx.x < tiles ? L.tile0 : 0;
+    for (int j = threadIdx.x + blockDim.x; j < tiles; j += blockDim.x) v += T.tile_count[j];
     const int n_surv = block_sum(v, lds);
     if (threadIdx.x == 0) {
         const long long it = q.it;
@@ -524,11 +610,45 @@ __device__ void finalize_iteration(const DevProblem& P, const DevPtrs& T, DevSta
     __syncthreads();
 }
 
+// Active regions (0/1 bytes) in activity word `wd` at byte offset c0, split at
+// the cursor into those at or after it (hi) and before it (lo).
+__device__ __forceinline__ void count_word(uint32_t wd, int c0, int cur, int& hi, int& lo)
+{
+    wd &= 0x01010101u;
+    const int k = min(max(cur - c0, 0), 4);  // bytes of this word before the cursor
+    const uint32_t below = k == 4 ? ~0u : (1u << (8 * k)) - 1u;
+    lo += __popc(wd & below);
+    hi += __popc(wd & ~below);
+}
+
+// Gives each active region in word `wd` its rank in the rotated order; ranks
+// below nsel are recorded (region index) in LDS or, past kSelLds, in sel.
+__device__ __forceinline__ void rank_word(uint32_t wd, int c0, int cur, int nsel, int nc, int& r_hi,
+                                          int& r_lo, int* s_sel, int* sel, DevState& q)
+{
+    wd &= 0x01010101u;
+    while (wd) {
+        const int bit = __ffs(wd) - 1;
+        wd &= wd - 1;
+        const int c = c0 + (bit >> 3);
+        const bool at_or_after = c >= cur;
+        const int rank = at_or_after ? r_hi : r_lo;
+        r_hi += at_or_after;
+        r_lo += !at_or_after;
+        if (rank < nsel) {
+            if (nsel <= kSelLds) s_sel[rank] = c;
+            else sel[rank] = c;
+            if (rank == nsel - 1) q.cursor_next = (c + 1 == nc) ? 0 : c + 1;
+        }
+    }
+}
+
 // Selects the next iteration's nodes: regions whose owner is active, in
 // region order rotated to start at the cursor, at most n_select.  One block;
 // each thread owns a run of whole 4-region words of the activity bytes (0/1,
 // zero-padded past the last region).
-__device__ void select_nodes(const DevProblem& P, const DevPtrs& T, DevState& q, int* lds)
+__device__ void select_nodes(const DevProblem& P, const DevPtrs& T, DevState& q, const SelectLoads& L,
+                             int* lds, int* s_sel)
 {
     if (q.full) {
         if (threadIdx.x == 0) q.n_sel = 0;
@@ -537,45 +657,45 @@ __device__ void select_nodes(const DevProblem& P, const DevPtrs& T, DevState& q,
     }
     const int nc = P.n_cells;
     const int cur = q.cursor;
-    const int nwords = (nc + 3) >> 2;
-    const int per = (nwords + blockDim.x - 1) / blockDim.x;
-    const int w0 = threadIdx.x * per;
-    const int w1 = min(w0 + per, nwords);
     const uint32_t* act = reinterpret_cast<const uint32_t*>(T.act);
+    const bool in_regs = L.per <= kSelWords;
     int hi = 0, lo = 0;
-    for (int w = w0; w < w1; ++w) {
-        uint32_t wd = act[w] & 0x01010101u;
-        const int c0 = 4 * w;
-        if (c0 >= cur) {
-            hi += __popc(wd);
-        } else if (c0 + 4 <= cur) {
-            lo += __popc(wd);
-        } else {  // the cursor falls inside this word
-            const uint32_t below = (1u << (8 * (cur - c0))) - 1u;
-            lo += __popc(wd & below);
-            hi += __popc(wd & ~below);
-        }
+    if (in_regs) {
+#pragma unroll
+        for (int i = 0; i < kSelWords; ++i) count_word(L.wd[i], 4 * (L.w0 + i), cur, hi, lo);
+    } else {
+        for (int w = L.w0; w < L.w1; ++w) count_word(act[w], 4 * w, cur, hi, lo);
     }
     int total_hi, total_lo;
     const int ex_hi = block_exclusive_scan(hi, lds, &total_hi);
     const int ex_lo = block_exclusive_scan(lo, lds, &total_lo);
     const int nsel = min(total_hi + total_lo, P.n_select);
     int r_hi = ex_hi, r_lo = total_hi + ex_lo;
-    for (int w = w0; w < w1; ++w) {
-        uint32_t wd = act[w] & 0x01010101u;
-        while (wd) {
-            const int bit = __ffs(wd) - 1;
-            wd &= wd - 1;
-            const int c = 4 * w + (bit >> 3);
-            const int rank = c >= cur ? r_hi++ : r_lo++;
-            if (rank < nsel) {
-                T.sel[rank] = c;  // region for now; owner filled in below
-                if (rank == nsel - 1) q.cursor_next = (c + 1 == nc) ? 0 : c + 1;
-            }
-        }
+    if (in_regs) {
+#pragma unroll
+        for (int i = 0; i < kSelWords; ++i)
+            rank_word(L.wd[i], 4 * (L.w0 + i), cur, nsel, nc, r_hi, r_lo, s_sel, T.sel, q);
+    } else {
+        for (int w = L.w0; w < L.w1; ++w) rank_word(act[w], 4 * w, cur, nsel, nc, r_hi, r_lo, s_sel, T.sel, q);
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < nsel; r += blockDim.x) T.sel[r] = (int)(uint32_t)T.tbl[T.sel[r]];
+    // owners: the low word of each selected region's key; four loads in flight per thread
+    const uint32_t* tbl_lo = reinterpret_cast<const uint32_t*>(T.tbl);
+    const int bd = blockDim.x;
+    for (int r0 = threadIdx.x; r0 < nsel; r0 += 4 * bd) {
+        int c[4];
+        uint32_t o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = r0 + k * bd;
+            c[k] = r < nsel ? (nsel <= kSelLds ? s_sel[r] : T.sel[r]) : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = c[k] >= 0 ? tbl_lo[2 * (size_t)c[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c[k] >= 0) T.sel[r0 + k * bd] = (int)o[k];
+    }
     if (threadIdx.x == 0) {
         q.n_sel = nsel;
         if (nsel == 0) q.cursor_next = cur;
@@ -587,10 +707,13 @@ __device__ void select_nodes(const DevProblem& P, const DevPtrs& T, DevState& q,
 __global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs T)
 {
     __shared__ int lds[kSelectThreads / 64 + 1];
+    __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
+    SelectLoads L;
+    select_issue_loads(P, T, L);
     if (threadIdx.x == 0) s_st = *T.st;
     __syncthreads();
-    select_nodes(P, T, s_st, lds);
+    select_nodes(P, T, s_st, L, lds, s_sel);
     if (threadIdx.x == 0) *T.st = s_st;
 }
 
@@ -651,11 +774,14 @@ __global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
 __global__ __launch_bounds__(kSelectThreads) void k_finalize_select(DevProblem P, DevPtrs T)
 {
     __shared__ int lds[kSelectThreads / 64 + 1];
+    __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
+    SelectLoads L;
+    select_issue_loads(P, T, L);
     if (threadIdx.x == 0) s_st = *T.st;
     __syncthreads();
-    if (!s_st.full) finalize_iteration(P, T, s_st, lds);
-    select_nodes(P, T, s_st, lds);
+    if (!s_st.full) finalize_iteration(P, T, s_st, L, lds);
+    select_nodes(P, T, s_st, L, lds, s_sel);
     if (threadIdx.x == 0) *T.st = s_st;
 }
 
@@ -748,6 +874,7 @@ void for_each_array(const Sizes& z, F&& f)
     f("act", (size_t)z.n_act);
     f("boxes", sizeof(float4) * 2 * (size_t)(z.n_boxes > 0 ? z.n_boxes : 1));
     f("gcell", sizeof(int) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2]);
+    f("gclear", sizeof(float) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2]);
     f("glist", sizeof(uint16_t) * (size_t)(z.gb_entries > 0 ? z.gb_entries : 1));
     f("st", sizeof(DevState));
     f("stats", sizeof(kpx_iter_stats) * kStatsCap);
@@ -767,13 +894,65 @@ bool finite(float v) { return std::isfinite(v); }
 
 // Box grid: a uniform G^3 grid over the workspace; each grid cell lists the
 // boxes (grown by the margin) that overlap it, grown by a small slack so that
-// rounding in the device's float32 cell index can never miss a box.  G is the
-// finest resolution whose cells and lists fit the LDS budget.
+// rounding in the device's float32 cell index can never miss a box.  Each cell
+// also carries a clearance: a lower bound on the distance from any point of
+// the (slack-grown) cell to any box, so that a point p whose cell was looked
+// up has every box farther than that from it, and any later point within the
+// clearance of p needs no box test.  G is the finest resolution whose cells,
+// clearances and lists fit the LDS budget.
 struct BoxGrid {
     int n[3];
     std::vector<int> cells;  // first entry | count << 20
+    std::vector<float> clear2;  // squared clearance, rounded down
     std::vector<uint16_t> list;
 };
+
+// Squared clearance of every cell: the distance between the slack-grown cell
+// and the nearest margin-grown box (double), shrunk by a relative 1e-5 and an
+// absolute 1e-6 of the workspace extent (so that float32 rounding of the
+// device's squared distance cannot make it optimistic), then squared and
+// rounded down to float (the absolute part scales with the largest workspace
+// coordinate, since float32 positions carry errors of that order).  Cells that
+// touch a box get 0; without boxes, FLT_MAX.
+void box_grid_clearance(const kpx_problem* p, BoxGrid* g)
+{
+    const int G0 = g->n[0], G1 = g->n[1], G2 = g->n[2];
+    g->clear2.assign((size_t)G0 * G1 * G2, 3.4028234663852886e38f);
+    if (p->n_boxes == 0) return;
+    double wmax = 0.0, lo[3], step[3], slack[3];
+    for (int a = 0; a < 3; ++a) {
+        const double w = (double)p->ws_hi[a] - p->ws_lo[a];
+        wmax = std::max({wmax, w, std::fabs((double)p->ws_lo[a]), std::fabs((double)p->ws_hi[a])});
+        lo[a] = p->ws_lo[a];
+        step[a] = w / g->n[a];
+        slack[a] = 1e-4 * w;
+    }
+    for (int i = 0; i < G0; ++i)
+        for (int j = 0; j < G1; ++j)
+            for (int k = 0; k < G2; ++k) {
+                const int id[3] = {i, j, k};
+                double best = INFINITY;
+                for (int b = 0; b < p->n_boxes; ++b) {
+                    double d2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        const double c0 = lo[a] + id[a] * step[a] - slack[a];
+                        const double c1 = lo[a] + (id[a] + 1) * step[a] + slack[a];
+                        const double b0 = (double)p->boxes[6 * b + a] - p->margin;
+                        const double b1 = (double)p->boxes[6 * b + 3 + a] + p->margin;
+                        const double gap = std::max(0.0, std::max(b0 - c1, c0 - b1));
+                        d2 += gap * gap;
+                    }
+                    best = std::min(best, d2);
+                }
+                double r = std::sqrt(best) * (1.0 - 1e-5) - 1e-6 * wmax;
+                float r2 = 0.f;
+                if (r > 0.0) {
+                    r2 = (float)(r * r);
+                    if ((double)r2 > r * r) r2 = std::nextafter(r2, 0.f);
+                }
+                g->clear2[((size_t)i * G1 + j) * G2 + k] = r2;
+            }
+}
 
 void build_box_grid_at(const kpx_problem* p, int G, BoxGrid* g)
 {
@@ -805,19 +984,20 @@ void build_box_grid_at(const kpx_problem* p, int G, BoxGrid* g)
 
 size_t box_grid_bytes(const BoxGrid& g)
 {
-    return sizeof(int) * g.cells.size() + sizeof(uint16_t) * g.list.size();
+    return (sizeof(int) + sizeof(float)) * g.cells.size() + sizeof(uint16_t) * g.list.size();
 }
 
 void build_box_grid(const kpx_problem* p, BoxGrid* g)
 {
     if (p->n_boxes == 0) {
         build_box_grid_at(p, 1, g);
-        return;
+    } else {
+        for (int G = kBoxGridMax; G >= 1; --G) {
+            build_box_grid_at(p, G, g);
+            if (box_grid_bytes(*g) <= (size_t)kBoxGridBytes || G == 1) break;
+        }
     }
-    for (int G = kBoxGridMax; G >= 1; --G) {
-        build_box_grid_at(p, G, g);
-        if (box_grid_bytes(*g) <= (size_t)kBoxGridBytes || G == 1) return;
-    }
+    box_grid_clearance(p, g);
 }
 
 // Host-side validation of Problem 1 and the parameters; no GPU call.
@@ -940,6 +1120,34 @@ DevProblem make_dev_problem(const kpx_problem* p, const kpx_params* q, const Siz
     P.bound_mask = 0;
     for (int i = 0; i < z.d; ++i)
         if (std::isfinite(p->x_lo[i]) || std::isfinite(p->x_hi[i])) P.bound_mask |= 1u << i;
+    // the bound test in integration units: planning bounds (the workspace
+    // folded into the position bounds), angular components in revolutions
+    P.os_mask = 0;
+    for (int i = 0; i < KPX_MAX_STATE; ++i) {
+        P.bnd_s[i] = 0.f;
+        P.bnd_o[i] = 0.f;
+        P.os_lo[i] = -INFINITY;
+        P.os_hi[i] = INFINITY;
+        if (i >= z.d) continue;
+        double lo = P.x_lo[i], hi = P.x_hi[i];
+        if (i < 3) {
+            lo = std::max(lo, (double)P.ws_lo[i]);
+            hi = std::min(hi, (double)P.ws_hi[i]);
+        }
+        if (rev_state(p->dynamics, i)) {
+            lo *= 0.15915494309189535;
+            hi *= 0.15915494309189535;
+        }
+        if (std::isfinite(lo) && std::isfinite(hi) && hi > lo) {
+            P.bnd_s[i] = (float)(2.0 / (hi - lo));
+            P.bnd_o[i] = (float)(-(hi + lo) / (hi - lo));
+        } else if (std::isfinite(lo) || std::isfinite(hi)) {
+            // one finite bound, or an interval of at most one point: direct test
+            P.os_mask |= 1u << i;
+            P.os_lo[i] = (float)lo;
+            P.os_hi[i] = (float)hi;
+        }
+    }
     P.n_boxes = p->n_boxes;
     for (int a = 0; a < 3; ++a) {
         P.gb_lo[a] = p->ws_lo[a];
@@ -1053,6 +1261,7 @@ void carve(kpx_handle* h)
     T.act = (uint8_t*)ptrs[k++];
     T.boxes = (float4*)ptrs[k++];
     T.gcell = (int*)ptrs[k++];
+    T.gclear = (float*)ptrs[k++];
     T.glist = (uint16_t*)ptrs[k++];
     T.st = (DevState*)ptrs[k++];
     T.stats = (kpx_iter_stats*)ptrs[k++];
@@ -1090,7 +1299,7 @@ DevPtrs kernel_ptrs(const kpx_handle* h)
 size_t propagate_lds_bytes(const Sizes& z, int d)
 {
     return sizeof(float4) * 2 * (size_t)z.n_boxes + sizeof(float) * (size_t)d * kParMax +
-           sizeof(int) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2] +
+           (sizeof(int) + sizeof(float)) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2] +
            sizeof(uint16_t) * (size_t)z.gb_entries;
 }
 
@@ -1262,6 +1471,9 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
                        h->stream) != hipSuccess)
         return cleanup(KPX_ERR_DEVICE);
     if (hipMemcpyAsync(h->T.gcell, grid.cells.data(), sizeof(int) * grid.cells.size(),
+                       hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return cleanup(KPX_ERR_DEVICE);
+    if (hipMemcpyAsync(h->T.gclear, grid.clear2.data(), sizeof(float) * grid.clear2.size(),
                        hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return cleanup(KPX_ERR_DEVICE);
     if (!grid.list.empty() &&

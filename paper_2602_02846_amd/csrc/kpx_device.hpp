@@ -35,6 +35,26 @@ struct Dims<kDUBINS6> {
     static constexpr int D = 6, M = 3;
 };
 
+// The integration loop keeps angles and angular rates in revolutions
+// (radians / 2 pi): the hardware sine and cosine take revolutions, so no
+// per-evaluation rescaling is needed, and the kinematic equations are
+// homogeneous in (angle, rate) so they keep their form.  Components so scaled,
+// and the controls that are angular rates or feed one:
+//   QUAD12  angles 3-5, body rates 9-11; torques 1-3 (the gyroscopic
+//           coefficients are multiplied by 2 pi to compensate)
+//   DUBINS6 heading 3, flight-path angle 4; their rates, controls 0-1
+constexpr float kInv2Pi = 0.15915494309189535f;
+constexpr float k2Pi = 6.283185307179586f;
+
+__host__ __device__ constexpr bool rev_state(int dyn, int i)
+{
+    return dyn == kQUAD12 ? ((i >= 3 && i <= 5) || i >= 9) : dyn == kDUBINS6 ? (i == 3 || i == 4) : false;
+}
+__host__ __device__ constexpr bool rev_control(int dyn, int i)
+{
+    return dyn == kQUAD12 ? (i >= 1) : dyn == kDUBINS6 ? (i <= 1) : false;
+}
+
 // Problem constants in the form the kernels use them (prepared on the host in
 // float32): planning bounds already shrunk by the clearance margin, boxes grown
 // by it, region scales and reciprocal inertias precomputed.
@@ -51,6 +71,13 @@ struct DevProblem {
     float goal_c[3], goal_r2;      // (goal radius - margin)^2
     float inv_mass, inv_j[3], gyro[3], grav;
     uint32_t bound_mask;           // bit i: component i has a finite bound
+    // the bound test in integration units (angles and angular rates in
+    // revolutions): component i is in bounds iff |fma(x_i, bnd_s[i], bnd_o[i])| <= 1;
+    // (0, 0) for unbounded components and for those with one finite bound,
+    // which are listed in os_mask and tested against os_lo / os_hi directly
+    float bnd_s[12], bnd_o[12];
+    uint32_t os_mask;
+    float os_lo[12], os_hi[12];
     int n_boxes;
     // uniform grid over the workspace listing, per grid cell, the (grown)
     // boxes that overlap it: a point is only tested against its cell's list
@@ -122,8 +149,9 @@ template <int DYN>
 struct Hot {
     static constexpr int D = Dims<DYN>::D;
     float dt, h2, h6;
-    float lo[D], hi[D];
-    float inv_mass, inv_j[3], gyro[3], grav;
+    float bs[D], bo[D];            // scaled bound test (see DevProblem)
+    uint32_t os_mask;
+    float inv_mass, inv_j[3], gyro[3], grav;   // gyro in revolution units
     float gb_lo[3], gb_scale[3];
     int gb_n[3];
 };
@@ -138,20 +166,21 @@ __device__ __forceinline__ Hot<DYN> make_hot(const DevProblem& P)
     H.h6 = P.h6;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        H.lo[i] = i < 3 ? __builtin_fmaxf(P.x_lo[i], P.ws_lo[i]) : P.x_lo[i];
-        H.hi[i] = i < 3 ? __builtin_fminf(P.x_hi[i], P.ws_hi[i]) : P.x_hi[i];
-        // keep the bounds in vector registers: the loop compares against them
+        H.bs[i] = P.bnd_s[i];
+        H.bo[i] = P.bnd_o[i];
+        // keep the bound coefficients in vector registers: the loop uses them
         // every substep and scalar registers are short
-        asm volatile("" : "+v"(H.lo[i]));
-        asm volatile("" : "+v"(H.hi[i]));
+        asm volatile("" : "+v"(H.bs[i]));
+        asm volatile("" : "+v"(H.bo[i]));
     }
+    H.os_mask = P.os_mask;
     H.inv_mass = P.inv_mass;
     H.grav = P.grav;
     asm volatile("" : "+v"(H.dt), "+v"(H.h2), "+v"(H.h6), "+v"(H.inv_mass), "+v"(H.grav));
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         H.inv_j[a] = P.inv_j[a];
-        H.gyro[a] = P.gyro[a];
+        H.gyro[a] = P.gyro[a] * k2Pi;
         H.gb_lo[a] = P.gb_lo[a];
         H.gb_scale[a] = P.gb_scale[a];
         H.gb_n[a] = P.gb_n[a];
@@ -173,9 +202,10 @@ __device__ __forceinline__ void deriv(const Hot<DYN>& P, const float* x, const f
         xd[3] = u[0]; xd[4] = u[1]; xd[5] = u[2];
         if constexpr (COST == kPATH) ld = __builtin_sqrtf(x[3] * x[3] + x[4] * x[4] + x[5] * x[5]);
     } else if constexpr (DYN == kQUAD12) {
-        const float sph = __sinf(x[3]), cph = __cosf(x[3]);
-        const float sth = __sinf(x[4]), cth = __cosf(x[4]);
-        const float sps = __sinf(x[5]), cps = __cosf(x[5]);
+        // x[3..5] in revolutions
+        const float sph = __builtin_amdgcn_sinf(x[3]), cph = __builtin_amdgcn_cosf(x[3]);
+        const float sth = __builtin_amdgcn_sinf(x[4]), cth = __builtin_amdgcn_cosf(x[4]);
+        const float sps = __builtin_amdgcn_sinf(x[5]), cps = __builtin_amdgcn_cosf(x[5]);
         const float rc = __builtin_amdgcn_rcpf(cth);
         const float wp = x[9], wq = x[10], wr = x[11];
         const float a = sph * wq + cph * wr;
@@ -193,11 +223,12 @@ __device__ __forceinline__ void deriv(const Hot<DYN>& P, const float* x, const f
         xd[11] = (u[3] - P.gyro[2] * wp * wq) * P.inv_j[2];
         if constexpr (COST == kPATH) ld = __builtin_sqrtf(x[6] * x[6] + x[7] * x[7] + x[8] * x[8]);
     } else {
-        const float cg = __cosf(x[4]), sg = __sinf(x[4]);
+        // x[3], x[4] in revolutions
+        const float cg = __builtin_amdgcn_cosf(x[4]), sg = __builtin_amdgcn_sinf(x[4]);
         const float v = x[5];
         const float vc = v * cg;
-        xd[0] = vc * __cosf(x[3]);
-        xd[1] = vc * __sinf(x[3]);
+        xd[0] = vc * __builtin_amdgcn_cosf(x[3]);
+        xd[1] = vc * __builtin_amdgcn_sinf(x[3]);
         xd[2] = v * sg;
         xd[3] = u[0]; xd[4] = u[1]; xd[5] = u[2];
         if constexpr (COST == kPATH) ld = v;
@@ -238,15 +269,28 @@ __device__ __forceinline__ void rk4(const Hot<DYN>& P, float* x, const float* u,
     if constexpr (COST == kPATH) len = __builtin_fmaf(P.h6, lacc + lk, len);
 }
 
-// Workspace and state bounds (closed; unbounded components compare against
-// +-inf and always pass).
+// Workspace and state bounds (closed).  Each two-sided bound is an affine map
+// onto [-1, 1]; the squares of the mapped values are compared as unsigned
+// integers (order-preserving for non-negative floats), so one three-way
+// integer max folds two components and a NaN (bits above those of 1.0)
+// fails.  Components with one finite bound (rare) are compared directly.
 template <int DYN>
-__device__ __forceinline__ bool in_bounds(const Hot<DYN>& H, const float* x)
+__device__ __forceinline__ bool in_bounds(const Hot<DYN>& H, const float* x, const float* os_lo,
+                                          const float* os_hi)
 {
     constexpr int D = Dims<DYN>::D;
-    bool ok = true;
+    uint32_t m = 0;
 #pragma unroll
-    for (int i = 0; i < D; ++i) ok &= (x[i] >= H.lo[i]) & (x[i] <= H.hi[i]);
+    for (int i = 0; i < D; ++i) {
+        const float t = __builtin_fmaf(x[i], H.bs[i], H.bo[i]);
+        m = max(m, __float_as_uint(t * t));
+    }
+    bool ok = m <= 0x3F800000u;
+    if (H.os_mask) {  // uniform
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            if (H.os_mask & (1u << i)) ok &= (x[i] >= os_lo[i]) & (x[i] <= os_hi[i]);
+    }
     return ok;
 }
 
@@ -274,22 +318,20 @@ __device__ __forceinline__ bool in_box(const float4* b, float px, float py, floa
 }
 
 // Region index: grid over the workspace (clamped), row-major (x, y, z), then
-// optionally three velocity-sign bits (velocity >= 0).
-__device__ __forceinline__ int cell_of(const DevProblem& P, const float* x)
+// optionally three velocity-sign bits (velocity >= 0); p is the position and
+// v the velocity.
+__device__ __forceinline__ int cell_of(const DevProblem& P, const float* p, const float* v)
 {
     int idx[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int i = (int)__builtin_floorf((x[a] - P.cell_lo[a]) * P.cell_scale[a]);
+        int i = (int)__builtin_floorf((p[a] - P.cell_lo[a]) * P.cell_scale[a]);
         i = i < 0 ? 0 : i;
         i = i > P.grid[a] - 1 ? P.grid[a] - 1 : i;
         idx[a] = i;
     }
     int c = (idx[0] * P.grid[1] + idx[1]) * P.grid[2] + idx[2];
-    if (P.vel_sign_bins) {
-        const int v = P.vel_idx;
-        c = c * 8 + ((x[v] >= 0.f) << 2) + ((x[v + 1] >= 0.f) << 1) + (x[v + 2] >= 0.f);
-    }
+    if (P.vel_sign_bins) c = c * 8 + ((v[0] >= 0.f) << 2) + ((v[1] >= 0.f) << 1) + (v[2] >= 0.f);
     return c;
 }
 
