@@ -38,6 +38,34 @@ FLOPS_PER_SUBSTEP = {
 }
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 FLOP/clk)
 PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2602_02846_amd/csrc/kpx.hip", "paper_2602_02846_amd/csrc/kpx_device.hpp")
+
+
+def measured_traffic(workload):
+    """HBM bytes per propagate launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy), or
+    None when there is none or the kernel sources changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"propagate_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            k, sep, v = line.partition(":")
+            if sep:
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    try:
+        return int(fields["propagate_hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -121,7 +149,7 @@ def main():
             achieved = fl / avg_s / 1e12
             roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                        "traffic": None}
+                        "traffic": measured_traffic(a.workload)}
 
     # time to first solution and cost, from device timestamps of this query
     it_done = int(c1["iteration"])

@@ -47,7 +47,8 @@ constexpr int kBoxGridBytes = 48 * 1024;  // LDS budget of the box grid, its cle
 constexpr int kChunkMax = 1024;           // expansion slots per propagate chunk (at most)
 constexpr int kChunkMin = 64;
 constexpr int kParMax = 256;              // parent states staged per chunk (at most)
-constexpr int kPerThread = kChunkMax / kBlock;
+constexpr int kPropBlock = 256;           // propagate: one wave per SIMD, one block per CU
+constexpr int kPerThread = kChunkMax / kPropBlock;
 constexpr int kStatsCap = 1 << 16;
 constexpr int kMaxPath = 1 << 16;
 
@@ -89,8 +90,8 @@ struct DevPtrs {
     int* tile_count;
     uint8_t* act;        // region will be expanded next (owner active after this iteration)
     float4* boxes;       // 2 per box: lo, hi (grown by the margin)
-    int* gcell;          // box grid: first list entry | count << 20, per grid cell
-    float* gclear;       // box grid: squared clearance radius per grid cell (see propagate)
+    int2* gcell;         // box grid, per grid cell: (first list entry | count << 20,
+                         // bits of the clearance radius to the boxes not listed)
     uint16_t* glist;     // box grid: box indices
     DevState* st;
     kpx_iter_stats* stats;
@@ -204,29 +205,40 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, const float* x_init)
 
 // ------------------------------------------------------------------ propagate
 
-// Alg. 2 / Alg. 6: slot s = r * K + j expands the r-th selected node with the
-// j-th sample.  Integration stops at the first invalid substep.
-//
-// Most expansions end within a few substeps (an invalid state) while a few
-// run their whole duration, and a wave runs as long as its busiest lane.  So
-// each block (one per compute unit) takes chunks of slots and works through
-// each chunk as a queue:
-//   1. draw the chunk's samples, sort them by step count (longest first, a
-//      counting sort in LDS) and stage the chunk's parent states in LDS;
-//   2. every lane integrates one slot at a time and, when it finishes, takes
-//      the next slot of the queue (one LDS atomic per wave and refill);
-//   3. all lanes together bin the end states, take region minima and store.
-// The obstacle boxes and a uniform grid listing the boxes near each grid cell
-// live in LDS, so a substep touches no global memory.  Which lane integrates
-// which slot changes no result.
+// Copies three arrays of 16-byte words from global memory into LDS, each
+// thread issuing all of its loads (from clamped, always valid addresses)
+// before its first store, so that one memory round trip covers the copy.
+__device__ __forceinline__ void stage_lds(const int4* s0, int4* d0, int n0, const int4* s1, int4* d1, int n1,
+                                          const int4* s2, int4* d2, int n2)
+{
+    constexpr int U = 8;
+    const int e0 = n0, e1 = e0 + n1, e2 = e1 + n2;
+    if (e2 == 0) return;
+    for (int b = 0; b < e2; b += U * (int)blockDim.x) {
+        int4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = min(b + (int)threadIdx.x + u * (int)blockDim.x, e2 - 1);
+            const int4* src = i < e0 ? s0 + i : i < e1 ? s1 + (i - e0) : s2 + (i - e1);
+            v[u] = *src;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = b + (int)threadIdx.x + u * (int)blockDim.x;
+            int4* dst = i < e0 ? d0 + i : i < e1 ? d1 + (i - e0) : d2 + (i - e1);
+            if (i < e2) *dst = v[u];
+        }
+    }
+}
+
 template <int DYN, int COST>
-__global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
+__global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs T)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
-    extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | clearances | grid lists
+    extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | grid lists
     __shared__ float s_u[M][kChunkMax];
     __shared__ unsigned short s_n[kChunkMax];
-    __shared__ unsigned short s_order[kChunkMax];
+    __shared__ uint32_t s_order[kChunkMax];  // slot in chunk | parent row << 16
     __shared__ short s_fi[kChunkMax];
     __shared__ float s_len[COST == kPATH ? kChunkMax : 1];
     __shared__ float s_xe[6][kChunkMax];  // end position and velocity of valid slots
@@ -236,12 +248,17 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
     __shared__ int s_bin[kSortBins];
     __shared__ int s_next;
     __shared__ float s_os[2][D];
+    const int gbp = (P.gb_cells + 1) & ~1;  // grid cells, padded to whole 16-byte words
     float4* sbox = dyn_lds;
     float* spx = reinterpret_cast<float*>(dyn_lds + 2 * P.n_boxes);
-    int* sgc = reinterpret_cast<int*>(spx + D * kParMax);
-    float* sgr = reinterpret_cast<float*>(sgc + P.gb_cells);
-    uint16_t* sgl = reinterpret_cast<uint16_t*>(sgr + P.gb_cells);
+    int2* sgc = reinterpret_cast<int2*>(spx + D * kParMax);
+    uint16_t* sgl = reinterpret_cast<uint16_t*>(sgc + gbp);
 
+    // the obstacle data does not depend on the device state: its loads go
+    // out together with the state's
+    stage_lds(reinterpret_cast<const int4*>(T.boxes), reinterpret_cast<int4*>(sbox), 2 * P.n_boxes,
+              reinterpret_cast<const int4*>(T.gcell), reinterpret_cast<int4*>(sgc), gbp / 2,
+              reinterpret_cast<const int4*>(T.glist), reinterpret_cast<int4*>(sgl), (P.gb_entries + 7) / 8);
     DevState* st = T.st;
     const int S = st->n_sel * P.K;
     if (st->full || S == 0) return;  // kernel-uniform
@@ -251,16 +268,10 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
     if (blockIdx.x == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
-    for (int i = threadIdx.x; i < 2 * P.n_boxes; i += blockDim.x) sbox[i] = T.boxes[i];
-    for (int i = threadIdx.x; i < P.gb_cells; i += blockDim.x) {
-        sgc[i] = T.gcell[i];
-        sgr[i] = T.gclear[i];
-    }
     if (threadIdx.x < D) {
         s_os[0][threadIdx.x] = P.os_lo[threadIdx.x];
         s_os[1][threadIdx.x] = P.os_hi[threadIdx.x];
     }
-    for (int i = threadIdx.x; i < P.gb_entries; i += blockDim.x) sgl[i] = T.glist[i];
     const Hot<DYN> H = make_hot<DYN>(P);
     const int lane = threadIdx.x & 63;
     int my_valid = 0, my_steps = 0;
@@ -283,20 +294,21 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
         float pv[kStage];
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
-            const int idx = threadIdx.x + r * kBlock;
+            const int idx = threadIdx.x + r * kPropBlock;
             prow[r] = idx < nstage ? T.sel[r0 + idx % npar] : 0;
         }
         const int my_pid = (int)threadIdx.x < npar ? T.sel[r0 + threadIdx.x] : 0;
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
-            const int idx = threadIdx.x + r * kBlock;
+            const int idx = threadIdx.x + r * kPropBlock;
             pv[r] = idx < nstage ? T.x[(long long)(idx / npar) * P.cap + prow[r]] : 0.f;
         }
         const uint32_t my_pcost = (int)threadIdx.x < npar ? T.cost[my_pid] : 0u;
+        const bool one_each = cnt <= (int)blockDim.x;  // one slot per thread: no sort needed
         int bins[kPerThread];
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
-            const int li = threadIdx.x + r * kBlock;
+            const int li = threadIdx.x + r * kPropBlock;
             bins[r] = -1;
             if (li < cnt) {
                 float u[M];
@@ -306,61 +318,70 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
                 for (int k = 0; k < M; ++k) s_u[k][li] = u[k];
                 s_n[li] = (unsigned short)n;
                 bins[r] = (kSortBins - 1) - min(kSortBins - 1, (n - P.steps_min) >> P.sort_shift);
-                atomicAdd(&s_bin[bins[r]], 1);
+                if (one_each) s_order[li] = (uint32_t)li | (uint32_t)((base + li) / P.K - r0) << 16;
+                else atomicAdd(&s_bin[bins[r]], 1);
             }
         }
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
-            const int idx = threadIdx.x + r * kBlock;
+            const int idx = threadIdx.x + r * kPropBlock;
             if (idx < nstage) spx[(idx / npar) * kParMax + idx % npar] = pv[r];
         }
-        for (int idx = threadIdx.x + kStage * kBlock; idx < nstage; idx += kBlock)
+        for (int idx = threadIdx.x + kStage * kPropBlock; idx < nstage; idx += kPropBlock)
             spx[(idx / npar) * kParMax + idx % npar] = T.x[(long long)(idx / npar) * P.cap + T.sel[r0 + idx % npar]];
         if ((int)threadIdx.x < npar) {
             s_pid[threadIdx.x] = my_pid;
             s_pcost[threadIdx.x] = my_pcost;
         }
         __syncthreads();
-        if (threadIdx.x < 64) {  // exclusive prefix over the 64 bins in one wave
-            const int v = s_bin[threadIdx.x];
-            int x = v;
+        if (!one_each) {  // block-uniform: counting sort of the queue, longest first
+            if (threadIdx.x < 64) {  // exclusive prefix over the 64 bins in one wave
+                const int v = s_bin[threadIdx.x];
+                int x = v;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int y = __shfl_up(x, o);
-                if ((int)threadIdx.x >= o) x += y;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(x, o);
+                    if ((int)threadIdx.x >= o) x += y;
+                }
+                s_bin[threadIdx.x] = x - v;
             }
-            s_bin[threadIdx.x] = x - v;
-        }
-        __syncthreads();
+            __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kPerThread; ++r)
-            if (bins[r] >= 0)
-                s_order[atomicAdd(&s_bin[bins[r]], 1)] = (unsigned short)(threadIdx.x + r * kBlock);
-        __syncthreads();
+            for (int r = 0; r < kPerThread; ++r)
+                if (bins[r] >= 0)
+                    s_order[atomicAdd(&s_bin[bins[r]], 1)] =
+                        (uint32_t)(threadIdx.x + r * kPropBlock) |
+                        (uint32_t)((base + (int)threadIdx.x + r * kPropBlock) / P.K - r0) << 16;
+            __syncthreads();
+        }
 
         // 2. integrate, each lane refilling from the queue
         float x[D], u[M];
         float len = 0.f;
         int li = -1, n = 0, k = 0;
         int gcur = -1, gstart = 0, gcount = 0;
+        float gclr = 0.f;
         // safe ball: no box is within sqrt(r2) of (rx, ry, rz), the last
         // position whose grid cell was looked up
         float rx = 0.f, ry = 0.f, rz = 0.f, r2 = -1.f;
-        bool drained = false;
+        bool exhausted = false;  // wave-uniform: the queue has no slot left
         while (true) {
-            const bool want = li < 0 && !drained;
+            const bool want = li < 0 && !exhausted;
             const unsigned long long m = __ballot(want);
             if (m) {
                 const int leader = __ffsll((long long)m) - 1;
                 int first = 0;
                 if (lane == leader) first = atomicAdd(&s_next, __popcll(m));
-                first = __shfl(first, leader);
+                first = __builtin_amdgcn_readlane(first, leader);
+                // one slot per thread: nothing is left to take after the first
+                if (one_each || first + __popcll(m) >= cnt) exhausted = true;
                 if (want) {
                     const int q = first + __popcll(m & __lanemask_lt());
                     if (q < cnt) {
-                        li = s_order[q];
+                        const uint32_t o = s_order[q];
+                        li = (int)(o & 0xFFFFu);
+                        const int pj = (int)(o >> 16);
                         n = s_n[li];
-                        const int pj = (base + li) / P.K - r0;
 #pragma unroll
                         for (int c = 0; c < M; ++c) u[c] = s_u[c][li] * (rev_control(DYN, c) ? kInv2Pi : 1.f);
 #pragma unroll
@@ -369,8 +390,6 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
                         len = 0.f;
                         gcur = -1;
                         r2 = -1.f;
-                    } else {
-                        drained = true;
                     }
                 }
             }
@@ -383,20 +402,37 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
                 if (ok && __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)) >= r2) {
                     const int g = box_grid_cell(H, x);
                     if (g != gcur) {
-                        const int e = sgc[g];
-                        gstart = e & 0xFFFFF;
-                        gcount = e >> 20;
+                        const int2 e = sgc[g];
+                        gstart = e.x & 0xFFFFF;
+                        gcount = e.x >> 20;
+                        gclr = __int_as_float(e.y);
                         gcur = g;
                     }
-                    for (int j = 0; j < gcount; ++j)
-                        if (in_box(&sbox[2 * sgl[gstart + j]], x[0], x[1], x[2])) {
-                            ok = false;
-                            break;
+                    // L-infinity distance to each listed box: at most 0 exactly
+                    // when the closed box holds the point (the sign of a float
+                    // difference is exact); four boxes per round of LDS reads
+                    float dmin = __builtin_inff();
+                    for (int j = 0; j < gcount; j += 4) {
+                        int bi[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) bi[t] = sgl[gstart + min(j + t, gcount - 1)];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const float4 lo = sbox[2 * bi[t]], hi = sbox[2 * bi[t] + 1];
+                            const float d = __builtin_fmaxf(
+                                __builtin_fmaxf(__builtin_fmaxf(lo.x - x[0], lo.y - x[1]), lo.z - x[2]),
+                                __builtin_fmaxf(__builtin_fmaxf(x[0] - hi.x, x[1] - hi.y), x[2] - hi.z));
+                            dmin = __builtin_fminf(dmin, d);
                         }
+                    }
+                    ok = dmin > 0.f;
+                    // the ball: the distance to the nearest box, shrunk for the
+                    // float rounding of the distances compared against it
+                    const float r = __builtin_fminf(gclr, dmin);
                     rx = x[0];
                     ry = x[1];
                     rz = x[2];
-                    r2 = sgr[g];
+                    r2 = r * r * 0.99998f;
                 }
                 if (!ok || k == n) {
                     s_fi[li] = (short)(ok ? 0 : k);
@@ -420,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_propagate(DevProblem P, DevPtrs T)
         // 3. region map, cost, region minimum, candidate records
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
-            const int lj = threadIdx.x + r * kBlock;
+            const int lj = threadIdx.x + r * kPropBlock;
             if (lj >= cnt) continue;
             const int s = base + lj;
             const int fi = s_fi[lj];
@@ -873,8 +909,7 @@ void for_each_array(const Sizes& z, F&& f)
     f("tile_count", sizeof(int) * (size_t)z.n_tiles);
     f("act", (size_t)z.n_act);
     f("boxes", sizeof(float4) * 2 * (size_t)(z.n_boxes > 0 ? z.n_boxes : 1));
-    f("gcell", sizeof(int) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2]);
-    f("gclear", sizeof(float) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2]);
+    f("gcell", sizeof(int2) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2]);
     f("glist", sizeof(uint16_t) * (size_t)(z.gb_entries > 0 ? z.gb_entries : 1));
     f("st", sizeof(DevState));
     f("stats", sizeof(kpx_iter_stats) * kStatsCap);
@@ -895,64 +930,18 @@ bool finite(float v) { return std::isfinite(v); }
 // Box grid: a uniform G^3 grid over the workspace; each grid cell lists the
 // boxes (grown by the margin) that overlap it, grown by a small slack so that
 // rounding in the device's float32 cell index can never miss a box.  Each cell
-// also carries a clearance: a lower bound on the distance from any point of
-// the (slack-grown) cell to any box, so that a point p whose cell was looked
-// up has every box farther than that from it, and any later point within the
-// clearance of p needs no box test.  G is the finest resolution whose cells,
-// clearances and lists fit the LDS budget.
+// also carries a clearance radius: a lower bound on the distance from any
+// point of the (slack-grown) cell to any box that the cell does not list.  A
+// point p whose cell was looked up is then at least min(clearance, distance
+// to each listed box) from every box, and any later point closer than that
+// to p needs no box test.  G is the finest resolution whose cells and lists
+// fit the LDS budget.
 struct BoxGrid {
     int n[3];
-    std::vector<int> cells;  // first entry | count << 20
-    std::vector<float> clear2;  // squared clearance, rounded down
+    std::vector<int> cells;     // first entry | count << 20
+    std::vector<float> clear;   // clearance radius, rounded down
     std::vector<uint16_t> list;
 };
-
-// Squared clearance of every cell: the distance between the slack-grown cell
-// and the nearest margin-grown box (double), shrunk by a relative 1e-5 and an
-// absolute 1e-6 of the workspace extent (so that float32 rounding of the
-// device's squared distance cannot make it optimistic), then squared and
-// rounded down to float (the absolute part scales with the largest workspace
-// coordinate, since float32 positions carry errors of that order).  Cells that
-// touch a box get 0; without boxes, FLT_MAX.
-void box_grid_clearance(const kpx_problem* p, BoxGrid* g)
-{
-    const int G0 = g->n[0], G1 = g->n[1], G2 = g->n[2];
-    g->clear2.assign((size_t)G0 * G1 * G2, 3.4028234663852886e38f);
-    if (p->n_boxes == 0) return;
-    double wmax = 0.0, lo[3], step[3], slack[3];
-    for (int a = 0; a < 3; ++a) {
-        const double w = (double)p->ws_hi[a] - p->ws_lo[a];
-        wmax = std::max({wmax, w, std::fabs((double)p->ws_lo[a]), std::fabs((double)p->ws_hi[a])});
-        lo[a] = p->ws_lo[a];
-        step[a] = w / g->n[a];
-        slack[a] = 1e-4 * w;
-    }
-    for (int i = 0; i < G0; ++i)
-        for (int j = 0; j < G1; ++j)
-            for (int k = 0; k < G2; ++k) {
-                const int id[3] = {i, j, k};
-                double best = INFINITY;
-                for (int b = 0; b < p->n_boxes; ++b) {
-                    double d2 = 0.0;
-                    for (int a = 0; a < 3; ++a) {
-                        const double c0 = lo[a] + id[a] * step[a] - slack[a];
-                        const double c1 = lo[a] + (id[a] + 1) * step[a] + slack[a];
-                        const double b0 = (double)p->boxes[6 * b + a] - p->margin;
-                        const double b1 = (double)p->boxes[6 * b + 3 + a] + p->margin;
-                        const double gap = std::max(0.0, std::max(b0 - c1, c0 - b1));
-                        d2 += gap * gap;
-                    }
-                    best = std::min(best, d2);
-                }
-                double r = std::sqrt(best) * (1.0 - 1e-5) - 1e-6 * wmax;
-                float r2 = 0.f;
-                if (r > 0.0) {
-                    r2 = (float)(r * r);
-                    if ((double)r2 > r * r) r2 = std::nextafter(r2, 0.f);
-                }
-                g->clear2[((size_t)i * G1 + j) * G2 + k] = r2;
-            }
-}
 
 void build_box_grid_at(const kpx_problem* p, int G, BoxGrid* g)
 {
@@ -982,9 +971,55 @@ void build_box_grid_at(const kpx_problem* p, int G, BoxGrid* g)
     }
 }
 
+// Clearance of every cell: the distance (double) between the slack-grown cell
+// and the nearest margin-grown box it does not list, shrunk by a relative
+// 1e-5 and rounded down to float.  Without such a box, FLT_MAX.
+void box_grid_clearance(const kpx_problem* p, BoxGrid* g)
+{
+    const int G0 = g->n[0], G1 = g->n[1], G2 = g->n[2];
+    g->clear.assign((size_t)G0 * G1 * G2, 3.4028234663852886e38f);
+    if (p->n_boxes == 0) return;
+    double lo[3], step[3], slack[3];
+    for (int a = 0; a < 3; ++a) {
+        const double w = (double)p->ws_hi[a] - p->ws_lo[a];
+        lo[a] = p->ws_lo[a];
+        step[a] = w / g->n[a];
+        slack[a] = 1e-4 * w;
+    }
+    std::vector<char> listed(p->n_boxes);
+    for (int i = 0; i < G0; ++i)
+        for (int j = 0; j < G1; ++j)
+            for (int k = 0; k < G2; ++k) {
+                const size_t c = ((size_t)i * G1 + j) * G2 + k;
+                std::fill(listed.begin(), listed.end(), 0);
+                const int first = g->cells[c] & 0xFFFFF, count = g->cells[c] >> 20;
+                for (int e = 0; e < count; ++e) listed[g->list[first + e]] = 1;
+                const int id[3] = {i, j, k};
+                double best = INFINITY;
+                for (int b = 0; b < p->n_boxes; ++b) {
+                    if (listed[b]) continue;
+                    double d2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        const double c0 = lo[a] + id[a] * step[a] - slack[a];
+                        const double c1 = lo[a] + (id[a] + 1) * step[a] + slack[a];
+                        const double b0 = (double)p->boxes[6 * b + a] - p->margin;
+                        const double b1 = (double)p->boxes[6 * b + 3 + a] + p->margin;
+                        const double gap = std::max(0.0, std::max(b0 - c1, c0 - b1));
+                        d2 += gap * gap;
+                    }
+                    best = std::min(best, d2);
+                }
+                if (!std::isfinite(best)) continue;
+                const double r = std::sqrt(best) * (1.0 - 1e-5);
+                float rf = (float)r;
+                if ((double)rf > r) rf = std::nextafter(rf, 0.f);
+                g->clear[c] = rf;
+            }
+}
+
 size_t box_grid_bytes(const BoxGrid& g)
 {
-    return (sizeof(int) + sizeof(float)) * g.cells.size() + sizeof(uint16_t) * g.list.size();
+    return sizeof(int2) * g.cells.size() + sizeof(uint16_t) * g.list.size();
 }
 
 void build_box_grid(const kpx_problem* p, BoxGrid* g)
@@ -1260,8 +1295,7 @@ void carve(kpx_handle* h)
     T.tile_count = (int*)ptrs[k++];
     T.act = (uint8_t*)ptrs[k++];
     T.boxes = (float4*)ptrs[k++];
-    T.gcell = (int*)ptrs[k++];
-    T.gclear = (float*)ptrs[k++];
+    T.gcell = (int2*)ptrs[k++];
     T.glist = (uint16_t*)ptrs[k++];
     T.st = (DevState*)ptrs[k++];
     T.stats = (kpx_iter_stats*)ptrs[k++];
@@ -1298,15 +1332,16 @@ DevPtrs kernel_ptrs(const kpx_handle* h)
 
 size_t propagate_lds_bytes(const Sizes& z, int d)
 {
+    // every region padded to whole 16-byte words (the kernel stages them as such)
+    const size_t gbp = ((size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2] + 1) & ~(size_t)1;
     return sizeof(float4) * 2 * (size_t)z.n_boxes + sizeof(float) * (size_t)d * kParMax +
-           (sizeof(int) + sizeof(float)) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2] +
-           sizeof(uint16_t) * (size_t)z.gb_entries;
+           sizeof(int2) * gbp + 16 * (((size_t)z.gb_entries + 7) / 8);
 }
 
 template <int DYN, int COST>
 void launch_propagate(kpx_handle* h, const DevPtrs& T)
 {
-    k_propagate<DYN, COST><<<h->P.n_cu, kBlock, propagate_lds_bytes(h->z, Dims<DYN>::D), h->stream>>>(
+    k_propagate<DYN, COST><<<h->P.n_cu, kPropBlock, propagate_lds_bytes(h->z, Dims<DYN>::D), h->stream>>>(
         h->P, T);
 }
 
@@ -1470,11 +1505,14 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
     if (hipMemcpyAsync(h->T.boxes, boxes.data(), sizeof(float) * boxes.size(), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess)
         return cleanup(KPX_ERR_DEVICE);
-    if (hipMemcpyAsync(h->T.gcell, grid.cells.data(), sizeof(int) * grid.cells.size(),
-                       hipMemcpyHostToDevice, h->stream) != hipSuccess)
-        return cleanup(KPX_ERR_DEVICE);
-    if (hipMemcpyAsync(h->T.gclear, grid.clear2.data(), sizeof(float) * grid.clear2.size(),
-                       hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    std::vector<int2> gcell(grid.cells.size());
+    for (size_t c = 0; c < gcell.size(); ++c) {
+        int bits;
+        std::memcpy(&bits, &grid.clear[c], sizeof(bits));
+        gcell[c] = make_int2(grid.cells[c], bits);
+    }
+    if (hipMemcpyAsync(h->T.gcell, gcell.data(), sizeof(int2) * gcell.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess)
         return cleanup(KPX_ERR_DEVICE);
     if (!grid.list.empty() &&
         hipMemcpyAsync(h->T.glist, grid.list.data(), sizeof(uint16_t) * grid.list.size(),
