@@ -79,6 +79,8 @@ def parse():
                     help="bound on the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--time-all", action="store_true",
+                    help="HIP events around all four kernels (default: propagate only)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -119,7 +121,8 @@ def main():
     snap_start = planner.snapshot() if not a.no_cpu_baseline else None
     c0 = planner.counters()
     if not a.no_timing:
-        planner.set_timing(True)
+        # HIP events around propagate (the roofline kernel), or all four kernels
+        planner.set_timing(15 if a.time_all else 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     planner.iterate(a.steps)
@@ -142,7 +145,7 @@ def main():
         ms, launches = planner.read_timing()
         kernel_ms = {name: (ms[i] / launches[i] if launches[i] else None)
                      for i, name in enumerate(["propagate", "prune_flags", "insert",
-                                               "finalize_select"])}
+                                               "finalize_select"]) if launches[i]}
         if launches[0]:
             fl = FLOPS_PER_SUBSTEP[(prob.dynamics, prob.cost)] * substeps / launches[0]
             avg_s = ms[0] / launches[0] / 1e3

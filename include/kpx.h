@@ -246,10 +246,11 @@ int kpx_set_dump(kpx_handle* h, int32_t enable);
  * KPX_ERR_BUFFER when view->capacity < n_slots. */
 int kpx_read_dump(kpx_handle* h, kpx_dump_view* view, int64_t* n_slots);
 
-/* Brackets each of the four kernels of every following iteration with HIP
- * events on the handle's stream (enable = 1), or stops (0).  Enabling also
- * clears the accumulated times. */
-int kpx_set_timing(kpx_handle* h, int32_t enable);
+/* Brackets the kernels of every following iteration with HIP events on the
+ * handle's stream: bit k of kernel_mask (0..15) times kernel k (numbered as
+ * in kpx_read_timing); 0 stops.  Each call clears the accumulated times.
+ * KPX_ERR_ARG for a mask outside 0..15. */
+int kpx_set_timing(kpx_handle* h, int32_t kernel_mask);
 
 /* Waits and returns, per kernel (0 propagate, 1 prune + survivor flags,
  * 2 insert, 3 close of the iteration + next selection), the summed

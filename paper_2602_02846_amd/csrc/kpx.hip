@@ -116,42 +116,6 @@ __device__ __forceinline__ int wave_sum(int v)
     return v;
 }
 
-// Exclusive scan of one int per thread over the block; *total gets the sum.
-// `lds` holds blockDim/64 + 1 ints.
-__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int* total)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) lds[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int w = 0; w < nw; ++w) {
-            const int t = lds[w];
-            lds[w] = acc;
-            acc += t;
-        }
-        lds[nw] = acc;
-    }
-    __syncthreads();
-    const int excl = x - v + lds[wid];
-    *total = lds[nw];
-    __syncthreads();
-    return excl;
-}
-
-__device__ __forceinline__ int block_sum(int v, int* lds)
-{
-    int total;
-    block_exclusive_scan(v, lds, &total);
-    return total;
-}
-
 // ------------------------------------------------------------------ init
 
 __global__ void k_fill_table(unsigned long long* tbl, uint8_t* act, int n, int n_act)
@@ -453,16 +417,20 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs 
         }
         __syncthreads();
 
-        // 3. region map, cost, region minimum, candidate records
+        // 3. region map, cost, region minimum, candidate records.  Every
+        // atomic of a thread is issued before the first of their results is
+        // looked at, so that their round trips overlap.
+        unsigned long long keys[kPerThread], olds[kPerThread];
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
             const int lj = threadIdx.x + r * kPropBlock;
+            keys[r] = kEmpty;
+            olds[r] = kEmpty;
             if (lj >= cnt) continue;
             const int s = base + lj;
             const int fi = s_fi[lj];
             const int nn = s_n[lj];
             const int pj = s / P.K - r0;
-            const int parent = s_pid[pj];
             my_steps += fi ? fi : nn;
             if (fi == 0) {
                 ++my_valid;
@@ -477,13 +445,8 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs 
                 }
                 const unsigned long long key =
                     ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)(n_tree + s);
-                const unsigned long long old = atomicMin(&T.tbl[c], key);
-                if (key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
-                    // this lane took the region from a tree node: it is beaten (V_T)
-                    const uint32_t o = (uint32_t)old;
-                    T.status[o] = kTerminal;
-                    T.dead[o] = 1;
-                }
+                keys[r] = key;
+                olds[r] = atomicMin(&T.tbl[c], key);
                 T.ckey[s] = key;
                 T.ccell[s] = c;
                 T.cflag[s] = (uint8_t)(1 | (in_goal(P, pe) ? 2 : 0));
@@ -493,11 +456,21 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs 
                 T.cflag[s] = 0;
             }
             if (T.d_parent) {
-                T.d_parent[s] = parent;
+                T.d_parent[s] = s_pid[pj];
 #pragma unroll
                 for (int q = 0; q < M; ++q) T.d_u[(long long)q * P.s_max + s] = s_u[q][lj];
                 T.d_n[s] = nn;
                 T.d_fi[s] = fi;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) {
+            const unsigned long long key = keys[r], old = olds[r];
+            if (key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
+                // this lane took the region from a tree node: it is beaten (V_T)
+                const uint32_t o = (uint32_t)old;
+                T.status[o] = kTerminal;
+                T.dead[o] = 1;
             }
         }
     }
@@ -513,45 +486,54 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs 
 
 __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T, int n_prune_blocks)
 {
-    __shared__ int lds[kBlock / 64 + 1];
+    __shared__ int s_w[kBlock / 64];
     DevState* st = T.st;
-    if (st->full) return;
-    const long long n_tree = st->n_tree;
     if ((int)blockIdx.x < n_prune_blocks) {
         // Alg. 3 for the owner of region c (every live node owns its region);
         // also records whether the region's node is active after this iteration
         const int c = blockIdx.x * blockDim.x + threadIdx.x;
-        if (c >= P.n_cells) return;
-        const unsigned long long key = T.tbl[c];
+        const unsigned long long key = T.tbl[min(c, P.n_cells - 1)];
+        const int full = st->full;
+        const long long n_tree = st->n_tree;
+        if (full || c >= P.n_cells) return;
         uint8_t a = 0;
         if (key != kEmpty) {
             const uint32_t o = (uint32_t)key;
             if ((long long)o >= n_tree) {
                 a = 1;  // an arrival of this iteration owns it; it is inserted active
             } else {
+                // status, count and the first ancestor list in one round trip
                 uint8_t s = T.status[o];
+                const int ic0 = T.icount[o];
+                int4 A = T.anc[2 * o], B = T.anc[2 * o + 1];
                 if (s == kInactive) {  // lines 3-7
-                    const int ic = T.icount[o] + 1;
+                    const int ic = ic0 + 1;
                     T.icount[o] = (uint8_t)ic;
                     if (ic > P.i_max) {
                         s = kActive;
                         T.status[o] = kActive;
                     }
-                } else if (s == kActive && T.icount[o] <= P.i_max) {
+                } else if (s == kActive && ic0 <= P.i_max) {
                     // lines 13-15: any ancestor beaten in its region (or below
-                    // one); eight ancestors per step from the stored lists
-                    int q = o;
+                    // one); eight ancestors per step from the stored lists, the
+                    // next list fetched together with this step's flags
                     bool beaten = false;
-                    while (q >= 0) {
-                        const int4 a = T.anc[2 * q], b = T.anc[2 * q + 1];
-                        const int ids[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+                    while (true) {
+                        const int ids[8] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w};
                         uint8_t d[8];
 #pragma unroll
                         for (int j = 0; j < 8; ++j) d[j] = ids[j] >= 0 ? T.dead[ids[j]] : 0;
+                        const int nq = ids[7];
+                        int4 NA = make_int4(-1, -1, -1, -1), NB = NA;
+                        if (nq >= 0) {
+                            NA = T.anc[2 * nq];
+                            NB = T.anc[2 * nq + 1];
+                        }
 #pragma unroll
                         for (int j = 0; j < 8; ++j) beaten |= d[j] != 0;
-                        if (beaten) break;
-                        q = ids[7];
+                        if (beaten || nq < 0) break;
+                        A = NA;
+                        B = NB;
                     }
                     if (beaten) {
                         s = kInactive;
@@ -567,58 +549,116 @@ __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T,
     }
     // survivor mask V_U (App. A U-filter) and per-tile counts
     const int tile = blockIdx.x - n_prune_blocks;
-    const int S = st->n_sel * P.K;
     const int s = tile * kTile + threadIdx.x;
+    const int sc = min(s, P.s_max - 1);
+    const uint8_t fl = T.cflag[sc];
+    const unsigned long long key = T.ckey[sc];
+    const int cell = T.ccell[sc];
+    const int full = st->full;
+    const int S = st->n_sel * P.K;
+    if (full || tile * kTile >= S) return;  // block-uniform
     int f = 0;
     if (s < S) {
-        if (T.cflag[s] & 1) f = T.ckey[s] == T.tbl[T.ccell[s]];
+        if (fl & 1) f = key == T.tbl[cell];
         T.csurv[s] = (uint8_t)f;
     }
-    const int total = block_sum(f, lds);
-    if (threadIdx.x == 0) T.tile_count[tile] = total;
+    const int wt = wave_sum(f);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = wt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) total += s_w[w];
+        T.tile_count[tile] = total;
+    }
 }
 
-// ------------------------------------------------------------------ finalize + select (one block)
-
-// The finalize/select workgroup issues every load it needs before its first
-// barrier (device state, survivor tile counts, the activity words it owns), so
-// that one memory round trip covers them; the owners of the selected regions
-// are then gathered in one more.
-struct SelectLoads {
-    int tile0;                  // tile_count[threadIdx.x] (0 past n_tiles)
-    int per, w0, w1;            // activity words [w0, w1) of this thread
-    uint32_t wd[kSelWords];     // their values, when per <= kSelWords
-};
-
-__device__ __forceinline__ void select_issue_loads(const DevProblem& P, const DevPtrs& T, SelectLoads& L)
+// Exclusive scan of three ints per thread over the block, with the totals.
+// One barrier: each thread then sums the wave totals below its own wave.
+// `s_w` holds 3 x 16 ints (at most 1024 threads).
+__device__ __forceinline__ void block_scan3(int (&v)[3], int (&ex)[3], int (&tot)[3], int (*s_w)[16])
 {
-    // unconditional loads from clamped (always valid) addresses, masked after,
-    // so that none of them waits for another
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int inc[3] = {v[0], v[1], v[2]};
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int y = __shfl_up(inc[k], o);
+            if (lane >= o) inc[k] += y;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s_w[k][wid] = inc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int below = 0, all = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int t = s_w[k][w];
+            below += w < wid ? t : 0;
+            all += t;
+        }
+        ex[k] = below + inc[k] - v[k];
+        tot[k] = all;
+    }
+}
+
+// Closes an iteration (counters, statistics, capacity check) and selects the
+// next iteration's nodes: regions whose owner is active, in region order
+// rotated to start at the cursor, at most n_select.  One block; each thread
+// owns a run of whole 4-region words of the activity bytes (0/1, zero-padded
+// past the last region).  The survivor count and the two cursor-split counts
+// of active regions share one block scan.
+__device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, DevState& q, bool finalize,
+                                    int (*s_w)[16], int* s_sel)
+{
+    // every load of the block is in flight before the first barrier
     const int t0 = T.tile_count[min((int)threadIdx.x, P.n_tiles - 1)];
     const int nwords = (P.n_cells + 3) >> 2;
-    L.per = (nwords + (int)blockDim.x - 1) / (int)blockDim.x;
-    L.w0 = min((int)threadIdx.x * L.per, nwords);
-    L.w1 = min(L.w0 + L.per, nwords);
+    const int per = (nwords + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int w0 = min((int)threadIdx.x * per, nwords);
+    const int w1 = min(w0 + per, nwords);
     const uint32_t* act = reinterpret_cast<const uint32_t*>(T.act);
-    uint32_t raw[kSelWords];
+    uint32_t wd[kSelWords];
 #pragma unroll
-    for (int i = 0; i < kSelWords; ++i) raw[i] = act[min(L.w0 + i, nwords - 1)];
-    L.tile0 = (int)threadIdx.x < P.n_tiles ? t0 : 0;
+    for (int i = 0; i < kSelWords; ++i) wd[i] = act[min(w0 + i, nwords - 1)];
+    if (threadIdx.x == 0) q = *T.st;
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSelWords; ++i) L.wd[i] = L.w0 + i < L.w1 ? raw[i] : 0u;
-}
-
-// Finishes an iteration: counters, statistics, capacity check.  Runs in one
-// block on the state copy in LDS.
-__device__ void finalize_iteration(const DevProblem& P, const DevPtrs& T, DevState& q,
-                                   const SelectLoads& L, int* lds)
-{
+    for (int i = 0; i < kSelWords; ++i) wd[i] = w0 + i < w1 ? wd[i] & 0x01010101u : 0u;
+    const bool in_regs = per <= kSelWords;
+    // what the block needs of the state, read before thread 0 updates it
+    const bool was_full = q.full != 0;
+    const long long n_tree0 = q.n_tree;
+    finalize = finalize && !was_full;
+    // the cursor this selection starts from (closing the iteration moves it)
+    const int cur = finalize ? q.cursor_next : q.cursor;
     const int S = q.n_sel * P.K;
     const int tiles = (S + kTile - 1) / kTile;
-    int v = (int)threadIdx.x < tiles ? L.tile0 : 0;
-    for (int j = threadIdx.x + blockDim.x; j < tiles; j += blockDim.x) v += T.tile_count[j];
-    const int n_surv = block_sum(v, lds);
-    if (threadIdx.x == 0) {
+    int v[3] = {0, 0, 0};  // survivors of my tiles; active regions at / after the cursor; before it
+    if (finalize) {
+        v[0] = (int)threadIdx.x < tiles ? t0 : 0;
+        for (int j = threadIdx.x + blockDim.x; j < tiles; j += blockDim.x) v[0] += T.tile_count[j];
+    }
+    auto count = [&](uint32_t w, int c0) {
+        const int k = min(max(cur - c0, 0), 4);  // bytes of this word before the cursor
+        const uint32_t below = k == 4 ? ~0u : (1u << (8 * k)) - 1u;
+        v[2] += __popc(w & below);
+        v[1] += __popc(w & ~below);
+    };
+    if (in_regs) {
+#pragma unroll
+        for (int i = 0; i < kSelWords; ++i) count(wd[i], 4 * (w0 + i));
+    } else {
+        for (int w = w0; w < w1; ++w) count(act[w] & 0x01010101u, 4 * w);
+    }
+    int ex[3], tot[3];
+    block_scan3(v, ex, tot, s_w);
+    if (finalize && threadIdx.x == 0) {
+        const int n_surv = tot[0];
         const long long it = q.it;
         const long long n_tree = q.n_tree + n_surv;
         kpx_iter_stats* r = &T.stats[it & (kStatsCap - 1)];
@@ -640,185 +680,158 @@ __device__ void finalize_iteration(const DevProblem& P, const DevPtrs& T, DevSta
         if (q.sol != kEmpty && q.first_sol_it < 0) q.first_sol_it = it;
         q.it = it + 1;
         q.n_tree = n_tree;
-        q.cursor = q.cursor_next;
+        q.cursor = cur;
         q.full = (n_tree + P.surv_max > P.cap) ? 1 : 0;
     }
-    __syncthreads();
-}
-
-// Active regions (0/1 bytes) in activity word `wd` at byte offset c0, split at
-// the cursor into those at or after it (hi) and before it (lo).
-__device__ __forceinline__ void count_word(uint32_t wd, int c0, int cur, int& hi, int& lo)
-{
-    wd &= 0x01010101u;
-    const int k = min(max(cur - c0, 0), 4);  // bytes of this word before the cursor
-    const uint32_t below = k == 4 ? ~0u : (1u << (8 * k)) - 1u;
-    lo += __popc(wd & below);
-    hi += __popc(wd & ~below);
-}
-
-// Gives each active region in word `wd` its rank in the rotated order; ranks
-// below nsel are recorded (region index) in LDS or, past kSelLds, in sel.
-__device__ __forceinline__ void rank_word(uint32_t wd, int c0, int cur, int nsel, int nc, int& r_hi,
-                                          int& r_lo, int* s_sel, int* sel, DevState& q)
-{
-    wd &= 0x01010101u;
-    while (wd) {
-        const int bit = __ffs(wd) - 1;
-        wd &= wd - 1;
-        const int c = c0 + (bit >> 3);
-        const bool at_or_after = c >= cur;
-        const int rank = at_or_after ? r_hi : r_lo;
-        r_hi += at_or_after;
-        r_lo += !at_or_after;
-        if (rank < nsel) {
-            if (nsel <= kSelLds) s_sel[rank] = c;
-            else sel[rank] = c;
-            if (rank == nsel - 1) q.cursor_next = (c + 1 == nc) ? 0 : c + 1;
+    // the capacity check, from the totals every thread holds
+    const bool full = was_full || (finalize && n_tree0 + tot[0] + P.surv_max > P.cap);
+    const int nsel = full ? 0 : min(tot[1] + tot[2], P.n_select);
+    // ranks: regions at or after the cursor first, then those before it
+    int r_hi = ex[1], r_lo = tot[1] + ex[2];
+    auto rank = [&](uint32_t w, int c0) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int a = (int)((w >> (8 * b)) & 1u);
+            const int c = c0 + b;
+            const bool h = c >= cur;
+            const int rk = h ? r_hi : r_lo;
+            if (a && rk < nsel) {
+                if (nsel <= kSelLds) s_sel[rk] = c;
+                else T.sel[rk] = c;
+                if (rk == nsel - 1) q.cursor_next = (c + 1 == P.n_cells) ? 0 : c + 1;
+            }
+            r_hi += a & (int)h;
+            r_lo += a & (int)!h;
         }
-    }
-}
-
-// Selects the next iteration's nodes: regions whose owner is active, in
-// region order rotated to start at the cursor, at most n_select.  One block;
-// each thread owns a run of whole 4-region words of the activity bytes (0/1,
-// zero-padded past the last region).
-__device__ void select_nodes(const DevProblem& P, const DevPtrs& T, DevState& q, const SelectLoads& L,
-                             int* lds, int* s_sel)
-{
-    if (q.full) {
-        if (threadIdx.x == 0) q.n_sel = 0;
-        __syncthreads();
-        return;
-    }
-    const int nc = P.n_cells;
-    const int cur = q.cursor;
-    const uint32_t* act = reinterpret_cast<const uint32_t*>(T.act);
-    const bool in_regs = L.per <= kSelWords;
-    int hi = 0, lo = 0;
-    if (in_regs) {
+    };
+    if (nsel > 0) {
+        if (in_regs) {
 #pragma unroll
-        for (int i = 0; i < kSelWords; ++i) count_word(L.wd[i], 4 * (L.w0 + i), cur, hi, lo);
-    } else {
-        for (int w = L.w0; w < L.w1; ++w) count_word(act[w], 4 * w, cur, hi, lo);
-    }
-    int total_hi, total_lo;
-    const int ex_hi = block_exclusive_scan(hi, lds, &total_hi);
-    const int ex_lo = block_exclusive_scan(lo, lds, &total_lo);
-    const int nsel = min(total_hi + total_lo, P.n_select);
-    int r_hi = ex_hi, r_lo = total_hi + ex_lo;
-    if (in_regs) {
-#pragma unroll
-        for (int i = 0; i < kSelWords; ++i)
-            rank_word(L.wd[i], 4 * (L.w0 + i), cur, nsel, nc, r_hi, r_lo, s_sel, T.sel, q);
-    } else {
-        for (int w = L.w0; w < L.w1; ++w) rank_word(act[w], 4 * w, cur, nsel, nc, r_hi, r_lo, s_sel, T.sel, q);
+            for (int i = 0; i < kSelWords; ++i) rank(wd[i], 4 * (w0 + i));
+        } else {
+            for (int w = w0; w < w1; ++w) rank(act[w] & 0x01010101u, 4 * w);
+        }
     }
     __syncthreads();
     // owners: the low word of each selected region's key; four loads in flight per thread
     const uint32_t* tbl_lo = reinterpret_cast<const uint32_t*>(T.tbl);
     const int bd = blockDim.x;
     for (int r0 = threadIdx.x; r0 < nsel; r0 += 4 * bd) {
-        int c[4];
+        int cc[4];
         uint32_t o[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int r = r0 + k * bd;
-            c[k] = r < nsel ? (nsel <= kSelLds ? s_sel[r] : T.sel[r]) : -1;
+            cc[k] = r < nsel ? (nsel <= kSelLds ? s_sel[r] : T.sel[r]) : -1;
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = c[k] >= 0 ? tbl_lo[2 * (size_t)c[k]] : 0u;
+        for (int k = 0; k < 4; ++k) o[k] = cc[k] >= 0 ? tbl_lo[2 * (size_t)cc[k]] : 0u;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (c[k] >= 0) T.sel[r0 + k * bd] = (int)o[k];
+            if (cc[k] >= 0) T.sel[r0 + k * bd] = (int)o[k];
     }
     if (threadIdx.x == 0) {
         q.n_sel = nsel;
-        if (nsel == 0) q.cursor_next = cur;
+        if (nsel == 0 && !full) q.cursor_next = cur;
+        *T.st = q;
     }
-    __syncthreads();
 }
 
 // Selection alone (after create).
 __global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs T)
 {
-    __shared__ int lds[kSelectThreads / 64 + 1];
+    __shared__ int s_w[3][16];
     __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
-    SelectLoads L;
-    select_issue_loads(P, T, L);
-    if (threadIdx.x == 0) s_st = *T.st;
-    __syncthreads();
-    select_nodes(P, T, s_st, L, lds, s_sel);
-    if (threadIdx.x == 0) *T.st = s_st;
+    finalize_and_select(P, T, s_st, false, s_w, s_sel);
 }
 
 // ------------------------------------------------------------------ insert
 
 // App. A UpdateTree: survivors appended at |T| + rank (exclusive scan of V_U).
+// Every load that does not depend on another is issued first (the state, the
+// counts of the earlier tiles, this slot's flag and candidate record, its
+// parent); one barrier then gives each survivor its rank.
 template <int DYN>
 __global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
-    __shared__ int lds[kBlock / 64 + 1];
-    DevState* st = T.st;
-    if (st->full) return;  // kernel-uniform: nothing happens in a full tree
-    const int S = st->n_sel * P.K;
+    __shared__ int s_w[2][kBlock / 64];
     const int tile = blockIdx.x;
-    if (tile * kTile < S) {
-        int pre = 0;
-        for (int j = threadIdx.x; j < tile; j += blockDim.x) pre += T.tile_count[j];
-        pre = block_sum(pre, lds);
-        const int s = tile * kTile + threadIdx.x;
-        const int f = s < S ? T.csurv[s] : 0;
-        int total;
-        const int rank = pre + block_exclusive_scan(f, lds, &total);
-        if (f) {
-            const long long i = st->n_tree + rank;
-            const uint32_t it = (uint32_t)st->it;
-            float u[M];
-            int n;
-            sample<DYN>(P, it, (uint32_t)s, u, n);
+    const int s = tile * kTile + threadIdx.x;
+    const int sc = min(s, P.s_max - 1);
+    int pre = 0;
 #pragma unroll
-            for (int q = 0; q < D; ++q) T.x[(long long)q * P.cap + i] = T.cx[(long long)q * P.s_max + s];
+    for (int u = 0; u < 4; ++u) {
+        const int j = threadIdx.x + u * kBlock;
+        const int v = T.tile_count[min(j, max(tile - 1, 0))];
+        pre += j < tile ? v : 0;
+    }
+    const uint8_t f0 = T.csurv[sc];
+    const unsigned long long key = T.ckey[sc];
+    const int c = T.ccell[sc];
+    const uint8_t flag = T.cflag[sc];
+    const int par = T.sel[sc / P.K];
+    DevState* st = T.st;
+    const int full = st->full, n_sel = st->n_sel;
+    const long long n_tree = st->n_tree;
+    const uint32_t it = (uint32_t)st->it;
+    if (full) return;  // kernel-uniform: nothing happens in a full tree
+    const int S = n_sel * P.K;
+    if (tile * kTile >= S) return;  // block-uniform
+    for (int j = threadIdx.x + 4 * kBlock; j < tile; j += kBlock) pre += T.tile_count[j];
+    const int f = s < S ? f0 : 0;
+    // rank = survivors of the earlier tiles + those before this slot in its tile
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = f;
 #pragma unroll
-            for (int q = 0; q < M; ++q) T.u[(long long)q * P.cap + i] = u[q];
-            const unsigned long long key = T.ckey[s];
-            const uint32_t cf = (uint32_t)(key >> 32);
-            const int c = T.ccell[s];
-            const int par = T.sel[s / P.K];
-            const int4 pa = T.anc[2 * par], pb = T.anc[2 * par + 1];
-            T.anc[2 * i] = make_int4(par, pa.x, pa.y, pa.z);
-            T.anc[2 * i + 1] = make_int4(pa.w, pb.x, pb.y, pb.z);
-            T.steps[i] = (uint16_t)n;
-            T.parent[i] = par;
-            T.cost[i] = cf;
-            T.cell[i] = c;
-            T.status[i] = kActive;
-            T.icount[i] = 0;
-            T.dead[i] = 0;
-            const unsigned long long nk = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)i;
-            T.tbl[c] = nk;
-            if (T.cflag[s] & 2) atomicMin(&st->sol, nk);  // Alg. 4 lines 5-7
-        }
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    const int wpre = wave_sum(pre);
+    if (lane == 63) s_w[0][wid] = inc;
+    if (lane == 0) s_w[1][wid] = wpre;
+    __syncthreads();
+    int rank = inc - f;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) rank += (w < wid ? s_w[0][w] : 0) + s_w[1][w];
+    if (f) {
+        const long long i = n_tree + rank;
+        float xv[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) xv[q] = T.cx[(long long)q * P.s_max + s];
+        const int4 pa = T.anc[2 * par], pb = T.anc[2 * par + 1];
+        float u[M];
+        int n;
+        sample<DYN>(P, it, (uint32_t)s, u, n);
+#pragma unroll
+        for (int q = 0; q < D; ++q) T.x[(long long)q * P.cap + i] = xv[q];
+#pragma unroll
+        for (int q = 0; q < M; ++q) T.u[(long long)q * P.cap + i] = u[q];
+        const uint32_t cf = (uint32_t)(key >> 32);
+        T.anc[2 * i] = make_int4(par, pa.x, pa.y, pa.z);
+        T.anc[2 * i + 1] = make_int4(pa.w, pb.x, pb.y, pb.z);
+        T.steps[i] = (uint16_t)n;
+        T.parent[i] = par;
+        T.cost[i] = cf;
+        T.cell[i] = c;
+        T.status[i] = kActive;
+        T.icount[i] = 0;
+        T.dead[i] = 0;
+        const unsigned long long nk = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)i;
+        T.tbl[c] = nk;
+        if (flag & 2) atomicMin(&st->sol, nk);  // Alg. 4 lines 5-7
     }
 }
 
-// Closes the iteration (counters, statistics, capacity check) and selects the
-// next iteration's nodes.  One block; the device state is read once into LDS
-// and written back once.
+// Closes the iteration and selects the next iteration's nodes (one block).
 __global__ __launch_bounds__(kSelectThreads) void k_finalize_select(DevProblem P, DevPtrs T)
 {
-    __shared__ int lds[kSelectThreads / 64 + 1];
+    __shared__ int s_w[3][16];
     __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
-    SelectLoads L;
-    select_issue_loads(P, T, L);
-    if (threadIdx.x == 0) s_st = *T.st;
-    __syncthreads();
-    if (!s_st.full) finalize_iteration(P, T, s_st, L, lds);
-    select_nodes(P, T, s_st, L, lds, s_sel);
-    if (threadIdx.x == 0) *T.st = s_st;
+    finalize_and_select(P, T, s_st, true, s_w, s_sel);
 }
 
 // ------------------------------------------------------------------ solution path
@@ -1239,8 +1252,12 @@ struct kpx_handle {
     size_t bytes = 0;
     bool owns = false;
     bool dump_on = false;
-    bool timing_on = false;
-    std::vector<hipEvent_t> events;  // 5 per timed iteration
+    int timing_mask = 0;                      // bit k: kernel k is timed
+    struct Timed {
+        int kernel;
+        hipEvent_t begin, end;
+    };
+    std::vector<Timed> timed;                 // one per timed launch
     std::vector<hipEvent_t> spare;
     int full_cached = 0;
     int n_prune_blocks = 0;
@@ -1400,12 +1417,21 @@ hipEvent_t take_event(kpx_handle* h)
     return e;
 }
 
-int record(kpx_handle* h)
+// Launches kernel k of an iteration through `launch`, bracketed by events on
+// the handle's stream when k is timed.
+template <typename F>
+int timed_launch(kpx_handle* h, int k, F&& launch)
 {
-    hipEvent_t e = take_event(h);
-    if (!e) return fail(h, KPX_ERR_DEVICE, "hipEventCreate failed");
-    KPX_HIP(h, hipEventRecord(e, h->stream));
-    h->events.push_back(e);
+    if (!(h->timing_mask & (1 << k))) {
+        launch();
+        return KPX_OK;
+    }
+    hipEvent_t a = take_event(h), b = a ? take_event(h) : nullptr;
+    if (!a || !b) return fail(h, KPX_ERR_DEVICE, "hipEventCreate failed");
+    KPX_HIP(h, hipEventRecord(a, h->stream));
+    launch();
+    KPX_HIP(h, hipEventRecord(b, h->stream));
+    h->timed.push_back({k, a, b});
     return KPX_OK;
 }
 
@@ -1543,16 +1569,17 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
     const DevPtrs T = kernel_ptrs(h);
     for (int i = 0; i < n_iters; ++i) {
         int rc;
-        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
-        propagate(h, T);
-        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
-        k_prune_flags<<<h->n_prune_blocks + h->z.n_tiles, kBlock, 0, h->stream>>>(h->P, T,
-                                                                                 h->n_prune_blocks);
-        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
-        insert(h, T);
-        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
-        k_finalize_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, T);
-        if (h->timing_on && (rc = record(h)) != KPX_OK) return rc;
+        if ((rc = timed_launch(h, 0, [&] { propagate(h, T); })) != KPX_OK) return rc;
+        if ((rc = timed_launch(h, 1, [&] {
+                 k_prune_flags<<<h->n_prune_blocks + h->z.n_tiles, kBlock, 0, h->stream>>>(
+                     h->P, T, h->n_prune_blocks);
+             })) != KPX_OK)
+            return rc;
+        if ((rc = timed_launch(h, 2, [&] { insert(h, T); })) != KPX_OK) return rc;
+        if ((rc = timed_launch(h, 3, [&] {
+                 k_finalize_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, T);
+             })) != KPX_OK)
+            return rc;
     }
     KPX_HIP(h, hipGetLastError());
     return KPX_OK;
@@ -1742,13 +1769,16 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* v, int64_t* n_slots)
     return KPX_OK;
 }
 
-int kpx_set_timing(kpx_handle* h, int32_t enable)
+int kpx_set_timing(kpx_handle* h, int32_t kernel_mask)
 {
-    if (!h || (enable != 0 && enable != 1)) return KPX_ERR_ARG;
+    if (!h || kernel_mask < 0 || kernel_mask > 15) return KPX_ERR_ARG;
     KPX_HIP(h, hipStreamSynchronize(h->stream));
-    for (hipEvent_t e : h->events) h->spare.push_back(e);
-    h->events.clear();
-    h->timing_on = enable == 1;
+    for (const auto& t : h->timed) {
+        h->spare.push_back(t.begin);
+        h->spare.push_back(t.end);
+    }
+    h->timed.clear();
+    h->timing_mask = kernel_mask;
     return KPX_OK;
 }
 
@@ -1760,14 +1790,12 @@ int kpx_read_timing(kpx_handle* h, double ms[4], int64_t launches[4])
         ms[k] = 0.0;
         launches[k] = 0;
     }
-    const size_t n = h->events.size() / 5;
-    for (size_t i = 0; i < n; ++i)
-        for (int k = 0; k < 4; ++k) {
-            float t = 0.f;
-            KPX_HIP(h, hipEventElapsedTime(&t, h->events[5 * i + k], h->events[5 * i + k + 1]));
-            ms[k] += t;
-            launches[k] += 1;
-        }
+    for (const auto& e : h->timed) {
+        float t = 0.f;
+        KPX_HIP(h, hipEventElapsedTime(&t, e.begin, e.end));
+        ms[e.kernel] += t;
+        launches[e.kernel] += 1;
+    }
     return KPX_OK;
 }
 
@@ -1832,7 +1860,10 @@ int kpx_destroy(kpx_handle* h)
 {
     if (!h) return KPX_OK;
     if (h->stream || h->base) (void)hipStreamSynchronize(h->stream);
-    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    for (const auto& t : h->timed) {
+        (void)hipEventDestroy(t.begin);
+        (void)hipEventDestroy(t.end);
+    }
     for (hipEvent_t e : h->spare) (void)hipEventDestroy(e);
     if (h->owns && h->base) (void)hipFree(h->base);
     delete h;

@@ -355,8 +355,10 @@ class Planner:
         out["n_slots"] = k
         return out
 
-    def set_timing(self, enable: bool = True):
-        self._check(lib().kpx_set_timing(self.h, 1 if enable else 0))
+    def set_timing(self, enable=True):
+        """True times all four kernels, False none; an int is the kernel bit mask."""
+        mask = (15 if enable else 0) if isinstance(enable, bool) else int(enable)
+        self._check(lib().kpx_set_timing(self.h, mask))
 
     def read_timing(self):
         ms = (C.c_double * 4)()

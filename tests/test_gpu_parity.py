@@ -121,4 +121,10 @@ def test_stats_ring_and_timing(kpx):
     assert np.all(np.diff(st["n_tree"]) == st["n_survivors"][1:])
     assert np.all(st["t_end"] >= st["t_begin"])
     assert pl.clock_rate_khz() > 0
+    pl.set_timing(1)  # propagate only
+    pl.iterate(5)
+    ms, launches = pl.read_timing()
+    assert launches == [5, 0, 0, 0] and ms[0] > 0 and ms[1:] == [0.0, 0.0, 0.0]
+    with pytest.raises(kpx.KPXError):
+        pl.set_timing(16)
     pl.close()
