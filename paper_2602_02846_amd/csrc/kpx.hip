@@ -41,6 +41,7 @@ constexpr int kTile = kBlock;             // survivor slots per tile (one per th
 constexpr int kSelectThreads = 1024;
 constexpr int kSelWords = 8;            // activity words per select thread kept in registers
 constexpr int kSelLds = 8192;            // selections ranked in LDS (more go through global memory)
+constexpr int kSelBlocksMax = 1024;      // region blocks the many-block selection handles
 constexpr int kSortBins = 64;             // step-count bins of the in-block sort
 constexpr int kBoxGridMax = 16;           // box-grid cells per workspace axis (at most)
 constexpr int kBoxGridBytes = 48 * 1024;  // LDS budget of the box grid, its clearances and lists
@@ -67,6 +68,7 @@ struct DevState {
     int cursor;
     int cursor_next;
     int full;
+    int n_surv;          // survivors of this iteration (written by the insert kernel)
 };
 
 struct DevPtrs {
@@ -93,7 +95,9 @@ struct DevPtrs {
     int2* gcell;         // box grid, per grid cell: (first list entry | count << 20,
                          // bits of the clearance radius to the boxes not listed)
     uint16_t* glist;     // box grid: box indices
-    DevState* st;
+    DevState* st;        // this iteration's state (read by every kernel)
+    DevState* st_next;   // the next iteration's, written by the close of this one
+    int2* bcount;        // per block of kBlock regions: active regions at / after the cursor, before it
     kpx_iter_stats* stats;
     int* d_parent;       // dump (may be null)
     float* d_u;
@@ -165,6 +169,7 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, const float* x_init)
     st->cursor = 0;
     st->cursor_next = 0;
     st->full = 0;
+    st->n_surv = 0;
 }
 
 // ------------------------------------------------------------------ propagate
@@ -486,18 +491,20 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs 
 
 __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T, int n_prune_blocks)
 {
-    __shared__ int s_w[kBlock / 64];
+    __shared__ int s_w[kBlock / 64], s_w2[kBlock / 64];
     DevState* st = T.st;
     if ((int)blockIdx.x < n_prune_blocks) {
         // Alg. 3 for the owner of region c (every live node owns its region);
-        // also records whether the region's node is active after this iteration
+        // also records whether the region's node is active after this
+        // iteration, and per block the active regions on either side of the
+        // selection cursor
         const int c = blockIdx.x * blockDim.x + threadIdx.x;
         const unsigned long long key = T.tbl[min(c, P.n_cells - 1)];
-        const int full = st->full;
+        const int full = st->full, cur = st->cursor_next;
         const long long n_tree = st->n_tree;
-        if (full || c >= P.n_cells) return;
+        if (full) return;  // kernel-uniform
         uint8_t a = 0;
-        if (key != kEmpty) {
+        if (c < P.n_cells && key != kEmpty) {
             const uint32_t o = (uint32_t)key;
             if ((long long)o >= n_tree) {
                 a = 1;  // an arrival of this iteration owns it; it is inserted active
@@ -544,7 +551,22 @@ __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T,
                 a = s == kActive;
             }
         }
-        T.act[c] = a;
+        if (c < P.n_cells) T.act[c] = a;
+        const int hi = __popcll(__ballot(a && c >= cur)), lo = __popcll(__ballot(a && c < cur));
+        if ((threadIdx.x & 63) == 0) {
+            s_w[threadIdx.x >> 6] = hi;
+            s_w2[threadIdx.x >> 6] = lo;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int th = 0, tl = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                th += s_w[w];
+                tl += s_w2[w];
+            }
+            T.bcount[blockIdx.x] = make_int2(th, tl);
+        }
         return;
     }
     // survivor mask V_U (App. A U-filter) and per-tile counts
@@ -613,7 +635,7 @@ __device__ __forceinline__ void block_scan3(int (&v)[3], int (&ex)[3], int (&tot
 // past the last region).  The survivor count and the two cursor-split counts
 // of active regions share one block scan.
 __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, DevState& q, bool finalize,
-                                    int (*s_w)[16], int* s_sel)
+                                    int (*s_w)[16], int* s_sel, DevState* out)
 {
     // every load of the block is in flight before the first barrier
     const int t0 = T.tile_count[min((int)threadIdx.x, P.n_tiles - 1)];
@@ -733,7 +755,8 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, DevSt
     if (threadIdx.x == 0) {
         q.n_sel = nsel;
         if (nsel == 0 && !full) q.cursor_next = cur;
-        *T.st = q;
+        q.n_surv = 0;
+        *out = q;
     }
 }
 
@@ -743,7 +766,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs
     __shared__ int s_w[3][16];
     __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
-    finalize_and_select(P, T, s_st, false, s_w, s_sel);
+    finalize_and_select(P, T, s_st, false, s_w, s_sel, T.st);
 }
 
 // ------------------------------------------------------------------ insert
@@ -796,6 +819,12 @@ __global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
     int rank = inc - f;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) rank += (w < wid ? s_w[0][w] : 0) + s_w[1][w];
+    if (threadIdx.x == 0 && (tile + 1) * kTile >= S) {  // the last tile: the survivor count
+        int total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) total += s_w[0][w] + s_w[1][w];
+        st->n_surv = total;
+    }
     if (f) {
         const long long i = n_tree + rank;
         float xv[D];
@@ -825,13 +854,132 @@ __global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
     }
 }
 
-// Closes the iteration and selects the next iteration's nodes (one block).
-__global__ __launch_bounds__(kSelectThreads) void k_finalize_select(DevProblem P, DevPtrs T)
+// Closes the iteration and selects the next iteration's nodes in one block
+// (regions in more blocks than the many-block kernel below handles).
+__global__ __launch_bounds__(kSelectThreads) void k_finalize_select_one(DevProblem P, DevPtrs T)
 {
     __shared__ int s_w[3][16];
     __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
-    finalize_and_select(P, T, s_st, true, s_w, s_sel);
+    finalize_and_select(P, T, s_st, true, s_w, s_sel, T.st_next);
+}
+
+// Closes the iteration and selects the next iteration's nodes with one block
+// per kBlock regions (the prune kernel's blocks, whose counts of active
+// regions on either side of the cursor give each block the ranks of its own
+// regions; ballots rank them within the block).  It reads this iteration's
+// state and writes the next one, so no block sees another's update; block 0
+// writes everything but the cursor past the last selected region, which the
+// thread holding that rank writes.
+__global__ __launch_bounds__(kBlock) void k_finalize_select(DevProblem P, DevPtrs T, int nb)
+{
+    constexpr int NW = kBlock / 64;
+    __shared__ int s_r[6][NW];
+    const DevState* st = T.st;
+    const int b = blockIdx.x, c = b * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // every load first: this thread's region and owner, the block counts, the state
+    const int cc = min(c, P.n_cells - 1);
+    const uint8_t act = T.act[cc];
+    const uint32_t own = reinterpret_cast<const uint32_t*>(T.tbl)[2 * (size_t)cc];
+    int2 bc[kSelBlocksMax / kBlock];
+#pragma unroll
+    for (int k = 0; k < kSelBlocksMax / kBlock; ++k)
+        bc[k] = T.bcount[min((int)threadIdx.x + k * kBlock, nb - 1)];
+    const int was_full = st->full, n_sel = st->n_sel, n_surv0 = st->n_surv, cur = st->cursor_next;
+    const long long n_tree = st->n_tree;
+    // active regions at / after the cursor and before it: in the blocks before
+    // this one, and in all
+    int v[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kSelBlocksMax / kBlock; ++k) {
+        const int j = threadIdx.x + k * kBlock;
+        if (j < nb) {
+            v[2] += bc[k].x;
+            v[3] += bc[k].y;
+            if (j < b) {
+                v[0] += bc[k].x;
+                v[1] += bc[k].y;
+            }
+        }
+    }
+    const bool a = c < P.n_cells && act != 0;
+    const bool h = c >= cur;
+    const unsigned long long mh = __ballot(a && h), ml = __ballot(a && !h);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_r[k][wid] = v[k];
+        s_r[4][wid] = __popcll(mh);
+        s_r[5][wid] = __popcll(ml);
+    }
+    __syncthreads();
+    int HB = 0, LB = 0, HT = 0, LT = 0, wh = 0, wl = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        HB += s_r[0][w];
+        LB += s_r[1][w];
+        HT += s_r[2][w];
+        LT += s_r[3][w];
+        wh += w < wid ? s_r[4][w] : 0;
+        wl += w < wid ? s_r[5][w] : 0;
+    }
+    const bool finalize = !was_full;
+    const int n_surv = finalize && n_sel > 0 ? n_surv0 : 0;
+    const bool full = was_full || n_tree + n_surv + P.surv_max > P.cap;
+    const int nsel = full ? 0 : min(HT + LT, P.n_select);
+    if (a) {
+        const unsigned long long below = __lanemask_lt();
+        const int rank = h ? HB + wh + __popcll(mh & below) : HT + LB + wl + __popcll(ml & below);
+        if (rank < nsel) {
+            T.sel[rank] = (int)own;
+            if (rank == nsel - 1) T.st_next->cursor_next = (c + 1 == P.n_cells) ? 0 : c + 1;
+        }
+    }
+    if (b == 0 && threadIdx.x == 0) {
+        DevState* o = T.st_next;
+        const long long it = st->it;
+        o->sol = st->sol;
+        o->full = full ? 1 : 0;
+        o->n_sel = nsel;
+        o->n_surv = 0;
+        if (finalize) {
+            const long long nt = n_tree + n_surv;
+            kpx_iter_stats* r = &T.stats[it & (kStatsCap - 1)];
+            r->iteration = it;
+            r->n_tree = nt;
+            r->n_select = n_sel;
+            r->n_valid = st->n_valid_acc;
+            r->n_survivors = n_surv;
+            r->reserved = 0;
+            r->substeps = (long long)st->substeps_acc;
+            r->solution_key = st->sol;
+            r->t_end = wall_clock64();
+            o->n_tree = nt;
+            o->it = it + 1;
+            o->first_sol_it = (st->sol != kEmpty && st->first_sol_it < 0) ? it : st->first_sol_it;
+            o->last_n_sel = n_sel;
+            o->last_n_valid = st->n_valid_acc;
+            o->last_n_surv = n_surv;
+            o->last_substeps = (long long)st->substeps_acc;
+            o->n_valid_acc = 0;
+            o->substeps_acc = 0;
+            o->cursor = cur;
+        } else {
+            o->n_tree = n_tree;
+            o->it = it;
+            o->first_sol_it = st->first_sol_it;
+            o->last_n_sel = st->last_n_sel;
+            o->last_n_valid = st->last_n_valid;
+            o->last_n_surv = st->last_n_surv;
+            o->last_substeps = st->last_substeps;
+            o->n_valid_acc = st->n_valid_acc;
+            o->substeps_acc = st->substeps_acc;
+            o->cursor = st->cursor;
+        }
+        if (nsel == 0) o->cursor_next = cur;
+    }
 }
 
 // ------------------------------------------------------------------ solution path
@@ -924,7 +1072,8 @@ void for_each_array(const Sizes& z, F&& f)
     f("boxes", sizeof(float4) * 2 * (size_t)(z.n_boxes > 0 ? z.n_boxes : 1));
     f("gcell", sizeof(int2) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2]);
     f("glist", sizeof(uint16_t) * (size_t)(z.gb_entries > 0 ? z.gb_entries : 1));
-    f("st", sizeof(DevState));
+    f("st", 2 * sizeof(DevState));  // double-buffered by iteration parity
+    f("bcount", sizeof(int2) * (size_t)((z.n_cells + kBlock - 1) / kBlock));
     f("stats", sizeof(kpx_iter_stats) * kStatsCap);
     f("d_parent", sizeof(int) * S);
     f("d_u", sizeof(float) * z.m * S);
@@ -1261,6 +1410,7 @@ struct kpx_handle {
     std::vector<hipEvent_t> spare;
     int full_cached = 0;
     int n_prune_blocks = 0;
+    int cur = 0;                              // which device state is current
     std::string err;
 };
 
@@ -1315,6 +1465,8 @@ void carve(kpx_handle* h)
     T.gcell = (int2*)ptrs[k++];
     T.glist = (uint16_t*)ptrs[k++];
     T.st = (DevState*)ptrs[k++];
+    T.st_next = T.st + 1;
+    T.bcount = (int2*)ptrs[k++];
     T.stats = (kpx_iter_stats*)ptrs[k++];
     T.d_parent = (int*)ptrs[k++];
     T.d_u = (float*)ptrs[k++];
@@ -1338,6 +1490,8 @@ size_t total_bytes(const Sizes& z)
 DevPtrs kernel_ptrs(const kpx_handle* h)
 {
     DevPtrs T = h->T;
+    T.st = h->T.st + h->cur;
+    T.st_next = h->T.st + (h->cur ^ 1);
     if (!h->dump_on) {
         T.d_parent = nullptr;
         T.d_u = nullptr;
@@ -1438,7 +1592,8 @@ int timed_launch(kpx_handle* h, int k, F&& launch)
 int refresh_full(kpx_handle* h)
 {
     int full = 0;
-    KPX_HIP(h, hipMemcpyAsync(&full, &h->T.st->full, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipMemcpyAsync(&full, &(h->T.st + h->cur)->full, sizeof(int), hipMemcpyDeviceToHost,
+                              h->stream));
     KPX_HIP(h, hipStreamSynchronize(h->stream));
     h->full_cached = full;
     return KPX_OK;
@@ -1566,8 +1721,8 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
 {
     if (!h || n_iters < 0) return KPX_ERR_ARG;
     if (h->full_cached) return KPX_FULL;
-    const DevPtrs T = kernel_ptrs(h);
     for (int i = 0; i < n_iters; ++i) {
+        const DevPtrs T = kernel_ptrs(h);
         int rc;
         if ((rc = timed_launch(h, 0, [&] { propagate(h, T); })) != KPX_OK) return rc;
         if ((rc = timed_launch(h, 1, [&] {
@@ -1577,9 +1732,13 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
             return rc;
         if ((rc = timed_launch(h, 2, [&] { insert(h, T); })) != KPX_OK) return rc;
         if ((rc = timed_launch(h, 3, [&] {
-                 k_finalize_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, T);
+                 if (h->n_prune_blocks <= kSelBlocksMax)
+                     k_finalize_select<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(h->P, T, h->n_prune_blocks);
+                 else
+                     k_finalize_select_one<<<1, kSelectThreads, 0, h->stream>>>(h->P, T);
              })) != KPX_OK)
             return rc;
+        h->cur ^= 1;  // the state the close of this iteration wrote is current
     }
     KPX_HIP(h, hipGetLastError());
     return KPX_OK;
@@ -1597,7 +1756,7 @@ int kpx_counters_read(kpx_handle* h, kpx_counters* out)
 {
     if (!h || !out) return KPX_ERR_ARG;
     DevState s;
-    KPX_HIP(h, hipMemcpyAsync(&s, h->T.st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipMemcpyAsync(&s, h->T.st + h->cur, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     KPX_HIP(h, hipStreamSynchronize(h->stream));
     h->full_cached = s.full;
     out->n_tree = s.n_tree;
@@ -1628,9 +1787,9 @@ int kpx_solution(kpx_handle* h, kpx_solution_info* info, float* states, float* c
     info->tree_index = -1;
     if (c.solution_key == kEmpty) return KPX_OK;
     switch (h->P.dyn) {
-    case kDI6: k_extract_path<kDI6><<<1, 64, 0, h->stream>>>(h->P, h->T, kMaxPath); break;
-    case kQUAD12: k_extract_path<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, h->T, kMaxPath); break;
-    default: k_extract_path<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, h->T, kMaxPath); break;
+    case kDI6: k_extract_path<kDI6><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), kMaxPath); break;
+    case kQUAD12: k_extract_path<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), kMaxPath); break;
+    default: k_extract_path<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), kMaxPath); break;
     }
     KPX_HIP(h, hipGetLastError());
     int len = 0;
