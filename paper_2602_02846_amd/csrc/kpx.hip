@@ -95,8 +95,8 @@ struct DevPtrs {
     int2* gcell;         // box grid, per grid cell: (first list entry | count << 20,
                          // bits of the clearance radius to the boxes not listed)
     uint16_t* glist;     // box grid: box indices
-    DevState* st;        // this iteration's state (read by every kernel)
-    DevState* st_next;   // the next iteration's, written by the close of this one
+    DevState* st;        // two states, by iteration parity: the current one is read by every
+                         // kernel of an iteration and the close of the iteration writes the other
     int2* bcount;        // per block of kBlock regions: active regions at / after the cursor, before it
     kpx_iter_stats* stats;
     int* d_parent;       // dump (may be null)
@@ -132,7 +132,7 @@ __global__ void k_fill_table(unsigned long long* tbl, uint8_t* act, int n, int n
 
 // Alg. 1 lines 1-5: the root is x_init, active; its region holds (0, root).
 template <int DYN>
-__global__ void k_init_root(DevProblem P, DevPtrs T, const float* x_init)
+__global__ void k_init_root(DevProblem P, DevPtrs T, DevState* st, const float* x_init)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
@@ -154,7 +154,6 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, const float* x_init)
     T.anc[1] = make_int4(-1, -1, -1, -1);
     T.tbl[c] = 0ull;  // cost 0, id 0
     T.act[c] = 1;
-    DevState* st = T.st;
     st->n_tree = 1;
     st->it = 0;
     st->first_sol_it = -1;
@@ -200,8 +199,11 @@ __device__ __forceinline__ void stage_lds(const int4* s0, int4* d0, int n0, cons
     }
 }
 
+// One block's share of propagate: block `blk` of `nblk` working for the
+// problem P (state `st`).
 template <int DYN, int COST>
-__global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs T)
+__device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtrs& T, DevState* st, int blk,
+                                               int nblk)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
     extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | grid lists
@@ -228,13 +230,12 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs 
     stage_lds(reinterpret_cast<const int4*>(T.boxes), reinterpret_cast<int4*>(sbox), 2 * P.n_boxes,
               reinterpret_cast<const int4*>(T.gcell), reinterpret_cast<int4*>(sgc), gbp / 2,
               reinterpret_cast<const int4*>(T.glist), reinterpret_cast<int4*>(sgl), (P.gb_entries + 7) / 8);
-    DevState* st = T.st;
     const int S = st->n_sel * P.K;
     if (st->full || S == 0) return;  // kernel-uniform
-    int chunk = max(kChunkMin, (S + (int)gridDim.x - 1) / (int)gridDim.x);
+    int chunk = max(kChunkMin, (S + nblk - 1) / nblk);
     chunk = min(chunk, min(kChunkMax, (kParMax - 1) * P.K));
-    if ((int)blockIdx.x * chunk >= S) return;  // block-uniform
-    if (blockIdx.x == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
+    if (blk * chunk >= S) return;  // block-uniform
+    if (blk == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
     if (threadIdx.x < D) {
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs 
     const int lane = threadIdx.x & 63;
     int my_valid = 0, my_steps = 0;
 
-    for (int base = blockIdx.x * chunk; base < S; base += gridDim.x * chunk) {
+    for (int base = blk * chunk; base < S; base += nblk * chunk) {
         const int cnt = min(chunk, S - base);
         const int r0 = base / P.K;
         const int npar = (base + cnt - 1) / P.K - r0 + 1;
@@ -487,18 +488,24 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs 
     }
 }
 
+template <int DYN, int COST>
+__global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs T, DevState* st)
+{
+    propagate_body<DYN, COST>(P, T, st, blockIdx.x, gridDim.x);
+}
+
 // ------------------------------------------------------------------ prune + survivor flags
 
-__global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T, int n_prune_blocks)
+__device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevPtrs& T, const DevState* st,
+                                                 int blk, int n_prune_blocks)
 {
     __shared__ int s_w[kBlock / 64], s_w2[kBlock / 64];
-    DevState* st = T.st;
-    if ((int)blockIdx.x < n_prune_blocks) {
+    if (blk < n_prune_blocks) {
         // Alg. 3 for the owner of region c (every live node owns its region);
         // also records whether the region's node is active after this
         // iteration, and per block the active regions on either side of the
         // selection cursor
-        const int c = blockIdx.x * blockDim.x + threadIdx.x;
+        const int c = blk * kBlock + threadIdx.x;
         const unsigned long long key = T.tbl[min(c, P.n_cells - 1)];
         const int full = st->full, cur = st->cursor_next;
         const long long n_tree = st->n_tree;
@@ -565,12 +572,12 @@ __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T,
                 th += s_w[w];
                 tl += s_w2[w];
             }
-            T.bcount[blockIdx.x] = make_int2(th, tl);
+            T.bcount[blk] = make_int2(th, tl);
         }
         return;
     }
     // survivor mask V_U (App. A U-filter) and per-tile counts
-    const int tile = blockIdx.x - n_prune_blocks;
+    const int tile = blk - n_prune_blocks;
     const int s = tile * kTile + threadIdx.x;
     const int sc = min(s, P.s_max - 1);
     const uint8_t fl = T.cflag[sc];
@@ -593,6 +600,12 @@ __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T,
         for (int w = 0; w < kBlock / 64; ++w) total += s_w[w];
         T.tile_count[tile] = total;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T, const DevState* st,
+                                                        int n_prune_blocks)
+{
+    prune_flags_body(P, T, st, blockIdx.x, n_prune_blocks);
 }
 
 // Exclusive scan of three ints per thread over the block, with the totals.
@@ -634,8 +647,8 @@ __device__ __forceinline__ void block_scan3(int (&v)[3], int (&ex)[3], int (&tot
 // owns a run of whole 4-region words of the activity bytes (0/1, zero-padded
 // past the last region).  The survivor count and the two cursor-split counts
 // of active regions share one block scan.
-__device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, DevState& q, bool finalize,
-                                    int (*s_w)[16], int* s_sel, DevState* out)
+__device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, const DevState* in, DevState& q,
+                                    bool finalize, int (*s_w)[16], int* s_sel, DevState* out)
 {
     // every load of the block is in flight before the first barrier
     const int t0 = T.tile_count[min((int)threadIdx.x, P.n_tiles - 1)];
@@ -647,7 +660,7 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, DevSt
     uint32_t wd[kSelWords];
 #pragma unroll
     for (int i = 0; i < kSelWords; ++i) wd[i] = act[min(w0 + i, nwords - 1)];
-    if (threadIdx.x == 0) q = *T.st;
+    if (threadIdx.x == 0) q = *in;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSelWords; ++i) wd[i] = w0 + i < w1 ? wd[i] & 0x01010101u : 0u;
@@ -761,12 +774,12 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, DevSt
 }
 
 // Selection alone (after create).
-__global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs T)
+__global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs T, DevState* st)
 {
     __shared__ int s_w[3][16];
     __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
-    finalize_and_select(P, T, s_st, false, s_w, s_sel, T.st);
+    finalize_and_select(P, T, st, s_st, false, s_w, s_sel, st);
 }
 
 // ------------------------------------------------------------------ insert
@@ -776,11 +789,11 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs
 // counts of the earlier tiles, this slot's flag and candidate record, its
 // parent); one barrier then gives each survivor its rank.
 template <int DYN>
-__global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
+__device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& T, DevState* st, int blk)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
     __shared__ int s_w[2][kBlock / 64];
-    const int tile = blockIdx.x;
+    const int tile = blk;
     const int s = tile * kTile + threadIdx.x;
     const int sc = min(s, P.s_max - 1);
     int pre = 0;
@@ -795,7 +808,6 @@ __global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
     const int c = T.ccell[sc];
     const uint8_t flag = T.cflag[sc];
     const int par = T.sel[sc / P.K];
-    DevState* st = T.st;
     const int full = st->full, n_sel = st->n_sel;
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
@@ -854,14 +866,21 @@ __global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T)
     }
 }
 
+template <int DYN>
+__global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T, DevState* st)
+{
+    insert_body<DYN>(P, T, st, blockIdx.x);
+}
+
 // Closes the iteration and selects the next iteration's nodes in one block
 // (regions in more blocks than the many-block kernel below handles).
-__global__ __launch_bounds__(kSelectThreads) void k_finalize_select_one(DevProblem P, DevPtrs T)
+__global__ __launch_bounds__(kSelectThreads) void k_finalize_select_one(DevProblem P, DevPtrs T, const DevState* st,
+                                                                       DevState* st_next)
 {
     __shared__ int s_w[3][16];
     __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
-    finalize_and_select(P, T, s_st, true, s_w, s_sel, T.st_next);
+    finalize_and_select(P, T, st, s_st, true, s_w, s_sel, st_next);
 }
 
 // Closes the iteration and selects the next iteration's nodes with one block
@@ -871,12 +890,12 @@ __global__ __launch_bounds__(kSelectThreads) void k_finalize_select_one(DevProbl
 // state and writes the next one, so no block sees another's update; block 0
 // writes everything but the cursor past the last selected region, which the
 // thread holding that rank writes.
-__global__ __launch_bounds__(kBlock) void k_finalize_select(DevProblem P, DevPtrs T, int nb)
+__device__ __forceinline__ void finalize_select_body(const DevProblem& P, const DevPtrs& T, const DevState* st,
+                                                     DevState* st_next, int blk, int nb)
 {
     constexpr int NW = kBlock / 64;
     __shared__ int s_r[6][NW];
-    const DevState* st = T.st;
-    const int b = blockIdx.x, c = b * kBlock + threadIdx.x;
+    const int b = blk, c = b * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     // every load first: this thread's region and owner, the block counts, the state
     const int cc = min(c, P.n_cells - 1);
@@ -934,11 +953,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize_select(DevProblem P, DevPtr
         const int rank = h ? HB + wh + __popcll(mh & below) : HT + LB + wl + __popcll(ml & below);
         if (rank < nsel) {
             T.sel[rank] = (int)own;
-            if (rank == nsel - 1) T.st_next->cursor_next = (c + 1 == P.n_cells) ? 0 : c + 1;
+            if (rank == nsel - 1) st_next->cursor_next = (c + 1 == P.n_cells) ? 0 : c + 1;
         }
     }
     if (b == 0 && threadIdx.x == 0) {
-        DevState* o = T.st_next;
+        DevState* o = st_next;
         const long long it = st->it;
         o->sol = st->sol;
         o->full = full ? 1 : 0;
@@ -982,14 +1001,20 @@ __global__ __launch_bounds__(kBlock) void k_finalize_select(DevProblem P, DevPtr
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_finalize_select(DevProblem P, DevPtrs T, const DevState* st,
+                                                            DevState* st_next, int nb)
+{
+    finalize_select_body(P, T, st, st_next, blockIdx.x, nb);
+}
+
 // ------------------------------------------------------------------ solution path
 
 template <int DYN>
-__global__ void k_extract_path(DevProblem P, DevPtrs T, int max_nodes)
+__global__ void k_extract_path(DevProblem P, DevPtrs T, const DevState* st, int max_nodes)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
-    const unsigned long long sol = T.st->sol;
+    const unsigned long long sol = st->sol;
     if (sol == kEmpty) {
         *T.path_len = 0;
         return;
@@ -1465,7 +1490,6 @@ void carve(kpx_handle* h)
     T.gcell = (int2*)ptrs[k++];
     T.glist = (uint16_t*)ptrs[k++];
     T.st = (DevState*)ptrs[k++];
-    T.st_next = T.st + 1;
     T.bcount = (int2*)ptrs[k++];
     T.stats = (kpx_iter_stats*)ptrs[k++];
     T.d_parent = (int*)ptrs[k++];
@@ -1487,11 +1511,12 @@ size_t total_bytes(const Sizes& z)
     return o;
 }
 
+DevState* cur_state(const kpx_handle* h) { return h->T.st + h->cur; }
+DevState* next_state(const kpx_handle* h) { return h->T.st + (h->cur ^ 1); }
+
 DevPtrs kernel_ptrs(const kpx_handle* h)
 {
     DevPtrs T = h->T;
-    T.st = h->T.st + h->cur;
-    T.st_next = h->T.st + (h->cur ^ 1);
     if (!h->dump_on) {
         T.d_parent = nullptr;
         T.d_u = nullptr;
@@ -1513,7 +1538,7 @@ template <int DYN, int COST>
 void launch_propagate(kpx_handle* h, const DevPtrs& T)
 {
     k_propagate<DYN, COST><<<h->P.n_cu, kPropBlock, propagate_lds_bytes(h->z, Dims<DYN>::D), h->stream>>>(
-        h->P, T);
+        h->P, T, cur_state(h));
 }
 
 template <int DYN, int COST>
@@ -1553,9 +1578,9 @@ void insert(kpx_handle* h, const DevPtrs& T)
 {
     const int grid = h->z.n_tiles;
     switch (h->P.dyn) {
-    case kDI6: k_insert<kDI6><<<grid, kBlock, 0, h->stream>>>(h->P, T); break;
-    case kQUAD12: k_insert<kQUAD12><<<grid, kBlock, 0, h->stream>>>(h->P, T); break;
-    default: k_insert<kDUBINS6><<<grid, kBlock, 0, h->stream>>>(h->P, T); break;
+    case kDI6: k_insert<kDI6><<<grid, kBlock, 0, h->stream>>>(h->P, T, cur_state(h)); break;
+    case kQUAD12: k_insert<kQUAD12><<<grid, kBlock, 0, h->stream>>>(h->P, T, cur_state(h)); break;
+    default: k_insert<kDUBINS6><<<grid, kBlock, 0, h->stream>>>(h->P, T, cur_state(h)); break;
     }
 }
 
@@ -1592,8 +1617,7 @@ int timed_launch(kpx_handle* h, int k, F&& launch)
 int refresh_full(kpx_handle* h)
 {
     int full = 0;
-    KPX_HIP(h, hipMemcpyAsync(&full, &(h->T.st + h->cur)->full, sizeof(int), hipMemcpyDeviceToHost,
-                              h->stream));
+    KPX_HIP(h, hipMemcpyAsync(&full, &cur_state(h)->full, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     KPX_HIP(h, hipStreamSynchronize(h->stream));
     h->full_cached = full;
     return KPX_OK;
@@ -1706,11 +1730,11 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
     k_fill_table<<<std::min(1024, (z.n_act + kBlock - 1) / kBlock), kBlock, 0, h->stream>>>(
         h->T.tbl, h->T.act, z.n_cells, z.n_act);
     switch (h->P.dyn) {
-    case kDI6: k_init_root<kDI6><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
-    case kQUAD12: k_init_root<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
-    default: k_init_root<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, h->T, xi); break;
+    case kDI6: k_init_root<kDI6><<<1, 64, 0, h->stream>>>(h->P, h->T, h->T.st, xi); break;
+    case kQUAD12: k_init_root<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, h->T, h->T.st, xi); break;
+    default: k_init_root<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, h->T, h->T.st, xi); break;
     }
-    k_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, h->T);
+    k_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, h->T, h->T.st);
     if (hipGetLastError() != hipSuccess) return cleanup(KPX_ERR_DEVICE);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(KPX_ERR_DEVICE);
     *out = h;
@@ -1727,15 +1751,17 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
         if ((rc = timed_launch(h, 0, [&] { propagate(h, T); })) != KPX_OK) return rc;
         if ((rc = timed_launch(h, 1, [&] {
                  k_prune_flags<<<h->n_prune_blocks + h->z.n_tiles, kBlock, 0, h->stream>>>(
-                     h->P, T, h->n_prune_blocks);
+                     h->P, T, cur_state(h), h->n_prune_blocks);
              })) != KPX_OK)
             return rc;
         if ((rc = timed_launch(h, 2, [&] { insert(h, T); })) != KPX_OK) return rc;
         if ((rc = timed_launch(h, 3, [&] {
                  if (h->n_prune_blocks <= kSelBlocksMax)
-                     k_finalize_select<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(h->P, T, h->n_prune_blocks);
+                     k_finalize_select<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
+                         h->P, T, cur_state(h), next_state(h), h->n_prune_blocks);
                  else
-                     k_finalize_select_one<<<1, kSelectThreads, 0, h->stream>>>(h->P, T);
+                     k_finalize_select_one<<<1, kSelectThreads, 0, h->stream>>>(h->P, T, cur_state(h),
+                                                                                next_state(h));
              })) != KPX_OK)
             return rc;
         h->cur ^= 1;  // the state the close of this iteration wrote is current
@@ -1756,7 +1782,7 @@ int kpx_counters_read(kpx_handle* h, kpx_counters* out)
 {
     if (!h || !out) return KPX_ERR_ARG;
     DevState s;
-    KPX_HIP(h, hipMemcpyAsync(&s, h->T.st + h->cur, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    KPX_HIP(h, hipMemcpyAsync(&s, cur_state(h), sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     KPX_HIP(h, hipStreamSynchronize(h->stream));
     h->full_cached = s.full;
     out->n_tree = s.n_tree;
@@ -1787,9 +1813,9 @@ int kpx_solution(kpx_handle* h, kpx_solution_info* info, float* states, float* c
     info->tree_index = -1;
     if (c.solution_key == kEmpty) return KPX_OK;
     switch (h->P.dyn) {
-    case kDI6: k_extract_path<kDI6><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), kMaxPath); break;
-    case kQUAD12: k_extract_path<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), kMaxPath); break;
-    default: k_extract_path<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), kMaxPath); break;
+    case kDI6: k_extract_path<kDI6><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), cur_state(h), kMaxPath); break;
+    case kQUAD12: k_extract_path<kQUAD12><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), cur_state(h), kMaxPath); break;
+    default: k_extract_path<kDUBINS6><<<1, 64, 0, h->stream>>>(h->P, kernel_ptrs(h), cur_state(h), kMaxPath); break;
     }
     KPX_HIP(h, hipGetLastError());
     int len = 0;
