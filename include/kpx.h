@@ -282,6 +282,40 @@ const char* kpx_status_string(int status);
 /* Message for the last failing call on h (empty string if none). */
 const char* kpx_last_error(const kpx_handle* h);
 
+/* ---------------------------------------------------------------- batches
+ * Independent queries (handles made by kpx_create, any mix of models, sizes,
+ * obstacle sets and capacities) iterated together: each kernel of an
+ * iteration is launched once for all the queries (once per robot model and
+ * cost for propagate and insert), so that small queries share the GPU.  Every
+ * query computes exactly what kpx_iterate would compute for it alone. */
+typedef struct kpx_batch kpx_batch;
+
+/* Groups n host-array handles (not copied; the caller keeps them alive and
+ * destroys them after the batch).  They must be distinct, share one stream,
+ * have run the same number of iterations modulo 2, have candidate recording
+ * off, and have at most 262144 regions each.  KPX_ERR_ARG otherwise;
+ * KPX_ERR_OOM / KPX_ERR_DEVICE on allocation or runtime failure. */
+int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out);
+
+/* enable = 1: kpx_batch_iterate replays HIP graphs of two iterations
+ * (captured on first use on the batch's own stream); 0: plain launches.
+ * KPX_ERR_ARG for other values. */
+int kpx_batch_set_graph(kpx_batch* b, int32_t enable);
+
+/* Enqueues n_iters iterations of every query, ordered after the work already
+ * on the handles' stream and before any later work on it; returns at once.
+ * A query whose tree is full stops changing, as with kpx_iterate; each
+ * handle's kpx_sync reports it.  KPX_ERR_STATE if a handle was iterated on
+ * its own since the batch was made (an odd number of times). */
+int kpx_batch_iterate(kpx_batch* b, int32_t n_iters);
+
+/* Waits for the batch's work and releases what the batch allocated (not the
+ * handles).  NULL is ok. */
+int kpx_batch_destroy(kpx_batch* b);
+
+/* Message for the last failing call on b (empty string if none). */
+const char* kpx_batch_last_error(const kpx_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

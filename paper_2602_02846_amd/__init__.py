@@ -5,6 +5,6 @@ include/kpx.h); this package only marshals arguments to it.
 """
 
 from .kpx import (  # noqa: F401
-    ACTIVE, INACTIVE, TERMINAL, KPXError, Planner, lib, philox, workspace_bytes,
+    ACTIVE, INACTIVE, TERMINAL, Batch, KPXError, Planner, lib, philox, workspace_bytes,
     status_string, OK, FULL,
 )

@@ -1007,6 +1007,102 @@ __global__ __launch_bounds__(kBlock) void k_finalize_select(DevProblem P, DevPtr
     finalize_select_body(P, T, st, st_next, blockIdx.x, nb);
 }
 
+// ------------------------------------------------------------------ batches of queries
+
+// A batch runs the iterations of independent queries together.  Each launch
+// covers the blocks of every query (of one robot model and cost, for the
+// kernels that depend on them), and block b finds its query and its place
+// among that query's blocks in a map: (query, block, blocks of the query,
+// region blocks of the query).  The per-query problems and trees sit in
+// device arrays; `par` is the state parity all the queries share.
+// The batched kernels read each query's pointers from device memory, where
+// the compiler cannot see that they address global memory, and would make
+// every access through them a generic one.  Rebuilding each pointer from its
+// integer value in the global address space makes them global accesses.
+template <typename V>
+__device__ __forceinline__ V* as_global(V* p)
+{
+    return (V*)(__attribute__((address_space(1))) V*)(uintptr_t)p;
+}
+
+__device__ __forceinline__ DevPtrs global_ptrs(const DevPtrs& src)
+{
+    DevPtrs T = src;
+    T.x = as_global(T.x);
+    T.u = as_global(T.u);
+    T.steps = as_global(T.steps);
+    T.parent = as_global(T.parent);
+    T.cost = as_global(T.cost);
+    T.cell = as_global(T.cell);
+    T.status = as_global(T.status);
+    T.icount = as_global(T.icount);
+    T.dead = as_global(T.dead);
+    T.anc = as_global(T.anc);
+    T.tbl = as_global(T.tbl);
+    T.sel = as_global(T.sel);
+    T.ckey = as_global(T.ckey);
+    T.ccell = as_global(T.ccell);
+    T.cx = as_global(T.cx);
+    T.cflag = as_global(T.cflag);
+    T.csurv = as_global(T.csurv);
+    T.tile_count = as_global(T.tile_count);
+    T.act = as_global(T.act);
+    T.boxes = as_global(T.boxes);
+    T.gcell = as_global(T.gcell);
+    T.glist = as_global(T.glist);
+    T.st = as_global(T.st);
+    T.bcount = as_global(T.bcount);
+    T.stats = as_global(T.stats);
+    T.d_parent = as_global(T.d_parent);
+    T.d_u = as_global(T.d_u);
+    T.d_n = as_global(T.d_n);
+    T.d_fi = as_global(T.d_fi);
+    T.path = as_global(T.path);
+    T.path_x = as_global(T.path_x);
+    T.path_u = as_global(T.path_u);
+    T.path_n = as_global(T.path_n);
+    T.path_len = as_global(T.path_len);
+    T.x_init = as_global(T.x_init);
+    return T;
+}
+
+template <int DYN, int COST>
+__global__ __launch_bounds__(kPropBlock) void kb_propagate(const DevProblem* __restrict__ Ps,
+                                                         const DevPtrs* __restrict__ Ts,
+                                                         const int4* __restrict__ map, int par)
+{
+    const int4 m = map[blockIdx.x];
+    const DevPtrs T = global_ptrs(Ts[m.x]);
+    propagate_body<DYN, COST>(Ps[m.x], T, T.st + par, m.y, m.z);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_prune_flags(const DevProblem* __restrict__ Ps,
+                                                         const DevPtrs* __restrict__ Ts,
+                                                         const int4* __restrict__ map, int par)
+{
+    const int4 m = map[blockIdx.x];
+    const DevPtrs T = global_ptrs(Ts[m.x]);
+    prune_flags_body(Ps[m.x], T, T.st + par, m.y, m.w);
+}
+
+template <int DYN>
+__global__ __launch_bounds__(kBlock) void kb_insert(const DevProblem* __restrict__ Ps, const DevPtrs* __restrict__ Ts,
+                                                    const int4* __restrict__ map, int par)
+{
+    const int4 m = map[blockIdx.x];
+    const DevPtrs T = global_ptrs(Ts[m.x]);
+    insert_body<DYN>(Ps[m.x], T, T.st + par, m.y);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_finalize_select(const DevProblem* __restrict__ Ps,
+                                                             const DevPtrs* __restrict__ Ts,
+                                                             const int4* __restrict__ map, int par)
+{
+    const int4 m = map[blockIdx.x];
+    const DevPtrs T = global_ptrs(Ts[m.x]);
+    finalize_select_body(Ps[m.x], T, T.st + par, T.st + (par ^ 1), m.y, m.w);
+}
+
 // ------------------------------------------------------------------ solution path
 
 template <int DYN>
@@ -1541,23 +1637,29 @@ void launch_propagate(kpx_handle* h, const DevPtrs& T)
         h->P, T, cur_state(h));
 }
 
-template <int DYN, int COST>
-hipError_t set_lds(kpx_handle* h)
+// Allows `dynamic` bytes of dynamic LDS for a propagate kernel, after checking
+// that they fit beside its static LDS: KPX_OK, KPX_ERR_ARG (too large) or
+// KPX_ERR_DEVICE.
+int allow_lds(const void* kernel, size_t dynamic, int lds_max)
 {
-    return hipFuncSetAttribute((const void*)k_propagate<DYN, COST>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)propagate_lds_bytes(h->z, Dims<DYN>::D));
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) return KPX_ERR_DEVICE;
+    if (fa.sharedSizeBytes + dynamic > (size_t)lds_max) return KPX_ERR_ARG;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic) != hipSuccess)
+        return KPX_ERR_DEVICE;
+    return KPX_OK;
 }
 
-hipError_t set_propagate_lds(kpx_handle* h)
+// The propagate kernel for a (model, cost) pair, single-query or batched.
+const void* propagate_kernel(int dyn, int cost, bool batched)
 {
-    switch (h->P.dyn * 2 + h->P.cost) {
-    case 0: return set_lds<kDI6, kTIME>(h);
-    case 1: return set_lds<kDI6, kPATH>(h);
-    case 2: return set_lds<kQUAD12, kTIME>(h);
-    case 3: return set_lds<kQUAD12, kPATH>(h);
-    case 4: return set_lds<kDUBINS6, kTIME>(h);
-    default: return set_lds<kDUBINS6, kPATH>(h);
+    switch (dyn * 2 + cost) {
+    case 0: return batched ? (const void*)kb_propagate<kDI6, kTIME> : (const void*)k_propagate<kDI6, kTIME>;
+    case 1: return batched ? (const void*)kb_propagate<kDI6, kPATH> : (const void*)k_propagate<kDI6, kPATH>;
+    case 2: return batched ? (const void*)kb_propagate<kQUAD12, kTIME> : (const void*)k_propagate<kQUAD12, kTIME>;
+    case 3: return batched ? (const void*)kb_propagate<kQUAD12, kPATH> : (const void*)k_propagate<kQUAD12, kPATH>;
+    case 4: return batched ? (const void*)kb_propagate<kDUBINS6, kTIME> : (const void*)k_propagate<kDUBINS6, kTIME>;
+    default: return batched ? (const void*)kb_propagate<kDUBINS6, kPATH> : (const void*)k_propagate<kDUBINS6, kPATH>;
     }
 }
 
@@ -1625,6 +1727,110 @@ int refresh_full(kpx_handle* h)
 
 }  // namespace
 
+// ============================================================== batches
+
+// Independent queries iterated together (see the batched kernels).  The batch
+// keeps only the per-query problem and pointer arrays, the block maps and,
+// optionally, HIP graphs of two iterations; the queries stay in their handles.
+struct kpx_batch {
+    std::vector<kpx_handle*> hs;
+    hipStream_t user = nullptr;     // the handles' stream
+    hipStream_t stream = nullptr;   // the batch's own stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    void* mem = nullptr;            // problems | pointers | block maps
+    DevProblem* d_P = nullptr;
+    DevPtrs* d_T = nullptr;
+    struct Group {
+        int dyn = 0, cost = 0;
+        int4* prop = nullptr;
+        int n_prop = 0;
+        size_t lds = 0;
+        int4* ins = nullptr;
+        int n_ins = 0;
+    };
+    std::vector<Group> groups;
+    int4* prune = nullptr;
+    int n_prune = 0;
+    int4* fin = nullptr;
+    int n_fin = 0;
+    int cur = 0;
+    bool graph_on = false;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // two iterations from state parity 0 / 1
+    std::string err;
+};
+
+namespace {
+
+int bfail(kpx_batch* b, int code, const std::string& msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+template <int DYN, int COST>
+void kb_propagate_launch(const kpx_batch* b, const kpx_batch::Group& g, int par)
+{
+    kb_propagate<DYN, COST><<<g.n_prop, kPropBlock, g.lds, b->stream>>>(b->d_P, b->d_T, g.prop, par);
+}
+
+// Enqueues one iteration of every query on the batch stream, at state parity par.
+void batch_enqueue(const kpx_batch* b, int par)
+{
+    for (const auto& g : b->groups) {
+        switch (g.dyn * 2 + g.cost) {
+        case 0: kb_propagate_launch<kDI6, kTIME>(b, g, par); break;
+        case 1: kb_propagate_launch<kDI6, kPATH>(b, g, par); break;
+        case 2: kb_propagate_launch<kQUAD12, kTIME>(b, g, par); break;
+        case 3: kb_propagate_launch<kQUAD12, kPATH>(b, g, par); break;
+        case 4: kb_propagate_launch<kDUBINS6, kTIME>(b, g, par); break;
+        default: kb_propagate_launch<kDUBINS6, kPATH>(b, g, par); break;
+        }
+    }
+    kb_prune_flags<<<b->n_prune, kBlock, 0, b->stream>>>(b->d_P, b->d_T, b->prune, par);
+    for (const auto& g : b->groups) {
+        switch (g.dyn) {
+        case kDI6: kb_insert<kDI6><<<g.n_ins, kBlock, 0, b->stream>>>(b->d_P, b->d_T, g.ins, par); break;
+        case kQUAD12: kb_insert<kQUAD12><<<g.n_ins, kBlock, 0, b->stream>>>(b->d_P, b->d_T, g.ins, par); break;
+        default: kb_insert<kDUBINS6><<<g.n_ins, kBlock, 0, b->stream>>>(b->d_P, b->d_T, g.ins, par); break;
+        }
+    }
+    kb_finalize_select<<<b->n_fin, kBlock, 0, b->stream>>>(b->d_P, b->d_T, b->fin, par);
+}
+
+// Captures two iterations starting at parity p into b->exec[p].
+int batch_capture(kpx_batch* b, int p)
+{
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bfail(b, KPX_ERR_DEVICE, "hipStreamBeginCapture failed");
+    batch_enqueue(b, p);
+    batch_enqueue(b, p ^ 1);
+    if (hipStreamEndCapture(b->stream, &g) != hipSuccess || !g)
+        return bfail(b, KPX_ERR_DEVICE, "hipStreamEndCapture failed");
+    const hipError_t e = hipGraphInstantiate(&b->exec[p], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->exec[p] = nullptr;
+        return bfail(b, KPX_ERR_DEVICE, "hipGraphInstantiate failed");
+    }
+    return KPX_OK;
+}
+
+void batch_free(kpx_batch* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto& e : b->exec)
+        if (e) (void)hipGraphExecDestroy(e);
+    if (b->mem) (void)hipFree(b->mem);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // namespace
+
 // ============================================================== C ABI
 
 extern "C" {
@@ -1670,15 +1876,10 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
             return KPX_ERR_DEVICE;
         }
         h->P.n_cu = std::max(1, n_cu);
-        const size_t static_lds = sizeof(float) * KPX_MAX_CONTROL * kChunkMax + 3 * 2 * kChunkMax +
-                                  sizeof(float) * kChunkMax + sizeof(int) * (kSortBins + 1);
-        if (propagate_lds_bytes(z, z.d) + static_lds > (size_t)lds_max) {
+        const int rc = allow_lds(propagate_kernel(h->P.dyn, h->P.cost, false), propagate_lds_bytes(z, z.d), lds_max);
+        if (rc != KPX_OK) {
             delete h;
-            return KPX_ERR_ARG;
-        }
-        if (set_propagate_lds(h) != hipSuccess) {
-            delete h;
-            return KPX_ERR_DEVICE;
+            return rc;
         }
     }
     if (workspace) {
@@ -2073,6 +2274,155 @@ const char* kpx_status_string(int status)
 const char* kpx_last_error(const kpx_handle* h)
 {
     return h ? h->err.c_str() : "";
+}
+
+int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
+{
+    if (!handles || n < 1 || !out) return KPX_ERR_ARG;
+    *out = nullptr;
+    for (int q = 0; q < n; ++q) {
+        const kpx_handle* h = handles[q];
+        if (!h || h->stream != handles[0]->stream || h->cur != handles[0]->cur || h->dump_on ||
+            h->n_prune_blocks > kSelBlocksMax)
+            return KPX_ERR_ARG;
+        for (int r = 0; r < q; ++r)
+            if (handles[r] == h) return KPX_ERR_ARG;
+    }
+    kpx_batch* b = new (std::nothrow) kpx_batch;
+    if (!b) return KPX_ERR_OOM;
+    b->hs.assign(handles, handles + n);
+    b->user = handles[0]->stream;
+    b->cur = handles[0]->cur;
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        batch_free(b);
+        return KPX_ERR_DEVICE;
+    }
+    // block maps: (query, block, blocks of the query, region blocks of the query)
+    std::vector<int4> prune, fin;
+    std::vector<std::vector<int4>> prop, ins;
+    for (int q = 0; q < n; ++q) {
+        const kpx_handle* h = handles[q];
+        int gi = -1;
+        for (size_t i = 0; i < b->groups.size(); ++i)
+            if (b->groups[i].dyn == h->P.dyn && b->groups[i].cost == h->P.cost) gi = (int)i;
+        if (gi < 0) {
+            kpx_batch::Group g;
+            g.dyn = h->P.dyn;
+            g.cost = h->P.cost;
+            b->groups.push_back(g);
+            prop.emplace_back();
+            ins.emplace_back();
+            gi = (int)b->groups.size() - 1;
+        }
+        auto& g = b->groups[gi];
+        g.lds = std::max(g.lds, propagate_lds_bytes(h->z, h->z.d));
+        // propagate: about two slots per lane, at most one block per compute unit
+        const int np = std::max(1, std::min(h->P.n_cu, (h->z.s_max + 2 * kPropBlock - 1) / (2 * kPropBlock)));
+        for (int k = 0; k < np; ++k) prop[gi].push_back(make_int4(q, k, np, h->n_prune_blocks));
+        for (int k = 0; k < h->z.n_tiles; ++k) ins[gi].push_back(make_int4(q, k, h->z.n_tiles, h->n_prune_blocks));
+        const int npf = h->n_prune_blocks + h->z.n_tiles;
+        for (int k = 0; k < npf; ++k) prune.push_back(make_int4(q, k, npf, h->n_prune_blocks));
+        for (int k = 0; k < h->n_prune_blocks; ++k) fin.push_back(make_int4(q, k, h->n_prune_blocks, h->n_prune_blocks));
+    }
+    for (auto& g : b->groups) {
+        const int rc = allow_lds(propagate_kernel(g.dyn, g.cost, true), g.lds, lds_max);
+        if (rc != KPX_OK) {
+            batch_free(b);
+            return rc;
+        }
+    }
+    size_t n4 = prune.size() + fin.size();
+    for (size_t i = 0; i < b->groups.size(); ++i) n4 += prop[i].size() + ins[i].size();
+    const size_t bytes = align_up(sizeof(DevProblem) * n) + align_up(sizeof(DevPtrs) * n) + sizeof(int4) * n4;
+    if (hipMalloc(&b->mem, bytes) != hipSuccess) {
+        b->mem = nullptr;
+        batch_free(b);
+        return KPX_ERR_OOM;
+    }
+    char* m = (char*)b->mem;
+    b->d_P = (DevProblem*)m;
+    b->d_T = (DevPtrs*)(m + align_up(sizeof(DevProblem) * n));
+    int4* maps = (int4*)(m + align_up(sizeof(DevProblem) * n) + align_up(sizeof(DevPtrs) * n));
+    std::vector<DevProblem> hp(n);
+    std::vector<DevPtrs> ht(n);
+    for (int q = 0; q < n; ++q) {
+        hp[q] = handles[q]->P;
+        ht[q] = kernel_ptrs(handles[q]);
+    }
+    std::vector<int4> all;
+    all.reserve(n4);
+    auto place = [&](std::vector<int4>& v, int4*& dst, int& count) {
+        dst = maps + all.size();
+        count = (int)v.size();
+        all.insert(all.end(), v.begin(), v.end());
+    };
+    place(prune, b->prune, b->n_prune);
+    place(fin, b->fin, b->n_fin);
+    for (size_t i = 0; i < b->groups.size(); ++i) {
+        place(prop[i], b->groups[i].prop, b->groups[i].n_prop);
+        place(ins[i], b->groups[i].ins, b->groups[i].n_ins);
+    }
+    if (hipMemcpy(b->d_P, hp.data(), sizeof(DevProblem) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_T, ht.data(), sizeof(DevPtrs) * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(maps, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        batch_free(b);
+        return KPX_ERR_DEVICE;
+    }
+    *out = b;
+    return KPX_OK;
+}
+
+int kpx_batch_set_graph(kpx_batch* b, int32_t enable)
+{
+    if (!b || (enable != 0 && enable != 1)) return KPX_ERR_ARG;
+    b->graph_on = enable == 1;
+    return KPX_OK;
+}
+
+int kpx_batch_iterate(kpx_batch* b, int32_t n_iters)
+{
+    if (!b || n_iters < 0) return KPX_ERR_ARG;
+    for (kpx_handle* h : b->hs)
+        if (h->cur != b->cur || h->dump_on) return bfail(b, KPX_ERR_STATE, "a handle left the batch's step");
+    if (n_iters == 0) return KPX_OK;
+    // order the batch stream after the work already on the handles' stream
+    if (hipEventRecord(b->ev_in, b->user) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess)
+        return bfail(b, KPX_ERR_DEVICE, "stream ordering failed");
+    int i = 0;
+    if (b->graph_on) {
+        for (; i + 2 <= n_iters; i += 2) {
+            if (!b->exec[b->cur]) {
+                const int rc = batch_capture(b, b->cur);
+                if (rc != KPX_OK) return rc;
+            }
+            if (hipGraphLaunch(b->exec[b->cur], b->stream) != hipSuccess)
+                return bfail(b, KPX_ERR_DEVICE, "hipGraphLaunch failed");
+        }
+    }
+    for (; i < n_iters; ++i) batch_enqueue(b, b->cur ^ (i & 1));
+    // parity after n_iters iterations
+    if (n_iters & 1) b->cur ^= 1;
+    for (kpx_handle* h : b->hs) h->cur = b->cur;
+    if (hipGetLastError() != hipSuccess) return bfail(b, KPX_ERR_DEVICE, "a batched launch failed");
+    if (hipEventRecord(b->ev_out, b->stream) != hipSuccess || hipStreamWaitEvent(b->user, b->ev_out, 0) != hipSuccess)
+        return bfail(b, KPX_ERR_DEVICE, "stream ordering failed");
+    return KPX_OK;
+}
+
+int kpx_batch_destroy(kpx_batch* b)
+{
+    batch_free(b);
+    return KPX_OK;
+}
+
+const char* kpx_batch_last_error(const kpx_batch* b)
+{
+    return b ? b->err.c_str() : "";
 }
 
 }  // extern "C"

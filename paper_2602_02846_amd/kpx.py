@@ -134,10 +134,18 @@ def lib():
         L.kpx_status_string.restype = C.c_char_p
         L.kpx_last_error.argtypes = [_vp]
         L.kpx_last_error.restype = C.c_char_p
+        L.kpx_batch_create.argtypes = [C.POINTER(_vp), i32, C.POINTER(_vp)]
+        L.kpx_batch_set_graph.argtypes = [_vp, i32]
+        L.kpx_batch_iterate.argtypes = [_vp, i32]
+        L.kpx_batch_destroy.argtypes = [_vp]
+        L.kpx_batch_last_error.argtypes = [_vp]
+        L.kpx_batch_last_error.restype = C.c_char_p
         for name in ("kpx_workspace_bytes", "kpx_create", "kpx_iterate", "kpx_sync",
                      "kpx_counters_read", "kpx_solution", "kpx_snapshot", "kpx_set_dump",
                      "kpx_read_dump", "kpx_set_timing", "kpx_read_timing", "kpx_stats_capacity",
-                     "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy"):
+                     "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy",
+                     "kpx_batch_create", "kpx_batch_set_graph", "kpx_batch_iterate",
+                     "kpx_batch_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -376,3 +384,45 @@ class Planner:
         r = C.c_int64(0)
         self._check(lib().kpx_clock_rate_khz(self.h, C.byref(r)))
         return int(r.value)
+
+
+class Batch:
+    """Independent planning queries (Planner objects on one stream) iterated
+    together by the batched kernels; each planner keeps its own tree, and its
+    methods (counters, snapshot, solution) read it as before."""
+
+    def __init__(self, planners, graph: bool = False):
+        self.planners = list(planners)
+        arr = (_vp * len(self.planners))(*[p.h for p in self.planners])
+        b = _vp()
+        rc = lib().kpx_batch_create(arr, len(self.planners), C.byref(b))
+        if rc != OK:
+            raise KPXError(rc)
+        self.b = b
+        self.set_graph(graph)
+
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            msg = lib().kpx_batch_last_error(self.b).decode() if getattr(self, "b", None) else ""
+            raise KPXError(rc, msg)
+        return rc
+
+    def set_graph(self, enable: bool = True):
+        self._check(lib().kpx_batch_set_graph(self.b, 1 if enable else 0))
+
+    def iterate(self, n: int = 1) -> int:
+        return self._check(lib().kpx_batch_iterate(self.b, int(n)))
+
+    def sync(self):
+        return [p.sync() for p in self.planners]
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().kpx_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

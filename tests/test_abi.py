@@ -87,3 +87,7 @@ def test_null_arguments(kpx):
     assert L.kpx_destroy(None) == 0
     out = ctypes.c_size_t(0)
     assert L.kpx_workspace_bytes(None, None, ctypes.byref(out)) == -1
+    assert L.kpx_batch_create(None, 0, None) == -1
+    assert L.kpx_batch_set_graph(None, 1) == -1
+    assert L.kpx_batch_iterate(None, 1) == -1
+    assert L.kpx_batch_destroy(None) == 0

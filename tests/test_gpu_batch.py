@@ -1,0 +1,92 @@
+"""Batched queries through the C ABI: each query of a batch computes exactly
+what it computes alone (whose parity with the oracle the other GPU tests
+establish), with plain launches and with replayed HIP graphs."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("state", "control", "steps", "parent", "cost", "cell", "status", "icount", "cell_table")
+
+
+@pytest.fixture(scope="module")
+def kpx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_02846_amd as K
+
+    K.lib()
+    return K
+
+
+def _small_batch(n, seed, n_select_max=300):
+    ws = W.batch_workloads(seed, n)
+    for w in ws:  # test-sized: fewer nodes per iteration, same scenes and capacities
+        w.params.n_select = min(w.params.n_select, n_select_max)
+    return ws
+
+
+def _same(a, b, what):
+    for k in KEYS:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=f"{what}: {k}")
+    assert a["counters"] == b["counters"], what
+
+
+def test_batch_matches_each_query_alone(kpx):
+    ws = _small_batch(10, 3)
+    alone = []
+    for w in ws:
+        p = kpx.Planner(w.problem, w.params)
+        p.iterate(25)
+        p.sync()
+        alone.append(p.snapshot())
+        p.close()
+    ps = [kpx.Planner(w.problem, w.params) for w in ws]
+    b = kpx.Batch(ps)
+    b.iterate(25)
+    states = b.sync()
+    for q, (p, a) in enumerate(zip(ps, alone)):
+        _same(p.snapshot(), a, f"query {q}")
+    # the capacities include trees that fill up within the run
+    assert kpx.FULL in states and kpx.OK in states, states
+    b.close()
+    for p in ps:
+        p.close()
+
+
+def test_batch_graph_replays_match_plain_launches(kpx):
+    ws = _small_batch(8, 5, n_select_max=200)
+    plain = [kpx.Planner(w.problem, w.params) for w in ws]
+    graph = [kpx.Planner(w.problem, w.params) for w in ws]
+    bp, bg = kpx.Batch(plain), kpx.Batch(graph, graph=True)
+    for step in (6, 5, 4, 1, 6):  # replays of two iterations, and odd remainders
+        bp.iterate(step)
+        bg.iterate(step)
+        for q, (a, g) in enumerate(zip(plain, graph)):
+            _same(a.snapshot(), g.snapshot(), f"query {q} after {step}")
+        plain[0].counters()  # eager work between replays
+    for b in (bp, bg):
+        b.close()
+    for p in plain + graph:
+        p.close()
+
+
+def test_batch_rejects_bad_groupings(kpx):
+    ws = _small_batch(3, 7)
+    ps = [kpx.Planner(w.problem, w.params) for w in ws]
+    with pytest.raises(kpx.KPXError):
+        kpx.Batch([ps[0], ps[0]])  # the same handle twice
+    ps[1].set_dump(True)
+    with pytest.raises(kpx.KPXError):
+        kpx.Batch(ps)  # candidate recording on
+    ps[1].set_dump(False)
+    ps[2].iterate(1)  # out of step with the others
+    with pytest.raises(kpx.KPXError):
+        kpx.Batch(ps)
+    for p in ps:
+        p.close()

@@ -6,6 +6,7 @@ integration, no validity test, no sampling of controls.
 """
 
 from .scenes import (  # noqa: F401
+    batch_workloads,
     DYNAMICS,
     COSTS,
     STATE_DIM,

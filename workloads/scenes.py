@@ -268,6 +268,70 @@ def dubins6_workload(seed: int = 0, *, n_boxes: int = 200, n_select: int = 8192,
     return Workload("dubins6", prob, prm, iterations)
 
 
+def _start_goal(rng, min_dist=0.6, lo=0.1, hi=0.9):
+    while True:
+        a, b = rng.uniform(lo, hi, size=3), rng.uniform(lo, hi, size=3)
+        if np.linalg.norm(a - b) >= min_dist:
+            return a, b
+
+
+def batch_workloads(seed: int = 0, n_queries: int = 256, *, samples=None, iterations: int = 100,
+                    margin: float = 1e-4) -> list:
+    """Independent queries for the batched form: half double integrators
+    (even query index) and half quadrotors (odd), each with its own seeded
+    scene of U{4..256} boxes (centres U[0.1,0.9]^3, sides U[0.03,0.1]^3), a
+    start and goal ball (r = 0.05) drawn in [0.1,0.9]^3 at least 0.6 apart, a
+    tree capacity 2^U{10..18} and U{64..4096} nodes per iteration, clipped so
+    that one iteration's candidates fit in half the tree.  `samples` maps
+    "DI6" / "QUAD12" to the samples per node (default 8 / 16).  Query q has
+    query_id q and planner seed `seed`."""
+    samples = dict({"DI6": 8, "QUAD12": 16}, **(samples or {}))
+    out = []
+    for q in range(n_queries):
+        rng = np.random.default_rng(np.random.SeedSequence([int(seed) & 0xFFFFFFFF, 0xBA7, q]))
+        quad = q % 2 == 1
+        dyn = "QUAD12" if quad else "DI6"
+        start, goal = _start_goal(rng)
+        n_boxes = int(rng.integers(4, 257))
+        boxes = _random_boxes(rng, n_boxes, 0.1, 0.9, 0.03, 0.1, start, goal, 0.05)
+        cap = 1 << int(rng.integers(10, 19))
+        k = int(samples[dyn])
+        n_select = int(np.exp(rng.uniform(np.log(64), np.log(4096))))
+        n_select = max(1, min(n_select, (cap // 2) // k))
+        if quad:
+            m, inertia, g = 1.0, 0.01, 9.81
+            prob = Problem(
+                dynamics="QUAD12", cost="TIME",
+                dyn_params=_f32([m, inertia, inertia, inertia, g], 8),
+                x_init=_f32(list(start) + [0.0] * 9, MAX_STATE),
+                x_lo=_f32([-INF, -INF, -INF, -1, -1, -INF, -1, -1, -1, -10, -10, -10], MAX_STATE),
+                x_hi=_f32([INF, INF, INF, 1, 1, INF, 1, 1, 1, 10, 10, 10], MAX_STATE),
+                u_lo=_f32([0, -0.5, -0.5, -0.5], MAX_CONTROL),
+                u_hi=_f32([2 * m * g, 0.5, 0.5, 0.5], MAX_CONTROL),
+                ws_lo=_f32([0, 0, 0], 3), ws_hi=_f32([1, 1, 1], 3),
+                boxes=boxes, margin=float(np.float32(margin)),
+                goal_center=_f32(goal, 3), goal_radius=float(np.float32(0.05)))
+            prm = Params(dt=float(np.float32(0.005)), steps_min=5, steps_max=60, grid=(16, 16, 16),
+                         vel_sign_bins=1, n_select=n_select, samples_per_node=k, tree_cap=cap,
+                         i_max=10, seed=seed, query_id=q)
+        else:
+            prob = Problem(
+                dynamics="DI6", cost="TIME",
+                dyn_params=_f32([], 8),
+                x_init=_f32(list(start) + [0.0] * 3, MAX_STATE),
+                x_lo=_f32([-INF, -INF, -INF, -1, -1, -1], MAX_STATE),
+                x_hi=_f32([INF, INF, INF, 1, 1, 1], MAX_STATE),
+                u_lo=_f32([-1, -1, -1], MAX_CONTROL), u_hi=_f32([1, 1, 1], MAX_CONTROL),
+                ws_lo=_f32([0, 0, 0], 3), ws_hi=_f32([1, 1, 1], 3),
+                boxes=boxes, margin=float(np.float32(margin)),
+                goal_center=_f32(goal, 3), goal_radius=float(np.float32(0.05)))
+            prm = Params(dt=float(np.float32(0.01)), steps_min=5, steps_max=30, grid=(30, 30, 30),
+                         vel_sign_bins=0, n_select=n_select, samples_per_node=k, tree_cap=cap,
+                         i_max=10, seed=seed, query_id=q)
+        out.append(Workload(f"batch/{dyn.lower()}/{q}", prob, prm, iterations))
+    return out
+
+
 WORKLOADS = {"di6": di6_workload, "quad12": quad12_workload, "dubins6": dubins6_workload}
 
 
