@@ -73,7 +73,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=150)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="quad12", choices=["di6", "quad12", "dubins6"])
+    ap.add_argument("--workload", default="quad12", choices=["di6", "quad12", "dubins6", "batch256"])
+    ap.add_argument("--queries", type=int, default=256, help="queries of the batch256 workload")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch256: skip the sequential per-query comparison")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="bound on the oracle CPU-baseline sample")
@@ -100,6 +103,8 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.workload == "batch256":
+        return bench_batch(a)
     K.lib()  # fails loudly when the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -185,6 +190,98 @@ def main():
         "first_solution_iteration": first_it,
         "solution_cost": sol["cost"] if sol["found"] else None,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def bench_batch(a):
+    """Independent queries (half double integrators, half quadrotors, seeded
+    scenes of 4..256 boxes, capacities 2^10..2^18) iterated as one batch of
+    graph-replayed launches, against the same queries run one after another."""
+    import torch
+
+    import paper_2602_02846_amd as K
+    import workloads as W
+    from paper_2602_02846_amd.autotune import autotune_samples, first_solution_ms, with_samples
+
+    K.lib()
+    torch.cuda.set_device(0)
+    ws = W.batch_workloads(a.seed, a.queries)
+    chosen, scores = autotune_samples(ws)
+    ws = [with_samples(w, chosen[w.problem.dynamics]) for w in ws]
+    print(f"[bench] batch of {len(ws)} queries; samples per node {chosen} "
+          f"(autotuner medians, ms: {scores})", file=sys.stderr, flush=True)
+    n_iter = a.warmup + a.steps
+
+    planners = [K.Planner(w.problem, w.params) for w in ws]
+    batch = K.Batch(planners, graph=True)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    batch.iterate(a.warmup)
+    batch.sync()
+    c0 = [p.counters() for p in planners]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.iterate(a.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    batch.sync()
+    elapsed, whole = t1 - t0, t1 - tb0
+    edges = substeps = 0
+    flops = 0.0
+    for p, w, c in zip(planners, ws, c0):
+        c1 = p.counters()
+        done = int(c1["iteration"] - c["iteration"])
+        if done > 0:
+            st = p.stats(int(c["iteration"]), done)
+            e = int((st["n_select"].astype(np.int64) * w.params.samples_per_node).sum())
+            sub = int(st["substeps"].sum())
+            edges += e
+            substeps += sub
+            flops += FLOPS_PER_SUBSTEP[(w.problem.dynamics, w.problem.cost)] * sub
+    t_first = [first_solution_ms(p, n_iter) for p in planners]
+    solved = [t for t in t_first if t is not None]
+    costs = [p.solution()["cost"] for p in planners if p.counters()["first_solution_iteration"] >= 0]
+    batch.close()
+    for p in planners:
+        p.close()
+    print(f"[bench] batch: {a.steps} iterations in {elapsed * 1e3:.1f} ms, {edges} edges", file=sys.stderr,
+          flush=True)
+
+    seq = None
+    if not a.no_sequential:
+        t_seq, seq_edges_timed = 0.0, 0
+        for w in ws:
+            p = K.Planner(w.problem, w.params)
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            p.iterate(n_iter)
+            p.sync()
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - s0
+            p.close()
+        seq = {"whole_run_s": round(t_seq, 4), "queries_per_s": round(len(ws) / t_seq, 2)}
+
+    achieved = flops / elapsed / 1e12 if elapsed > 0 else 0.0
+    out = {
+        "metric": "propagated edges/s", "value": round(edges / elapsed, 1), "unit": "edges/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(elapsed * 1e3 / max(a.steps, 1), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch{len(ws)}: {len(ws) // 2} DI6 + {len(ws) - len(ws) // 2} QUAD12 "
+                               "queries, 4..256 boxes, caps 2^10..2^18, graph-replayed batch",
+                   "seed": a.seed, "samples_per_node": chosen, "edges_timed": edges,
+                   "substeps_timed": substeps},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "scope": "RK4 FLOPs over whole iterations (all kernels)"},
+        "queries_per_s": round(len(ws) / whole, 2),
+        "batch_whole_run_s": round(whole, 4),
+        "sequential": seq,
+        "speedup_vs_sequential": round(seq["whole_run_s"] / whole, 2) if seq else None,
+        "solved": len(solved), "queries": len(ws),
+        "time_to_first_solution_ms_median": round(float(np.median(solved)), 3) if solved else None,
+        "solution_cost_median": round(float(np.median(costs)), 4) if costs else None,
     }
     print(json.dumps(out))
 
