@@ -73,7 +73,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=150)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="quad12", choices=["di6", "quad12", "dubins6", "batch256"])
+    ap.add_argument("--workload", default="quad12",
+                    choices=["di6", "quad12", "dubins6", "di6_paper", "quad12_paper", "dubins6_paper",
+                             "batch256"])
     ap.add_argument("--queries", type=int, default=256, help="queries of the batch256 workload")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch256: skip the sequential per-query comparison")
@@ -81,6 +83,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="bound on the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solution-seeds", type=int, default=10,
+                    help="queries (seeds) for the median time to first solution and cost")
+    ap.add_argument("--solution-iters", type=int, default=200,
+                    help="iteration budget of each of those queries")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--time-all", action="store_true",
                     help="HIP events around all four kernels (default: propagate only)")
@@ -137,7 +143,7 @@ def main():
     c1 = planner.counters()
     done = int(c1["iteration"] - c0["iteration"])
     st = planner.stats(int(c0["iteration"]), done) if done > 0 else None
-    edges = int((st["n_select"].astype(np.int64) * prm.samples_per_node).sum()) if done else 0
+    edges = int((st["n_select"].astype(np.int64) * st["samples_per_node"]).sum()) if done else 0
     substeps = int(st["substeps"].sum()) if done else 0
     elapsed = t1 - t0
     value = edges / elapsed if elapsed > 0 else 0.0
@@ -169,19 +175,23 @@ def main():
     if first_it >= 0 and all_st.size and all_st["iteration"][0] == 0:
         t_first = float((int(all_st["t_end"][first_it]) - int(all_st["t_begin"][0])) / rate * 1e3)
 
+    planner.close()
+    sols = solution_medians(K, W, a) if a.solution_seeds > 0 else None
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(w, snap_start, a.cpu_seconds)
 
-    planner.close()
     out = {
         "metric": "propagated edges/s", "value": round(value, 1), "unit": "edges/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(elapsed * 1e3 / max(done, 1), 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{a.workload}: {prob.dynamics} {prob.n_boxes} boxes, "
-                   f"{prm.n_select}x{prm.samples_per_node} expansions/iteration, "
-                   f"{prm.n_cells} regions, cap {prm.tree_cap}",
+                   + (f"{prm.n_select}x{prm.samples_per_node} expansions/iteration, "
+                      if prm.samples_per_node else
+                      f"every active node sharing {prm.n_select} expansion slots per iteration, ")
+                   + f"{prm.n_cells} regions, cap {prm.tree_cap}",
                    "seed": a.seed, "iterations_timed": done, "edges_timed": edges,
                    "substeps_timed": substeps, "cost": prob.cost},
         "roofline": roofline,
@@ -189,9 +199,33 @@ def main():
         "time_to_first_solution_ms": t_first,
         "first_solution_iteration": first_it,
         "solution_cost": sol["cost"] if sol["found"] else None,
+        "solutions": sols,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def solution_medians(K, W, a):
+    """Median device-timed time to first solution and median solution cost of
+    the plain planner over seeds 0 .. solution_seeds - 1 of the workload, each
+    run for solution_iters iterations (or until its tree is full)."""
+    from paper_2602_02846_amd.autotune import first_solution_ms
+
+    times, costs = [], []
+    for seed in range(a.solution_seeds):
+        w = W.make_workload(a.workload, seed)
+        p = K.Planner(w.problem, w.params)
+        p.iterate(a.solution_iters)
+        p.sync()
+        t = first_solution_ms(p, a.solution_iters)
+        if t is not None:
+            times.append(t)
+            costs.append(p.solution()["cost"])
+        p.close()
+    return {"queries": a.solution_seeds, "iterations": a.solution_iters, "solved": len(times),
+            "time_to_first_solution_ms_median": round(float(np.median(times)), 3) if times else None,
+            "cost_median": round(float(np.median(costs)), 4) if costs else None,
+            "cost_unit": "s" if W.make_workload(a.workload, 0).problem.cost == "TIME" else "length"}
 
 
 def bench_batch(a):
@@ -234,7 +268,7 @@ def bench_batch(a):
         done = int(c1["iteration"] - c["iteration"])
         if done > 0:
             st = p.stats(int(c["iteration"]), done)
-            e = int((st["n_select"].astype(np.int64) * w.params.samples_per_node).sum())
+            e = int((st["n_select"].astype(np.int64) * st["samples_per_node"]).sum())
             sub = int(st["substeps"].sum())
             edges += e
             substeps += sub

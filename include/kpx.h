@@ -100,7 +100,11 @@ typedef struct kpx_problem {
  *                             (DI6 and QUAD12 only)
  *   n_select                  at most this many active nodes are expanded per
  *                             iteration, taken in region order from a rotating cursor
- *   samples_per_node          K (the branching factor lambda)
+ *   samples_per_node          K (the branching factor lambda); 0 selects the
+ *                             uncapped form of Sec. VI-A / App. A: every active
+ *                             node (up to n_select) with lambda =
+ *                             max(1, floor(n_select / |selected|)) samples, so that
+ *                             n_select is the size of the candidate buffer
  *   tree_cap                  t_e: capacity of the tree
  *   i_max                     inactivity threshold I_max (0..254)
  *   seed, query_id            Philox4x32-10 key and counter field
@@ -134,7 +138,7 @@ typedef struct kpx_counters {
     int64_t first_solution_iteration;  /* -1 until a goal node exists */
     uint64_t solution_key;             /* (cost field << 32) | tree index; all ones = none */
     int32_t full;                      /* 1 once the capacity pre-check failed */
-    int32_t reserved;
+    int32_t samples_per_node;          /* samples per node in the last iteration */
 } kpx_counters;
 
 typedef struct kpx_solution_info {
@@ -167,7 +171,8 @@ typedef struct kpx_tree_view {
 } kpx_tree_view;
 
 /* Host buffers for kpx_read_dump: the last iteration's expansions, one entry
- * per slot s = r * K + j (r-th selected node, j-th sample).  Any pointer may be
+ * per slot s = r * K + j (r-th selected node, j-th sample, K the samples per
+ * node of that iteration).  Any pointer may be
  * NULL.  state and control are component-major with leading dimension `capacity`. */
 typedef struct kpx_dump_view {
     int64_t capacity;
@@ -189,7 +194,7 @@ typedef struct kpx_iter_stats {
     int32_t n_select;
     int32_t n_valid;
     int32_t n_survivors;
-    int32_t reserved;
+    int32_t samples_per_node;
     int64_t substeps;
     uint64_t solution_key;
     uint64_t t_begin;         /* device wall clock ticks (kpx_clock_rate_khz) */

@@ -398,9 +398,27 @@ static int64_t n_cells_of(const ora_problem* P)
     return (int64_t)P->grid[0] * P->grid[1] * P->grid[2] * (P->vel_sign_bins ? 8 : 1);
 }
 
+/* Candidate slots of one iteration at most: n_select * K, or, in the
+ * uncapped form (samples_per_node = 0), the n_select slots that all active
+ * nodes share (Sec. VI-A / App. A: lambda = floor(t_e / |V_A|), read with the
+ * candidate buffer's size for t_e). */
+static int64_t slots_max(const ora_problem* P)
+{
+    return (int64_t)P->n_select * (P->samples_per_node > 0 ? P->samples_per_node : 1);
+}
+
+/* Samples per node for a selection of n_sel nodes. */
+static int64_t samples_for(const ora_problem* P, int64_t n_sel)
+{
+    if (P->samples_per_node > 0) return P->samples_per_node;
+    if (n_sel <= 0) return 1;
+    const int64_t k = P->n_select / n_sel;
+    return k > 1 ? k : 1;
+}
+
 static int64_t survivors_bound(const ora_problem* P)
 {
-    int64_t slots = (int64_t)P->n_select * P->samples_per_node;
+    int64_t slots = slots_max(P);
     int64_t cells = n_cells_of(P);
     return slots < cells ? slots : cells;
 }
@@ -430,7 +448,7 @@ int ora_init(const ora_problem* P, ora_tree* T)
     for (int i = 0; i < m; ++i)
         if (!(P->u_lo[i] <= P->u_hi[i])) return ORA_ERR_ARG;
     if (P->vel_sign_bins && vel_index(P->dynamics) < 0) return ORA_ERR_ARG;
-    if (P->n_select < 1 || P->samples_per_node < 1) return ORA_ERR_ARG;
+    if (P->n_select < 1 || P->samples_per_node < 0) return ORA_ERR_ARG;
     if (P->steps_min < 1 || P->steps_max < P->steps_min) return ORA_ERR_ARG;
     if (!(P->dt > 0.0f) || !(P->margin >= 0.0f) || !(P->goal_radius > P->margin)) return ORA_ERR_ARG;
     if (P->n_boxes < 0 || (P->n_boxes > 0 && !P->boxes)) return ORA_ERR_ARG;
@@ -556,21 +574,23 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
 {
     const int d = ora_state_dim(P->dynamics);
     const int m = ora_control_dim(P->dynamics);
-    const int64_t K = P->samples_per_node;
     if (T->full || T->n_tree + survivors_bound(P) > T->cap) {
         T->full = 1;
         C->n_slots = 0;
+        C->k = 0;
         return ORA_FULL;
     }
-    if (C->cap_slots < (int64_t)P->n_select * K) return ORA_ERR_ARG;
+    if (C->cap_slots < slots_max(P)) return ORA_ERR_ARG;
     const int64_t n_tree = T->n_tree;
 
     /* which nodes of V_A are expanded */
     int64_t* sel = (int64_t*)malloc(sizeof(int64_t) * (size_t)P->n_select);
     int64_t cursor_next = T->cursor;
     const int64_t n_sel = ora_select(P, T, sel, &cursor_next);
+    const int64_t K = samples_for(P, n_sel);
     const int64_t n_slots = n_sel * K;
     C->n_slots = n_slots;
+    C->k = K;
     C->substeps_total = 0;
 
     /* Alg. 2 lines 1-7: each of the K expansions of each selected node */

@@ -111,6 +111,7 @@ typedef struct {
     uint8_t* survivor;
     int64_t* new_index;     /* tree index when a survivor, else -1 */
     int64_t substeps_total;
+    int64_t k;              /* samples per selected node in this iteration */
 } ora_cands;
 
 /* Decisions of an implementation under test.  The oracle adopts one only

@@ -67,6 +67,7 @@ class CandsC(C.Structure):
         ("n", _i32p), ("xn", _f64p), ("valid", _u8p), ("first_invalid", _i32p),
         ("substeps", _i32p), ("flags", _u32p), ("cell", _i64p), ("cost", _f64p), ("goal", _u8p),
         ("survivor", _u8p), ("new_index", _i64p), ("substeps_total", C.c_int64),
+        ("k", C.c_int64),
     ]
 
 
@@ -310,6 +311,11 @@ class Cands:
     @property
     def substeps_total(self) -> int:
         return int(self.c.substeps_total)
+
+    @property
+    def k(self) -> int:
+        """Samples per selected node in the last step."""
+        return int(self.c.k)
 
     def view(self) -> dict:
         k = self.n_slots

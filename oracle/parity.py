@@ -146,6 +146,7 @@ def compare_trees(P, tr, snap, report):
     assert int(c["cursor"]) == tr.c.cursor
     assert int(c["iteration"]) == tr.c.iter
     assert int(c["n_select"]) == tr.c.last_n_sel
+    assert int(c["samples_per_node"]) == tr.cands.k
     assert int(c["n_valid"]) == tr.c.last_n_valid
     assert int(c["n_survivors"]) == tr.c.last_n_surv
     assert int(c["substeps"]) == tr.cands.substeps_total

@@ -69,6 +69,8 @@ struct DevState {
     int cursor_next;
     int full;
     int n_surv;          // survivors of this iteration (written by the insert kernel)
+    int k;               // samples per selected node in this iteration
+    int last_k;          // ... in the last completed one
 };
 
 struct DevPtrs {
@@ -169,6 +171,17 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, DevState* st, const float* 
     st->cursor_next = 0;
     st->full = 0;
     st->n_surv = 0;
+    st->k = 0;
+    st->last_k = 0;
+}
+
+// Samples per selected node for a selection of nsel nodes: K when fixed;
+// otherwise (samples_per_node = 0, the uncapped form of Sec. VI-A / App. A)
+// every active node is selected, up to the candidate buffer's n_select slots,
+// and the buffer is shared out evenly: lambda = max(1, floor(n_select / nsel)).
+__device__ __forceinline__ int samples_for(const DevProblem& P, int nsel)
+{
+    return P.K > 0 ? P.K : (nsel > 0 ? max(1, P.n_select / nsel) : 1);
 }
 
 // ------------------------------------------------------------------ propagate
@@ -230,10 +243,11 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     stage_lds(reinterpret_cast<const int4*>(T.boxes), reinterpret_cast<int4*>(sbox), 2 * P.n_boxes,
               reinterpret_cast<const int4*>(T.gcell), reinterpret_cast<int4*>(sgc), gbp / 2,
               reinterpret_cast<const int4*>(T.glist), reinterpret_cast<int4*>(sgl), (P.gb_entries + 7) / 8);
-    const int S = st->n_sel * P.K;
+    const int K = st->k;
+    const int S = st->n_sel * K;
     if (st->full || S == 0) return;  // kernel-uniform
     int chunk = max(kChunkMin, (S + nblk - 1) / nblk);
-    chunk = min(chunk, min(kChunkMax, (kParMax - 1) * P.K));
+    chunk = min(chunk, min(kChunkMax, (kParMax - 1) * K));
     if (blk * chunk >= S) return;  // block-uniform
     if (blk == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
     const long long n_tree = st->n_tree;
@@ -248,8 +262,8 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
 
     for (int base = blk * chunk; base < S; base += nblk * chunk) {
         const int cnt = min(chunk, S - base);
-        const int r0 = base / P.K;
-        const int npar = (base + cnt - 1) / P.K - r0 + 1;
+        const int r0 = base / K;
+        const int npar = (base + cnt - 1) / K - r0 + 1;
         // the sort bins and the queue head are free once the previous chunk
         // has left its integration loop
         if (threadIdx.x < kSortBins) s_bin[threadIdx.x] = 0;
@@ -288,7 +302,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                 for (int k = 0; k < M; ++k) s_u[k][li] = u[k];
                 s_n[li] = (unsigned short)n;
                 bins[r] = (kSortBins - 1) - min(kSortBins - 1, (n - P.steps_min) >> P.sort_shift);
-                if (one_each) s_order[li] = (uint32_t)li | (uint32_t)((base + li) / P.K - r0) << 16;
+                if (one_each) s_order[li] = (uint32_t)li | (uint32_t)((base + li) / K - r0) << 16;
                 else atomicAdd(&s_bin[bins[r]], 1);
             }
         }
@@ -321,7 +335,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                 if (bins[r] >= 0)
                     s_order[atomicAdd(&s_bin[bins[r]], 1)] =
                         (uint32_t)(threadIdx.x + r * kPropBlock) |
-                        (uint32_t)((base + (int)threadIdx.x + r * kPropBlock) / P.K - r0) << 16;
+                        (uint32_t)((base + (int)threadIdx.x + r * kPropBlock) / K - r0) << 16;
             __syncthreads();
         }
 
@@ -436,7 +450,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             const int s = base + lj;
             const int fi = s_fi[lj];
             const int nn = s_n[lj];
-            const int pj = s / P.K - r0;
+            const int pj = s / K - r0;
             my_steps += fi ? fi : nn;
             if (fi == 0) {
                 ++my_valid;
@@ -584,7 +598,7 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
     const unsigned long long key = T.ckey[sc];
     const int cell = T.ccell[sc];
     const int full = st->full;
-    const int S = st->n_sel * P.K;
+    const int S = st->n_sel * st->k;
     if (full || tile * kTile >= S) return;  // block-uniform
     int f = 0;
     if (s < S) {
@@ -671,7 +685,8 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, const
     finalize = finalize && !was_full;
     // the cursor this selection starts from (closing the iteration moves it)
     const int cur = finalize ? q.cursor_next : q.cursor;
-    const int S = q.n_sel * P.K;
+    const int k_cur = q.k;
+    const int S = q.n_sel * k_cur;
     const int tiles = (S + kTile - 1) / kTile;
     int v[3] = {0, 0, 0};  // survivors of my tiles; active regions at / after the cursor; before it
     if (finalize) {
@@ -702,11 +717,12 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, const
         r->n_select = q.n_sel;
         r->n_valid = q.n_valid_acc;
         r->n_survivors = n_surv;
-        r->reserved = 0;
+        r->samples_per_node = k_cur;
         r->substeps = (long long)q.substeps_acc;
         r->solution_key = q.sol;
         r->t_end = wall_clock64();
         q.last_n_sel = q.n_sel;
+        q.last_k = k_cur;
         q.last_n_valid = q.n_valid_acc;
         q.last_n_surv = n_surv;
         q.last_substeps = (long long)q.substeps_acc;
@@ -767,6 +783,7 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, const
     }
     if (threadIdx.x == 0) {
         q.n_sel = nsel;
+        q.k = samples_for(P, nsel);
         if (nsel == 0 && !full) q.cursor_next = cur;
         q.n_surv = 0;
         *out = q;
@@ -807,12 +824,13 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     const unsigned long long key = T.ckey[sc];
     const int c = T.ccell[sc];
     const uint8_t flag = T.cflag[sc];
-    const int par = T.sel[sc / P.K];
+    const int K = P.K > 0 ? P.K : st->k;
+    const int par = T.sel[sc / K];
     const int full = st->full, n_sel = st->n_sel;
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
     if (full) return;  // kernel-uniform: nothing happens in a full tree
-    const int S = n_sel * P.K;
+    const int S = n_sel * K;
     if (tile * kTile >= S) return;  // block-uniform
     for (int j = threadIdx.x + 4 * kBlock; j < tile; j += kBlock) pre += T.tile_count[j];
     const int f = s < S ? f0 : 0;
@@ -906,6 +924,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
     for (int k = 0; k < kSelBlocksMax / kBlock; ++k)
         bc[k] = T.bcount[min((int)threadIdx.x + k * kBlock, nb - 1)];
     const int was_full = st->full, n_sel = st->n_sel, n_surv0 = st->n_surv, cur = st->cursor_next;
+    const int k_cur = st->k;
     const long long n_tree = st->n_tree;
     // active regions at / after the cursor and before it: in the blocks before
     // this one, and in all
@@ -962,6 +981,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
         o->sol = st->sol;
         o->full = full ? 1 : 0;
         o->n_sel = nsel;
+        o->k = samples_for(P, nsel);
         o->n_surv = 0;
         if (finalize) {
             const long long nt = n_tree + n_surv;
@@ -971,7 +991,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
             r->n_select = n_sel;
             r->n_valid = st->n_valid_acc;
             r->n_survivors = n_surv;
-            r->reserved = 0;
+            r->samples_per_node = k_cur;
             r->substeps = (long long)st->substeps_acc;
             r->solution_key = st->sol;
             r->t_end = wall_clock64();
@@ -979,6 +999,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
             o->it = it + 1;
             o->first_sol_it = (st->sol != kEmpty && st->first_sol_it < 0) ? it : st->first_sol_it;
             o->last_n_sel = n_sel;
+            o->last_k = k_cur;
             o->last_n_valid = st->n_valid_acc;
             o->last_n_surv = n_surv;
             o->last_substeps = (long long)st->substeps_acc;
@@ -990,6 +1011,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
             o->it = it;
             o->first_sol_it = st->first_sol_it;
             o->last_n_sel = st->last_n_sel;
+            o->last_k = st->last_k;
             o->last_n_valid = st->last_n_valid;
             o->last_n_surv = st->last_n_surv;
             o->last_substeps = st->last_substeps;
@@ -1365,8 +1387,10 @@ int validate(const kpx_problem* p, const kpx_params* q, Sizes* z, std::string* w
     if (q->vel_sign_bins && p->dynamics == KPX_DUBINS6) return bad("sign bins need a velocity state");
     if (q->vel_sign_bins) nc *= 8;
     if (nc > (1ll << 30)) return bad("too many regions");
-    if (q->n_select < 1 || q->samples_per_node < 1) return bad("n_select / samples_per_node");
-    const long long S = (long long)q->n_select * q->samples_per_node;
+    if (q->n_select < 1 || q->samples_per_node < 0) return bad("n_select / samples_per_node");
+    // candidate slots per iteration: n_select * K, or n_select (the buffer the
+    // uncapped form shares out) when samples_per_node = 0
+    const long long S = (long long)q->n_select * (q->samples_per_node > 0 ? q->samples_per_node : 1);
     if (S > (1ll << 28)) return bad("n_select * samples_per_node too large");
     if (q->i_max < 0 || q->i_max > 254) return bad("i_max out of 0..254");
     const long long surv = std::min(nc, S);
@@ -1996,7 +2020,7 @@ int kpx_counters_read(kpx_handle* h, kpx_counters* out)
     out->first_solution_iteration = s.first_sol_it;
     out->solution_key = s.sol;
     out->full = s.full;
-    out->reserved = 0;
+    out->samples_per_node = s.last_k;
     return KPX_OK;
 }
 
@@ -2116,7 +2140,7 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* v, int64_t* n_slots)
     kpx_counters c;
     int rc = kpx_counters_read(h, &c);
     if (rc != KPX_OK) return rc;
-    const size_t S = (size_t)c.n_select * (size_t)h->prm.samples_per_node;
+    const size_t S = (size_t)c.n_select * (size_t)c.samples_per_node;
     *n_slots = (int64_t)S;
     if (v->capacity < (int64_t)S) return fail(h, KPX_ERR_BUFFER, "dump capacity < slots");
     if (S == 0) return KPX_OK;

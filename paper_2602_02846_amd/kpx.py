@@ -58,7 +58,7 @@ class CountersC(C.Structure):
         ("n_tree", C.c_int64), ("iteration", C.c_int64), ("cursor", C.c_int64),
         ("n_select", C.c_int64), ("n_valid", C.c_int64), ("n_survivors", C.c_int64),
         ("substeps", C.c_int64), ("first_solution_iteration", C.c_int64),
-        ("solution_key", C.c_uint64), ("full", C.c_int32), ("reserved", C.c_int32),
+        ("solution_key", C.c_uint64), ("full", C.c_int32), ("samples_per_node", C.c_int32),
     ]
 
 
@@ -89,7 +89,7 @@ class DumpViewC(C.Structure):
 class IterStatsC(C.Structure):
     _fields_ = [
         ("iteration", C.c_int64), ("n_tree", C.c_int64), ("n_select", C.c_int32),
-        ("n_valid", C.c_int32), ("n_survivors", C.c_int32), ("reserved", C.c_int32),
+        ("n_valid", C.c_int32), ("n_survivors", C.c_int32), ("samples_per_node", C.c_int32),
         ("substeps", C.c_int64), ("solution_key", C.c_uint64), ("t_begin", C.c_uint64),
         ("t_end", C.c_uint64),
     ]
@@ -97,7 +97,7 @@ class IterStatsC(C.Structure):
 
 STATS_DTYPE = np.dtype([
     ("iteration", np.int64), ("n_tree", np.int64), ("n_select", np.int32),
-    ("n_valid", np.int32), ("n_survivors", np.int32), ("reserved", np.int32),
+    ("n_valid", np.int32), ("n_survivors", np.int32), ("samples_per_node", np.int32),
     ("substeps", np.int64), ("solution_key", np.uint64), ("t_begin", np.uint64),
     ("t_end", np.uint64)])
 
@@ -341,7 +341,7 @@ class Planner:
         self._check(lib().kpx_set_dump(self.h, 1 if enable else 0))
 
     def read_dump(self) -> dict:
-        S = int(self.params.n_select) * int(self.params.samples_per_node)
+        S = int(self.params.n_slots)  # candidate buffer slots
         cap = max(S, 1)
         a = {
             "parent": np.zeros(cap, np.int32), "control": np.zeros((MAX_CONTROL, cap), np.float32),

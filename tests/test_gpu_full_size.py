@@ -41,7 +41,8 @@ def check_tree_invariants(kpx, snap, n_slots_max, n_cells):
                   snap["cost"][owners])
 
 
-@pytest.mark.parametrize("name,warm", [("quad12", 12), ("dubins6", 12), ("di6", 40)])
+@pytest.mark.parametrize("name,warm", [("quad12", 12), ("dubins6", 12), ("di6", 40),
+                                       ("quad12_paper", 6), ("dubins6_paper", 6), ("di6_paper", 10)])
 def test_full_size_sampled_slots(kpx, ora, name, warm):
     w = W.make_workload(name, 0)
     P = ora.Problem(w.problem, w.params)
@@ -53,7 +54,8 @@ def test_full_size_sampled_slots(kpx, ora, name, warm):
     dump = pl.read_dump()
     post = pl.snapshot()
     S = dump["n_slots"]
-    assert S == pre["counters"]["n_select"] * 0 + S and S > 0
+    c1 = post["counters"]
+    assert S > 0 and S == int(c1["n_select"]) * int(c1["samples_per_node"]) <= w.params.n_slots
     it = int(pre["counters"]["iteration"])
     n0 = int(pre["counters"]["n_tree"])
     rng = np.random.default_rng(0)

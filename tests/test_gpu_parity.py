@@ -128,3 +128,22 @@ def test_stats_ring_and_timing(kpx):
     with pytest.raises(kpx.KPXError):
         pl.set_timing(16)
     pl.close()
+
+
+# the uncapped form (samples_per_node = 0): all active nodes share the buffer
+UNCAPPED = {
+    "di6": (dict(n_select=900, samples=0, tree_cap=1 << 15), 25),
+    "quad12": (dict(n_select=1100, samples=0, tree_cap=1 << 15, grid=(8, 8, 8)), 20),
+}
+
+
+@pytest.mark.parametrize("case", sorted(UNCAPPED))
+def test_lockstep_uncapped_form(kpx, ora, case):
+    kw, iters = UNCAPPED[case]
+    w = W.make_workload(case, 6, **kw)
+    P = ora.Problem(w.problem, w.params)
+    pl = _planner(kpx, w)
+    rep = parity.lockstep(ora, P, pl, iters)
+    print(case, rep)
+    assert rep["iterations"] == iters and rep["valid"] > 0
+    pl.close()

@@ -121,8 +121,17 @@ def _run_with_invariants(ora, w, iterations):
             break
         c = tr.cands.view()
         S = tr.cands.n_slots
-        assert S == len(sel) * K
-        assert np.array_equal(c["parent"], np.repeat(sel, K))
+        if K == 0:
+            # uncapped form: every active node up to the buffer, sharing it evenly
+            n_active = int(np.count_nonzero(pre_status == A))
+            assert len(sel) == min(n_active, w.params.n_select)
+            k_it = max(1, w.params.n_select // len(sel)) if len(sel) else 1
+            assert tr.cands.k == k_it and S == len(sel) * k_it <= w.params.n_select
+        else:
+            k_it = K
+            assert tr.cands.k == K
+        assert S == len(sel) * k_it
+        assert np.array_equal(c["parent"], np.repeat(sel, k_it))
         # selected nodes were ACTIVE
         assert np.all(pre_status[sel] == A)
         # brute-force region minimum over incumbents and this iteration's arrivals
@@ -192,6 +201,15 @@ def test_full_run_invariants_double_integrator(ora, cost):
 def test_full_run_invariants_quadrotor_small(ora):
     w = W.make_workload("quad12", 2, n_select=48, samples=6, grid=(8, 8, 8), tree_cap=1 << 15)
     _run_with_invariants(ora, w, 40)
+
+
+def test_full_run_invariants_uncapped_form(ora):
+    """samples_per_node = 0: every active node (up to a 600-slot buffer) with
+    lambda = max(1, floor(600 / |selected|)) samples, checked against the
+    active nodes counted before each step."""
+    w = W.make_workload("di6", 4, n_select=600, samples=0, tree_cap=1 << 15)
+    P, tr, sols = _run_with_invariants(ora, w, 30)
+    assert tr.n_tree > 300
 
 
 def test_full_run_invariants_dubins_small(ora):

@@ -99,7 +99,9 @@ class Params:
 
     @property
     def n_slots(self) -> int:
-        return int(self.n_select) * int(self.samples_per_node)
+        """Candidate slots per iteration at most: n_select * K, or n_select
+        (the buffer shared out among all active nodes) when K = 0."""
+        return int(self.n_select) * max(1, int(self.samples_per_node))
 
 
 @dataclasses.dataclass
@@ -332,7 +334,28 @@ def batch_workloads(seed: int = 0, n_queries: int = 256, *, samples=None, iterat
     return out
 
 
+# The uncapped form at the paper's large-delta sizes (App. B): every active
+# node is expanded, the candidate buffer holds t_e slots shared out as
+# lambda = floor(t_e / |V_A|), the tree holds t_e nodes, and the regions number
+# about the paper's 27,000 / 52,000 / 100,000 (30^3; 40 x 40 x 32 = 51,200;
+# 23^3 x 8 velocity-sign classes = 97,336).
+PAPER_SIZES = {
+    "di6": dict(n_select=100_000, samples=0, tree_cap=100_000, grid=(30, 30, 30)),
+    "dubins6": dict(n_select=300_000, samples=0, tree_cap=300_000, grid=(40, 40, 32)),
+    "quad12": dict(n_select=1_000_000, samples=0, tree_cap=1_000_000, grid=(23, 23, 23)),
+}
+
+
+def _paper(name):
+    def make(seed: int = 0, **overrides) -> Workload:
+        w = WORKLOADS[name](seed, **dict(PAPER_SIZES[name], **overrides))
+        w.name = name + "_paper"
+        return w
+    return make
+
+
 WORKLOADS = {"di6": di6_workload, "quad12": quad12_workload, "dubins6": dubins6_workload}
+WORKLOADS.update({n + "_paper": _paper(n) for n in ("di6", "quad12", "dubins6")})
 
 
 def make_workload(name: str, seed: int = 0, **overrides) -> Workload:
