@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kpx_oracle.c")
+SRC_DIFF = os.path.join(HERE, "kpx_oracle_diff.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 MAX_STATE = 12
@@ -91,11 +92,12 @@ class VerifyC(C.Structure):
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (strict IEEE float64, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
-            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "kpx_oracle.h"))):
+    deps = [SRC, SRC_DIFF, os.path.join(HERE, "kpx_oracle.h"), os.path.join(HERE, "kpx_oracle_diff.h")]
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(map(os.path.getmtime, deps)):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-                               "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
+                               "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, SRC, SRC_DIFF,
+                               "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -441,3 +443,99 @@ def run(P: Problem, iterations: int, on_step=None) -> Tree:
         if rc == FULL:
             break
     return T
+
+
+# ---------------------------------------------------------------- differentiable rollout
+
+class OradProblemC(C.Structure):
+    _fields_ = [
+        ("mass", C.c_double), ("jx", C.c_double), ("jy", C.c_double), ("jz", C.c_double),
+        ("grav", C.c_double), ("dt", C.c_double), ("boxes", _f32p), ("n_boxes", C.c_int32),
+        ("goal", C.c_double * 3), ("w_ctrl", C.c_double), ("w_obst", C.c_double),
+        ("k_obst", C.c_double), ("d_safe", C.c_double), ("w_goal", C.c_double),
+    ]
+
+
+_dlib = None
+
+
+def _diff_lib():
+    global _dlib
+    if _dlib is None:
+        L = lib()
+        pp = C.POINTER(OradProblemC)
+        L.orad_segment.argtypes = [C.c_int32, C.c_int32]
+        L.orad_segment.restype = C.c_int32
+        L.orad_box_sd.argtypes = [_f32p, _f64p]
+        L.orad_box_sd.restype = C.c_double
+        L.orad_loss.argtypes = [pp, _f64p, _f64p, C.c_int32, _f64p]
+        L.orad_loss.restype = C.c_double
+        L.orad_grad.argtypes = [pp, _f64p, _f64p, C.c_int32, C.c_double, _f64p]
+        L.orad_grad.restype = None
+        L.orad_first_invalid.argtypes = [pp, _f64p, _f64p, C.c_int32, _f64p, _f64p, _f64p, _f64p]
+        L.orad_first_invalid.restype = C.c_int32
+        _dlib = L
+    return _dlib
+
+
+class DiffProblem:
+    """The scene and loss weights of the differentiable rollout (float32
+    values widened, as everywhere in the oracle)."""
+
+    def __init__(self, problem, dt, goal=None, w_ctrl=0.1, w_obst=1.0, k_obst=50.0, d_safe=0.02,
+                 w_goal=1.0):
+        f = lambda v: float(np.float32(v))  # noqa: E731
+        self.problem = problem
+        self.boxes = np.ascontiguousarray(problem.boxes, dtype=np.float32).reshape(-1, 6)
+        s = OradProblemC()
+        dp = problem.dyn_params
+        s.mass, s.jx, s.jy, s.jz, s.grav = (f(dp[0]), f(dp[1]), f(dp[2]), f(dp[3]), f(dp[4]))
+        s.dt = f(dt)
+        s.boxes = _ptr(self.boxes, _f32p) if self.boxes.size else None
+        s.n_boxes = self.boxes.shape[0]
+        g = problem.goal_center if goal is None else goal
+        s.goal = (C.c_double * 3)(*[f(v) for v in g[:3]])
+        s.w_ctrl, s.w_obst, s.k_obst, s.d_safe, s.w_goal = (f(w_ctrl), f(w_obst), f(k_obst),
+                                                            f(d_safe), f(w_goal))
+        self.c = s
+        self.ref = C.byref(s)
+
+
+def diff_segment(k: int, n: int) -> int:
+    return int(_diff_lib().orad_segment(int(k), int(n)))
+
+
+def box_sd(box, p) -> float:
+    b = np.ascontiguousarray(box, dtype=np.float32)
+    q = np.ascontiguousarray(p, dtype=np.float64)
+    return float(_diff_lib().orad_box_sd(_ptr(b, _f32p), _ptr(q, _f64p)))
+
+
+def diff_loss(D, x0, u, n, states=False):
+    x = np.ascontiguousarray(x0, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(16)
+    st = np.zeros(((int(n) + 1), 12), np.float64) if states else None
+    L = _diff_lib().orad_loss(D.ref, _ptr(x, _f64p), _ptr(uu, _f64p), int(n),
+                              _ptr(st, _f64p) if states else None)
+    return (L, st) if states else L
+
+
+def diff_grad(D, x0, u, n, h=1e-20):
+    x = np.ascontiguousarray(x0, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(16)
+    g = np.zeros(16, np.float64)
+    _diff_lib().orad_grad(D.ref, _ptr(x, _f64p), _ptr(uu, _f64p), int(n), float(h), _ptr(g, _f64p))
+    return g
+
+
+def diff_first_invalid(D, x0, u, n):
+    p = D.problem
+    x = np.ascontiguousarray(x0, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(16)
+    lo = np.ascontiguousarray(np.asarray(p.x_lo, np.float64)[:12])
+    hi = np.ascontiguousarray(np.asarray(p.x_hi, np.float64)[:12])
+    wl = np.ascontiguousarray(np.asarray(p.ws_lo, np.float64)[:3])
+    wh = np.ascontiguousarray(np.asarray(p.ws_hi, np.float64)[:3])
+    return int(_diff_lib().orad_first_invalid(D.ref, _ptr(x, _f64p), _ptr(uu, _f64p), int(n),
+                                              _ptr(lo, _f64p), _ptr(hi, _f64p), _ptr(wl, _f64p),
+                                              _ptr(wh, _f64p)))

@@ -7,6 +7,8 @@ integration, no validity test, no sampling of controls.
 
 from .scenes import (  # noqa: F401
     batch_workloads,
+    diff_workload,
+    DiffBatch,
     DYNAMICS,
     COSTS,
     STATE_DIM,

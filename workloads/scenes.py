@@ -334,6 +334,41 @@ def batch_workloads(seed: int = 0, n_queries: int = 256, *, samples=None, iterat
     return out
 
 
+@dataclasses.dataclass
+class DiffBatch:
+    """Edges for the differentiable rollout: the quadrotor scene (problem), its
+    step size, and per edge a start state x0 (E x 12), 4 control segments u
+    (E x 16, segment-major) and a step count n (E)."""
+    problem: Problem
+    dt: float
+    x0: np.ndarray
+    u: np.ndarray
+    n: np.ndarray
+
+
+def diff_workload(seed: int = 0, n_edges: int = 65536, steps=(20, 40)) -> DiffBatch:
+    """Quadrotor edges in the 64-box wall scene of quad12_workload: starts
+    uniform over the start side (x in [0.05, 0.45], y, z in [0.05, 0.95]) with
+    small attitudes (|roll|, |pitch| <= 0.2), any yaw, velocities in
+    [-0.5, 0.5] and body rates in [-1, 1]; each of the 4 control segments
+    uniform in the control box; n uniform in steps, dt = 0.005."""
+    w = quad12_workload(seed)
+    rng = _rng(seed, 0xD1F)
+    E = int(n_edges)
+    x0 = np.zeros((E, 12), np.float32)
+    x0[:, 0] = rng.uniform(0.05, 0.45, E)
+    x0[:, 1:3] = rng.uniform(0.05, 0.95, (E, 2))
+    x0[:, 3:5] = rng.uniform(-0.2, 0.2, (E, 2))
+    x0[:, 5] = rng.uniform(-np.pi, np.pi, E)
+    x0[:, 6:9] = rng.uniform(-0.5, 0.5, (E, 3))
+    x0[:, 9:12] = rng.uniform(-1.0, 1.0, (E, 3))
+    lo = np.asarray(w.problem.u_lo[:4], np.float32)
+    hi = np.asarray(w.problem.u_hi[:4], np.float32)
+    u = (lo + (hi - lo) * rng.uniform(0.0, 1.0, (E, 4, 4))).astype(np.float32).reshape(E, 16)
+    n = rng.integers(steps[0], steps[1] + 1, E).astype(np.int32)
+    return DiffBatch(w.problem, w.params.dt, x0, u, n)
+
+
 # The uncapped form at the paper's large-delta sizes (App. B): every active
 # node is expanded, the candidate buffer holds t_e slots shared out as
 # lambda = floor(t_e / |V_A|), the tree holds t_e nodes, and the regions number
