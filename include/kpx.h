@@ -321,6 +321,63 @@ int kpx_batch_destroy(kpx_batch* b);
 /* Message for the last failing call on b (empty string if none). */
 const char* kpx_batch_last_error(const kpx_batch* b);
 
+/* ------------------------------------------------------ differentiable edges
+ * An extension past the paper, which cites gradient-based trajectory
+ * optimization only as related work (Sec. II): loss and control gradient of
+ * quadrotor edges (the Sec. V model and the planner's RK4 integrator), for
+ * local refinement of edges.  A batch holds E independent edges, each n RK4 steps of
+ * size dt (4 <= n <= 40) from x0 under 4 piecewise-constant control segments,
+ * step k using segment j with floor(j n / 4) <= k < floor((j + 1) n / 4).
+ * The loss of an edge is
+ *   n dt + w_ctrl |u|^2 + w_obst sum_{k=1..n} softplus(k_obst (d_safe - sd(p_k)))
+ *        + w_goal |p_n - goal|^2
+ * with sd(p) the signed distance of position p to the nearest box (negative
+ * inside); the gradient is with respect to the edge's 16 controls.  It is
+ * computed by reverse mode through the RK4 steps, in float32.
+ *
+ * Device arrays are structure-of-arrays over the edges: x0 is 12 x E
+ * (component i of edge e at i * E + e), u is 16 x E (control c of segment j
+ * at (4 j + c) * E + e), n, loss are E, grad is 16 x E.  An edge with n
+ * outside 4..40 gets loss NaN and a zero gradient. */
+typedef struct kpx_diff_problem {
+    float dyn_params[8];      /* mass, Ixx, Iyy, Izz, gravity (as for KPX_QUAD12) */
+    float dt;                 /* RK4 step, > 0 */
+    const float* boxes;       /* host, n_boxes x 6 (lo x y z, hi x y z); copied */
+    int32_t n_boxes;          /* 0 .. KPX_MAX_BOXES */
+    float goal[3];
+    float w_ctrl, w_obst, k_obst, d_safe, w_goal;
+    float u_lo[4], u_hi[4];   /* control box for kpx_diff_polish's projection */
+} kpx_diff_problem;
+
+typedef struct kpx_diff kpx_diff;
+
+/* Copies the problem to the device.  hip_stream (a hipStream_t, NULL for the
+ * default stream) orders every later call of the object.  KPX_ERR_ARG for
+ * non-positive mass, inertia or dt, u_lo > u_hi, a box with lo > hi, or a
+ * box count outside 0 .. KPX_MAX_BOXES;
+ * KPX_ERR_OOM / KPX_ERR_DEVICE otherwise.  *out is NULL on error. */
+int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out);
+
+/* Enqueues loss (device, E) and, when grad (device, 16 x E) is not NULL, the
+ * gradient of E edges (x0, u, n: device, layouts above); returns at once.
+ * The inputs are only read.  E = 0 does nothing.  KPX_ERR_ARG for a NULL
+ * pointer or E < 0; KPX_ERR_DEVICE if the launch fails. */
+int kpx_diff_loss_grad(kpx_diff* d, const float* x0, const float* u, const int32_t* n, int64_t E, float* loss,
+                       float* grad);
+
+/* Enqueues `steps` projected gradient steps u <- clamp(u - lr grad, u_lo, u_hi)
+ * on every edge, in place on u (device, 16 x E), and writes the loss of the
+ * final controls to loss (device, E).  steps = 0 only evaluates the loss.
+ * KPX_ERR_ARG for steps < 0, lr < 0 or NaN, or as kpx_diff_loss_grad. */
+int kpx_diff_polish(kpx_diff* d, const float* x0, float* u, const int32_t* n, int64_t E, int32_t steps, float lr,
+                    float* loss);
+
+/* Waits for the object's work and releases it.  NULL is ok. */
+int kpx_diff_destroy(kpx_diff* d);
+
+/* Message for the last failing call on d (empty string if none). */
+const char* kpx_diff_last_error(const kpx_diff* d);
+
 #ifdef __cplusplus
 }
 #endif

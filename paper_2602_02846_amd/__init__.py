@@ -8,3 +8,4 @@ from .kpx import (  # noqa: F401
     ACTIVE, INACTIVE, TERMINAL, Batch, KPXError, Planner, lib, philox, workspace_bytes,
     status_string, OK, FULL,
 )
+from .diff import Rollout, edge_loss  # noqa: F401,E402

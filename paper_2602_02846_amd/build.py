@@ -6,7 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "kpx.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "kpx_device.hpp"),
+SRC_DIFF = os.path.join(HERE, "csrc", "kpx_diff.hip")
+DEPS = [SRC, SRC_DIFF, os.path.join(HERE, "csrc", "kpx_device.hpp"),
         os.path.join(os.path.dirname(HERE), "include", "kpx.h")]
 LIB = os.path.join(HERE, "libkpx.so")
 
@@ -30,7 +31,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
             os.path.getmtime(p) for p in DEPS):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC, SRC_DIFF]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)

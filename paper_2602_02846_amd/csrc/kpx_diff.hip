@@ -1,0 +1,514 @@
+// kpx_diff.hip -- differentiable quadrotor edge rollout on MI355X (gfx950):
+// loss and its gradient with respect to the edge's controls, for batches of
+// independent edges, behind the kpx_diff_* calls of include/kpx.h.
+//
+// An edge is n RK4 steps (the planner's integrator and 12D quadrotor model,
+// Sec. V) of size dt from x0 under 4 piecewise-constant control segments; step
+// k uses segment j with floor(j n / 4) <= k < floor((j + 1) n / 4).  Its loss
+//   n dt + w_ctrl |u|^2 + w_obst sum_{k=1..n} softplus(k_obst (d_safe - sd(p_k)))
+//        + w_goal |p_n - goal|^2
+// adds to the edge's duration a control effort, a smooth obstacle penalty on
+// the signed distance sd of each substep position to the nearest box, and a
+// goal distance.  One thread per edge.  The forward pass keeps the state every
+// 8 steps; the backward pass recomputes each 8-step block from its checkpoint
+// and runs the adjoint of the RK4 steps through it (reverse-mode, with the
+// vector-Jacobian product of the dynamics written out by hand).
+#include "../../include/kpx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <string>
+
+namespace {
+
+constexpr int kDiffBlock = 256;
+constexpr int kCkpt = 8;                      // steps per checkpoint block
+constexpr int kMaxBlocks = 5;                 // checkpoint blocks: n <= 40
+constexpr int kDiffMaxSteps = kCkpt * kMaxBlocks;
+constexpr int kDiffMaxBoxes = 1024;  // 32 KiB of LDS beside 60 KiB of checkpoints
+
+struct DiffConst {
+    float inv_m, inv_j[3], gyro[3], grav, dt;
+    float goal[3];
+    float w_ctrl, w_obst, k_obst, d_safe, w_goal;
+    float u_lo[4], u_hi[4];
+    int n_boxes;
+};
+
+// dynamics: state (position, ZYX Euler angles phi theta psi, world-frame
+// velocity, body rates p q r), control (thrust, body torques)
+__device__ __forceinline__ void f_quad(const DiffConst& C, const float* x, const float* u, float* xd)
+{
+    float sph, cph, sth, cth, sps, cps;
+    __sincosf(x[3], &sph, &cph);
+    __sincosf(x[4], &sth, &cth);
+    __sincosf(x[5], &sps, &cps);
+    const float sec = 1.0f / cth, tth = sth * sec;
+    const float a = sph * x[10] + cph * x[11];
+    xd[0] = x[6];
+    xd[1] = x[7];
+    xd[2] = x[8];
+    xd[3] = x[9] + a * tth;
+    xd[4] = cph * x[10] - sph * x[11];
+    xd[5] = a * sec;
+    const float acc = u[0] * C.inv_m;
+    xd[6] = acc * (cps * sth * cph + sps * sph);
+    xd[7] = acc * (sps * sth * cph - cps * sph);
+    xd[8] = acc * (cth * cph) - C.grav;
+    xd[9] = (u[1] - C.gyro[0] * x[10] * x[11]) * C.inv_j[0];
+    xd[10] = (u[2] - C.gyro[1] * x[9] * x[11]) * C.inv_j[1];
+    xd[11] = (u[3] - C.gyro[2] * x[9] * x[10]) * C.inv_j[2];
+}
+
+// vector-Jacobian product of f_quad: gx += (df/dx)^T w, gu += (df/du)^T w
+__device__ __forceinline__ void vjp_quad(const DiffConst& C, const float* x, const float* u, const float* w,
+                                         float* gx, float* gu)
+{
+    float sph, cph, sth, cth, sps, cps;
+    __sincosf(x[3], &sph, &cph);
+    __sincosf(x[4], &sth, &cth);
+    __sincosf(x[5], &sps, &cps);
+    const float sec = 1.0f / cth, tth = sth * sec;
+    const float wp = x[9], wq = x[10], wr = x[11];
+    const float a = sph * wq + cph * wr;  // d a / d phi = b
+    const float b = cph * wq - sph * wr;
+    // position rates = velocity
+    gx[6] += w[0];
+    gx[7] += w[1];
+    gx[8] += w[2];
+    // Euler-angle rates
+    gx[3] += w[3] * b * tth - w[4] * a + w[5] * b * sec;
+    gx[4] += w[3] * a * sec * sec + w[5] * a * sec * tth;
+    gx[9] += w[3];
+    gx[10] += w[3] * sph * tth + w[4] * cph + w[5] * sph * sec;
+    gx[11] += w[3] * cph * tth - w[4] * sph + w[5] * cph * sec;
+    // thrust along the rotated body axis
+    const float acc = u[0] * C.inv_m;
+    const float r0 = cps * sth * cph + sps * sph, r1 = sps * sth * cph - cps * sph, r2 = cth * cph;
+    gu[0] += (w[6] * r0 + w[7] * r1 + w[8] * r2) * C.inv_m;
+    gx[3] += acc * (w[6] * (sps * cph - cps * sth * sph) - w[7] * (sps * sth * sph + cps * cph) -
+                    w[8] * cth * sph);
+    gx[4] += acc * cph * (w[6] * cps * cth + w[7] * sps * cth - w[8] * sth);
+    gx[5] += acc * (w[6] * (cps * sph - sps * sth * cph) + w[7] * (cps * sth * cph + sps * sph));
+    // Euler's equations
+    const float w9 = w[9] * C.inv_j[0], w10 = w[10] * C.inv_j[1], w11 = w[11] * C.inv_j[2];
+    gu[1] += w9;
+    gu[2] += w10;
+    gu[3] += w11;
+    gx[9] -= w10 * C.gyro[1] * wr + w11 * C.gyro[2] * wq;
+    gx[10] -= w9 * C.gyro[0] * wr + w11 * C.gyro[2] * wp;
+    gx[11] -= w9 * C.gyro[0] * wq + w10 * C.gyro[1] * wp;
+}
+
+__device__ __forceinline__ void rk4_step(const DiffConst& C, float* x, const float* u)
+{
+    const float h = C.dt, h2 = 0.5f * C.dt, h6 = C.dt / 6.0f;
+    float k[12], acc[12], t[12];
+    f_quad(C, x, u, k);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        acc[i] = k[i];
+        t[i] = fmaf(h2, k[i], x[i]);
+    }
+    f_quad(C, t, u, k);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        acc[i] = fmaf(2.f, k[i], acc[i]);
+        t[i] = fmaf(h2, k[i], x[i]);
+    }
+    f_quad(C, t, u, k);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        acc[i] = fmaf(2.f, k[i], acc[i]);
+        t[i] = fmaf(h, k[i], x[i]);
+    }
+    f_quad(C, t, u, k);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) x[i] = fmaf(h6, acc[i] + k[i], x[i]);
+}
+
+// Adjoint of one RK4 step from x: lam (dL/dx_{k+1}) becomes dL/dx_k, and
+// gu accumulates dL/du through this step.  The stages are recomputed.
+__device__ __forceinline__ void rk4_vjp(const DiffConst& C, const float* x, const float* u, float* lam, float* gu)
+{
+    const float h = C.dt, h2 = 0.5f * C.dt, h6 = C.dt / 6.0f, h3 = C.dt / 3.0f;
+    float k1[12], k2[12], k3[12], x2[12], x3[12], x4[12];
+    f_quad(C, x, u, k1);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) x2[i] = fmaf(h2, k1[i], x[i]);
+    f_quad(C, x2, u, k2);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) x3[i] = fmaf(h2, k2[i], x[i]);
+    f_quad(C, x3, u, k3);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) x4[i] = fmaf(h, k3[i], x[i]);
+    float a[12], g[12], out[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        out[i] = lam[i];
+        a[i] = h6 * lam[i];  // adjoint of k4
+        g[i] = 0.f;
+    }
+    vjp_quad(C, x4, u, a, g, gu);  // g = dL/dx4
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        out[i] += g[i];
+        a[i] = fmaf(h3, lam[i], h * g[i]);  // adjoint of k3
+        g[i] = 0.f;
+    }
+    vjp_quad(C, x3, u, a, g, gu);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        out[i] += g[i];
+        a[i] = fmaf(h3, lam[i], h2 * g[i]);  // adjoint of k2
+        g[i] = 0.f;
+    }
+    vjp_quad(C, x2, u, a, g, gu);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        out[i] += g[i];
+        a[i] = fmaf(h6, lam[i], h2 * g[i]);  // adjoint of k1
+        g[i] = 0.f;
+    }
+    vjp_quad(C, x, u, a, g, gu);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) lam[i] = out[i] + g[i];
+}
+
+// Signed distance of p to the nearest box (LDS, two float4 per box), and its
+// gradient: the box's q = max(lo - p, p - hi) per axis decides outside
+// (|max(q, 0)|, > 0) or inside (max q, <= 0).  Any box that holds p is nearer
+// than every box that does not; the search keeps the smallest squared outside
+// distance and the smallest inside max q, so one square root remains.  Ties
+// go to the first box.
+__device__ __forceinline__ float nearest_sd(const float4* box, int nb, const float* p, float* grad)
+{
+    float best_out2 = INFINITY, best_in = INFINITY;
+    int bo = -1, bi = -1;
+    for (int b = 0; b < nb; ++b) {
+        const float4 lo = box[2 * b], hi = box[2 * b + 1];
+        const float qx = fmaxf(lo.x - p[0], p[0] - hi.x);
+        const float qy = fmaxf(lo.y - p[1], p[1] - hi.y);
+        const float qz = fmaxf(lo.z - p[2], p[2] - hi.z);
+        const float m = fmaxf(qx, fmaxf(qy, qz));
+        if (m > 0.f) {
+            const float ox = fmaxf(qx, 0.f), oy = fmaxf(qy, 0.f), oz = fmaxf(qz, 0.f);
+            const float o2 = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+            if (o2 < best_out2) {
+                best_out2 = o2;
+                bo = b;
+            }
+        } else if (m < best_in) {
+            best_in = m;
+            bi = b;
+        }
+    }
+    grad[0] = grad[1] = grad[2] = 0.f;
+    const int b = bi >= 0 ? bi : bo;
+    if (b < 0) return INFINITY;  // no boxes
+    const float4 lo = box[2 * b], hi = box[2 * b + 1];
+    const float lov[3] = {lo.x, lo.y, lo.z}, hiv[3] = {hi.x, hi.y, hi.z};
+    float q[3], s[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float below = lov[i] - p[i], above = p[i] - hiv[i];
+        q[i] = fmaxf(below, above);
+        s[i] = below >= above ? -1.f : 1.f;  // dq / dp
+    }
+    if (bi >= 0) {  // inside: sd = max q
+        int ai = 0;
+        if (q[1] > q[ai]) ai = 1;
+        if (q[2] > q[ai]) ai = 2;
+        grad[ai] = s[ai];
+        return q[ai];
+    }
+    const float d = sqrtf(best_out2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) grad[i] = q[i] > 0.f ? s[i] * q[i] / d : 0.f;
+    return d;
+}
+
+__device__ __forceinline__ float softplus(float z)
+{
+    return z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+}
+
+__device__ __forceinline__ float sigmoid(float z)
+{
+    return 1.f / (1.f + expf(-z));
+}
+
+// obstacle penalty of position p, with dP/dp added to g (scaled by w_obst)
+__device__ __forceinline__ float penalty(const DiffConst& C, const float4* box, const float* p, float* g)
+{
+    if (C.n_boxes == 0 || C.w_obst == 0.f) return 0.f;
+    float gs[3];
+    const float sd = nearest_sd(box, C.n_boxes, p, gs);
+    const float z = C.k_obst * (C.d_safe - sd);
+    if (g) {
+        const float c = -C.w_obst * C.k_obst * sigmoid(z);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) g[i] += c * gs[i];
+    }
+    return C.w_obst * softplus(z);
+}
+
+__device__ __forceinline__ void segment_controls(const float* u, int seg, float* us)
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) us[c] = seg == 0 ? u[c] : seg == 1 ? u[4 + c] : seg == 2 ? u[8 + c] : u[12 + c];
+}
+
+// Loss of edge e and, when grad != nullptr, its gradient with respect to the
+// 16 controls; `polish` > 0 instead takes that many projected gradient steps
+// u <- clamp(u - lr * grad, u_lo, u_hi) in place and leaves the final loss.
+// Dynamic LDS: the boxes (2 float4 each), then the checkpoints x_0, x_8, ...
+// of every thread ([slot * 12 + component][thread]).
+__global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* __restrict__ boxes,
+                                                     const float* __restrict__ x0g, float* __restrict__ ug,
+                                                     const int* __restrict__ ng, long long E,
+                                                     float* __restrict__ loss, float* __restrict__ grad,
+                                                     int polish, float lr)
+{
+    extern __shared__ float4 lds[];
+    float4* sbox = lds;
+    float* sck = reinterpret_cast<float*>(lds + 2 * C.n_boxes);
+    for (int i = threadIdx.x; i < 2 * C.n_boxes; i += blockDim.x) sbox[i] = boxes[i];
+    __syncthreads();
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    float* ck = sck + threadIdx.x;  // component i of slot b at ck[(b * 12 + i) * kDiffBlock]
+    const int n = ng[e];
+    float u[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) u[i] = ug[(long long)i * E + e];
+    if (n < 4 || n > kDiffMaxSteps) {  // outside the supported edge lengths
+        loss[e] = NAN;
+        if (grad)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) grad[(long long)i * E + e] = 0.f;
+        return;
+    }
+    const int b1 = n / 4, b2 = n / 2, b3 = (3 * n) / 4;  // segment boundaries
+    const int n_blk = (n + kCkpt - 1) / kCkpt;
+    const int rounds = polish > 0 ? polish + 1 : 1;
+    float L = 0.f;
+    for (int round = 0; round < rounds; ++round) {
+        const bool need_grad = grad != nullptr || round + 1 < rounds;
+        // forward, keeping x_k at slot k / 8 for k = 0, 8, ..
+        float x[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) x[i] = x0g[(long long)i * E + e];
+        float pen = 0.f;
+        for (int k = 0; k < n; ++k) {
+            if (k % kCkpt == 0 && need_grad)
+#pragma unroll
+                for (int i = 0; i < 12; ++i) ck[((k / kCkpt) * 12 + i) * kDiffBlock] = x[i];
+            float us[4];
+            segment_controls(u, (k >= b1) + (k >= b2) + (k >= b3), us);
+            rk4_step(C, x, us);
+            pen += penalty(C, sbox, x, nullptr);
+        }
+        float u2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) u2 = fmaf(u[i], u[i], u2);
+        float gd2 = 0.f, lam[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) lam[i] = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float d = x[a] - C.goal[a];
+            gd2 = fmaf(d, d, gd2);
+            lam[a] = 2.f * C.w_goal * d;
+        }
+        L = n * C.dt + C.w_ctrl * u2 + pen + C.w_goal * gd2;
+        if (!need_grad) break;
+        // backward, block by block from the last: recompute the block's states
+        // from its checkpoint, then the adjoint of its steps in reverse.  x
+        // still holds x_n.
+        float gu[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) gu[i] = 2.f * C.w_ctrl * u[i];
+        for (int blk = n_blk - 1; blk >= 0; --blk) {
+            const int k0 = blk * kCkpt;
+            float xb[kCkpt + 1][12];  // x_{k0} .. x_{k0 + 8} (entries past x_n unused)
+#pragma unroll
+            for (int i = 0; i < 12; ++i) xb[0][i] = ck[(blk * 12 + i) * kDiffBlock];
+#pragma unroll
+            for (int t = 0; t < kCkpt; ++t) {
+                const int k = k0 + t;
+#pragma unroll
+                for (int i = 0; i < 12; ++i) xb[t + 1][i] = xb[t][i];
+                if (k + 1 < n) {  // x_n itself is x
+                    float us[4];
+                    segment_controls(u, (k >= b1) + (k >= b2) + (k >= b3), us);
+                    rk4_step(C, xb[t + 1], us);
+                } else if (k + 1 == n) {
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) xb[t + 1][i] = x[i];
+                }
+            }
+#pragma unroll
+            for (int t = kCkpt - 1; t >= 0; --t) {
+                const int k = k0 + t;  // step k: x_k -> x_{k+1}
+                if (k >= n) continue;
+                const int seg = (k >= b1) + (k >= b2) + (k >= b3);
+                float us[4], gs[4] = {0.f, 0.f, 0.f, 0.f};
+                segment_controls(u, seg, us);
+                penalty(C, sbox, xb[t + 1], lam);  // the penalty term of x_{k+1}
+                rk4_vjp(C, xb[t], us, lam, gs);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    gu[c] += seg == 0 ? gs[c] : 0.f;
+                    gu[4 + c] += seg == 1 ? gs[c] : 0.f;
+                    gu[8 + c] += seg == 2 ? gs[c] : 0.f;
+                    gu[12 + c] += seg == 3 ? gs[c] : 0.f;
+                }
+            }
+        }
+        if (round + 1 < rounds) {  // a projected gradient step
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int c = i & 3;
+                u[i] = fminf(fmaxf(u[i] - lr * gu[i], C.u_lo[c]), C.u_hi[c]);
+            }
+        } else if (grad) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) grad[(long long)i * E + e] = gu[i];
+        }
+    }
+    loss[e] = L;
+    if (polish > 0)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) ug[(long long)i * E + e] = u[i];
+}
+
+}  // namespace
+
+struct kpx_diff {
+    DiffConst C;
+    float4* boxes = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+extern "C" {
+
+int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out)
+{
+    if (!p || !out) return KPX_ERR_ARG;
+    *out = nullptr;
+    if (p->n_boxes < 0 || p->n_boxes > kDiffMaxBoxes || (p->n_boxes > 0 && !p->boxes)) return KPX_ERR_ARG;
+    const float m = p->dyn_params[0], jx = p->dyn_params[1], jy = p->dyn_params[2], jz = p->dyn_params[3];
+    if (!(m > 0.f) || !(jx > 0.f) || !(jy > 0.f) || !(jz > 0.f) || !(p->dt > 0.f)) return KPX_ERR_ARG;
+    for (int c = 0; c < 4; ++c)
+        if (!(p->u_lo[c] <= p->u_hi[c])) return KPX_ERR_ARG;
+    for (int b = 0; b < p->n_boxes; ++b)
+        for (int a = 0; a < 3; ++a)
+            if (!(p->boxes[6 * b + a] <= p->boxes[6 * b + 3 + a])) return KPX_ERR_ARG;
+    // dynamic LDS beyond the default limit (many boxes beside the checkpoints)
+    const size_t lds_max = sizeof(float4) * 2 * kDiffMaxBoxes + sizeof(float) * kMaxBlocks * 12 * kDiffBlock;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_diff), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_max) != hipSuccess)
+        return KPX_ERR_DEVICE;
+    kpx_diff* d = new (std::nothrow) kpx_diff;
+    if (!d) return KPX_ERR_OOM;
+    DiffConst& C = d->C;
+    C.inv_m = 1.0f / m;
+    C.inv_j[0] = 1.0f / jx;
+    C.inv_j[1] = 1.0f / jy;
+    C.inv_j[2] = 1.0f / jz;
+    C.gyro[0] = jz - jy;
+    C.gyro[1] = jx - jz;
+    C.gyro[2] = jy - jx;
+    C.grav = p->dyn_params[4];
+    C.dt = p->dt;
+    for (int a = 0; a < 3; ++a) C.goal[a] = p->goal[a];
+    C.w_ctrl = p->w_ctrl;
+    C.w_obst = p->w_obst;
+    C.k_obst = p->k_obst;
+    C.d_safe = p->d_safe;
+    C.w_goal = p->w_goal;
+    for (int c = 0; c < 4; ++c) {
+        C.u_lo[c] = p->u_lo[c];
+        C.u_hi[c] = p->u_hi[c];
+    }
+    C.n_boxes = p->n_boxes;
+    d->stream = (hipStream_t)hip_stream;
+    const size_t nb = (size_t)(p->n_boxes > 0 ? p->n_boxes : 1);
+    if (hipMalloc(&d->boxes, sizeof(float4) * 2 * nb) != hipSuccess) {
+        delete d;
+        return KPX_ERR_OOM;
+    }
+    float4* hb = new (std::nothrow) float4[2 * nb];
+    if (!hb) {
+        (void)hipFree(d->boxes);
+        delete d;
+        return KPX_ERR_OOM;
+    }
+    for (int b = 0; b < p->n_boxes; ++b) {
+        const float* s = p->boxes + 6 * b;
+        hb[2 * b] = make_float4(s[0], s[1], s[2], 0.f);
+        hb[2 * b + 1] = make_float4(s[3], s[4], s[5], 0.f);
+    }
+    const hipError_t e = p->n_boxes > 0 ? hipMemcpy(d->boxes, hb, sizeof(float4) * 2 * p->n_boxes,
+                                                    hipMemcpyHostToDevice)
+                                        : hipSuccess;
+    delete[] hb;
+    if (e != hipSuccess) {
+        (void)hipFree(d->boxes);
+        delete d;
+        return KPX_ERR_DEVICE;
+    }
+    *out = d;
+    return KPX_OK;
+}
+
+static int diff_launch(kpx_diff* d, const float* x0, float* u, const int32_t* n, int64_t E, float* loss,
+                       float* grad, int polish, float lr)
+{
+    if (!d || E < 0 || (E > 0 && (!x0 || !u || !n || !loss))) return KPX_ERR_ARG;
+    if (E == 0) return KPX_OK;
+    const long long blocks = (E + kDiffBlock - 1) / kDiffBlock;
+    if (blocks > 0x7FFFFFFFll) return KPX_ERR_ARG;
+    const size_t lds = sizeof(float4) * 2 * d->C.n_boxes + sizeof(float) * kMaxBlocks * 12 * kDiffBlock;
+    k_diff<<<(unsigned)blocks, kDiffBlock, lds, d->stream>>>(d->C, d->boxes, x0, u, n, E, loss, grad, polish, lr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        d->err = hipGetErrorString(e);
+        return KPX_ERR_DEVICE;
+    }
+    return KPX_OK;
+}
+
+int kpx_diff_loss_grad(kpx_diff* d, const float* x0, const float* u, const int32_t* n, int64_t E, float* loss,
+                       float* grad)
+{
+    return diff_launch(d, x0, const_cast<float*>(u), n, E, loss, grad, 0, 0.f);
+}
+
+int kpx_diff_polish(kpx_diff* d, const float* x0, float* u, const int32_t* n, int64_t E, int32_t steps, float lr,
+                    float* loss)
+{
+    if (steps < 0 || !(lr >= 0.f)) return KPX_ERR_ARG;
+    return diff_launch(d, x0, u, n, E, loss, nullptr, steps, lr);
+}
+
+int kpx_diff_destroy(kpx_diff* d)
+{
+    if (!d) return KPX_OK;
+    if (d->stream) (void)hipStreamSynchronize(d->stream);
+    else (void)hipDeviceSynchronize();
+    if (d->boxes) (void)hipFree(d->boxes);
+    delete d;
+    return KPX_OK;
+}
+
+const char* kpx_diff_last_error(const kpx_diff* d)
+{
+    return d ? d->err.c_str() : "";
+}
+
+}  // extern "C"

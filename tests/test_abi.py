@@ -91,3 +91,43 @@ def test_null_arguments(kpx):
     assert L.kpx_batch_set_graph(None, 1) == -1
     assert L.kpx_batch_iterate(None, 1) == -1
     assert L.kpx_batch_destroy(None) == 0
+
+
+def test_diff_invalid_arguments_are_rejected(kpx):
+    from paper_2602_02846_amd import diff
+
+    w = W.make_workload("quad12", 0)
+    dt = w.params.dt
+
+    def status(edit=None, dt=dt):
+        ww = W.make_workload("quad12", 0)
+        if edit:
+            edit(ww.problem)
+        return diff.create_status(ww.problem, dt)
+
+    assert status(dt=0.0) == -1
+    assert status(lambda p: p.dyn_params.__setitem__(0, 0.0)) == -1  # mass
+    assert status(lambda p: p.dyn_params.__setitem__(2, -1.0)) == -1  # inertia
+
+    def flip_u(p):
+        p.u_lo[1], p.u_hi[1] = p.u_hi[1], p.u_lo[1]
+    assert status(flip_u) == -1
+
+    def flip_box(p):
+        p.boxes[3, 1], p.boxes[3, 4] = p.boxes[3, 4], p.boxes[3, 1]
+    assert status(flip_box) == -1
+
+    def many_boxes(p):
+        p.boxes = np.tile(p.boxes, (1025 // len(p.boxes) + 1, 1))[:1025]
+    assert status(many_boxes) == -1
+
+
+def test_diff_null_arguments(kpx):
+    from paper_2602_02846_amd import diff
+
+    L = diff._lib()
+    assert L.kpx_diff_create(None, None, None) == -1
+    assert L.kpx_diff_loss_grad(None, None, None, None, 1, None, None) == -1
+    assert L.kpx_diff_polish(None, None, None, None, 1, 1, 0.1, None) == -1
+    assert L.kpx_diff_destroy(None) == 0
+    assert L.kpx_diff_last_error(None) == b""
