@@ -27,7 +27,7 @@ constexpr int kDiffBlock = 256;
 constexpr int kCkpt = 8;                      // steps per checkpoint block
 constexpr int kMaxBlocks = 5;                 // checkpoint blocks: n <= 40
 constexpr int kDiffMaxSteps = kCkpt * kMaxBlocks;
-constexpr int kDiffMaxBoxes = 1024;  // 32 KiB of LDS beside 60 KiB of checkpoints
+constexpr int kDiffMaxBoxes = 1024;  // 64 KiB of LDS beside 80 KiB of per-edge records
 
 struct DiffConst {
     float inv_m, inv_j[3], gyro[3], grav, dt;
@@ -177,37 +177,39 @@ __device__ __forceinline__ void rk4_vjp(const DiffConst& C, const float* x, cons
     for (int i = 0; i < 12; ++i) lam[i] = out[i] + g[i];
 }
 
-// Signed distance of p to the nearest box (LDS, two float4 per box), and its
-// gradient: the box's q = max(lo - p, p - hi) per axis decides outside
-// (|max(q, 0)|, > 0) or inside (max q, <= 0).  Any box that holds p is nearer
-// than every box that does not; the search keeps the smallest squared outside
-// distance and the smallest inside max q, so one square root remains.  Ties
-// go to the first box.
-__device__ __forceinline__ float nearest_sd(const float4* box, int nb, const float* p, float* grad)
+// Index of the box nearest to p (-1 without boxes or for a NaN position).
+// The scan reads each box as centre and half extent (cx cy cz pad ex ey ez
+// pad, LDS) at a wave-uniform index, so every read is a broadcast, and
+// q = |p - c| - e per axis.  The key orders by signed distance without a
+// square root: |max(q, 0)|^2 + min(max q, 0) is the squared distance of a box
+// that does not hold p (positive) and the signed distance max q <= 0 of one
+// that does, so holding boxes come first.  Ties go to the first box.
+__device__ __forceinline__ int nearest_box(const float4* ce, int nb, const float* p)
 {
-    float best_out2 = INFINITY, best_in = INFINITY;
-    int bo = -1, bi = -1;
+    float best = INFINITY;
+    int bi = -1;
+#pragma unroll 8
     for (int b = 0; b < nb; ++b) {
-        const float4 lo = box[2 * b], hi = box[2 * b + 1];
-        const float qx = fmaxf(lo.x - p[0], p[0] - hi.x);
-        const float qy = fmaxf(lo.y - p[1], p[1] - hi.y);
-        const float qz = fmaxf(lo.z - p[2], p[2] - hi.z);
+        const float4 c = ce[2 * b], e = ce[2 * b + 1];
+        const float qx = fabsf(p[0] - c.x) - e.x;
+        const float qy = fabsf(p[1] - c.y) - e.y;
+        const float qz = fabsf(p[2] - c.z) - e.z;
         const float m = fmaxf(qx, fmaxf(qy, qz));
-        if (m > 0.f) {
-            const float ox = fmaxf(qx, 0.f), oy = fmaxf(qy, 0.f), oz = fmaxf(qz, 0.f);
-            const float o2 = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
-            if (o2 < best_out2) {
-                best_out2 = o2;
-                bo = b;
-            }
-        } else if (m < best_in) {
-            best_in = m;
+        const float ox = fmaxf(qx, 0.f), oy = fmaxf(qy, 0.f), oz = fmaxf(qz, 0.f);
+        const float key = fmaf(ox, ox, fmaf(oy, oy, fmaf(oz, oz, fminf(m, 0.f))));
+        if (key < best) {
+            best = key;
             bi = b;
         }
     }
-    grad[0] = grad[1] = grad[2] = 0.f;
-    const int b = bi >= 0 ? bi : bo;
-    if (b < 0) return INFINITY;  // no boxes
+    return bi;
+}
+
+// Signed distance of p to box b (LDS, two float4 per box) and its gradient:
+// q = max(lo - p, p - hi) per axis; outside (max q > 0) sd = |max(q, 0)|,
+// inside sd = max q (the first axis on ties).
+__device__ __forceinline__ float box_sd(const float4* box, int b, const float* p, float* grad)
+{
     const float4 lo = box[2 * b], hi = box[2 * b + 1];
     const float lov[3] = {lo.x, lo.y, lo.z}, hiv[3] = {hi.x, hi.y, hi.z};
     float q[3], s[3];
@@ -217,16 +219,21 @@ __device__ __forceinline__ float nearest_sd(const float4* box, int nb, const flo
         q[i] = fmaxf(below, above);
         s[i] = below >= above ? -1.f : 1.f;  // dq / dp
     }
-    if (bi >= 0) {  // inside: sd = max q
+    const float m = fmaxf(q[0], fmaxf(q[1], q[2]));
+    if (!(m > 0.f)) {
         int ai = 0;
         if (q[1] > q[ai]) ai = 1;
         if (q[2] > q[ai]) ai = 2;
-        grad[ai] = s[ai];
-        return q[ai];
-    }
-    const float d = sqrtf(best_out2);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) grad[i] = q[i] > 0.f ? s[i] * q[i] / d : 0.f;
+        for (int i = 0; i < 3; ++i) grad[i] = i == ai ? s[i] : 0.f;
+        return m;
+    }
+    float o[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o[i] = fmaxf(q[i], 0.f);
+    const float d = sqrtf(fmaf(o[0], o[0], fmaf(o[1], o[1], o[2] * o[2])));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) grad[i] = s[i] * o[i] / d;
     return d;
 }
 
@@ -240,12 +247,13 @@ __device__ __forceinline__ float sigmoid(float z)
     return 1.f / (1.f + expf(-z));
 }
 
-// obstacle penalty of position p, with dP/dp added to g (scaled by w_obst)
-__device__ __forceinline__ float penalty(const DiffConst& C, const float4* box, const float* p, float* g)
+// obstacle penalty of position p with nearest box b (< 0: none), with
+// dP/dp added to g when g is not null
+__device__ __forceinline__ float penalty(const DiffConst& C, const float4* box, int b, const float* p, float* g)
 {
-    if (C.n_boxes == 0 || C.w_obst == 0.f) return 0.f;
+    if (b < 0 || C.w_obst == 0.f) return 0.f;
     float gs[3];
-    const float sd = nearest_sd(box, C.n_boxes, p, gs);
+    const float sd = box_sd(box, b, p, gs);
     const float z = C.k_obst * (C.d_safe - sd);
     if (g) {
         const float c = -C.w_obst * C.k_obst * sigmoid(z);
@@ -264,8 +272,10 @@ __device__ __forceinline__ void segment_controls(const float* u, int seg, float*
 // Loss of edge e and, when grad != nullptr, its gradient with respect to the
 // 16 controls; `polish` > 0 instead takes that many projected gradient steps
 // u <- clamp(u - lr * grad, u_lo, u_hi) in place and leaves the final loss.
-// Dynamic LDS: the boxes (2 float4 each), then the checkpoints x_0, x_8, ...
-// of every thread ([slot * 12 + component][thread]).
+// Dynamic LDS: the boxes (2 float4 each as lo, hi, then 2 each as centre,
+// half extent), the checkpoints x_0, x_8, ... of
+// every thread ([slot * 12 + component][thread]), and the nearest box of
+// every x_{k+1} ([k][thread], 16 bits).
 __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* __restrict__ boxes,
                                                      const float* __restrict__ x0g, float* __restrict__ ug,
                                                      const int* __restrict__ ng, long long E,
@@ -274,12 +284,15 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
 {
     extern __shared__ float4 lds[];
     float4* sbox = lds;
-    float* sck = reinterpret_cast<float*>(lds + 2 * C.n_boxes);
-    for (int i = threadIdx.x; i < 2 * C.n_boxes; i += blockDim.x) sbox[i] = boxes[i];
+    float* sck = reinterpret_cast<float*>(lds + 4 * C.n_boxes);
+    unsigned short* sidx = reinterpret_cast<unsigned short*>(sck + kMaxBlocks * 12 * kDiffBlock);
+    for (int i = threadIdx.x; i < 4 * C.n_boxes; i += blockDim.x) sbox[i] = boxes[i];
     __syncthreads();
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     float* ck = sck + threadIdx.x;  // component i of slot b at ck[(b * 12 + i) * kDiffBlock]
+    unsigned short* nbox = sidx + threadIdx.x;  // nearest box of x_{k+1} at nbox[k * kDiffBlock]
+    const int nb = C.w_obst != 0.f ? C.n_boxes : 0;
     const int n = ng[e];
     float u[16];
 #pragma unroll
@@ -309,7 +322,9 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
             float us[4];
             segment_controls(u, (k >= b1) + (k >= b2) + (k >= b3), us);
             rk4_step(C, x, us);
-            pen += penalty(C, sbox, x, nullptr);
+            const int bi = nearest_box(sbox + 2 * C.n_boxes, nb, x);
+            if (need_grad) nbox[k * kDiffBlock] = (unsigned short)bi;
+            pen += penalty(C, sbox, bi, x, nullptr);
         }
         float u2 = 0.f;
 #pragma unroll
@@ -357,7 +372,8 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
                 const int seg = (k >= b1) + (k >= b2) + (k >= b3);
                 float us[4], gs[4] = {0.f, 0.f, 0.f, 0.f};
                 segment_controls(u, seg, us);
-                penalty(C, sbox, xb[t + 1], lam);  // the penalty term of x_{k+1}
+                const int bi = nb > 0 ? (int)(short)nbox[k * kDiffBlock] : -1;
+                penalty(C, sbox, bi, xb[t + 1], lam);  // the penalty term of x_{k+1}
                 rk4_vjp(C, xb[t], us, lam, gs);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
@@ -387,6 +403,13 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
 
 }  // namespace
 
+// dynamic LDS of k_diff: boxes, checkpoints, nearest-box indices
+static size_t lds_bytes(int n_boxes)
+{
+    return sizeof(float4) * 4 * n_boxes + sizeof(float) * kMaxBlocks * 12 * kDiffBlock +
+           sizeof(unsigned short) * kDiffMaxSteps * kDiffBlock;
+}
+
 struct kpx_diff {
     DiffConst C;
     float4* boxes = nullptr;
@@ -409,7 +432,7 @@ int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out)
         for (int a = 0; a < 3; ++a)
             if (!(p->boxes[6 * b + a] <= p->boxes[6 * b + 3 + a])) return KPX_ERR_ARG;
     // dynamic LDS beyond the default limit (many boxes beside the checkpoints)
-    const size_t lds_max = sizeof(float4) * 2 * kDiffMaxBoxes + sizeof(float) * kMaxBlocks * 12 * kDiffBlock;
+    const size_t lds_max = lds_bytes(kDiffMaxBoxes);
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_diff), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_max) != hipSuccess)
         return KPX_ERR_DEVICE;
@@ -438,11 +461,12 @@ int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out)
     C.n_boxes = p->n_boxes;
     d->stream = (hipStream_t)hip_stream;
     const size_t nb = (size_t)(p->n_boxes > 0 ? p->n_boxes : 1);
-    if (hipMalloc(&d->boxes, sizeof(float4) * 2 * nb) != hipSuccess) {
+    // lo, hi of every box, then centre, half extent of every box
+    if (hipMalloc(&d->boxes, sizeof(float4) * 4 * nb) != hipSuccess) {
         delete d;
         return KPX_ERR_OOM;
     }
-    float4* hb = new (std::nothrow) float4[2 * nb];
+    float4* hb = new (std::nothrow) float4[4 * nb];
     if (!hb) {
         (void)hipFree(d->boxes);
         delete d;
@@ -452,8 +476,15 @@ int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out)
         const float* s = p->boxes + 6 * b;
         hb[2 * b] = make_float4(s[0], s[1], s[2], 0.f);
         hb[2 * b + 1] = make_float4(s[3], s[4], s[5], 0.f);
+        float c[3], h[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = (float)(0.5 * ((double)s[a] + (double)s[3 + a]));
+            h[a] = (float)(0.5 * ((double)s[3 + a] - (double)s[a]));
+        }
+        hb[2 * p->n_boxes + 2 * b] = make_float4(c[0], c[1], c[2], 0.f);
+        hb[2 * p->n_boxes + 2 * b + 1] = make_float4(h[0], h[1], h[2], 0.f);
     }
-    const hipError_t e = p->n_boxes > 0 ? hipMemcpy(d->boxes, hb, sizeof(float4) * 2 * p->n_boxes,
+    const hipError_t e = p->n_boxes > 0 ? hipMemcpy(d->boxes, hb, sizeof(float4) * 4 * p->n_boxes,
                                                     hipMemcpyHostToDevice)
                                         : hipSuccess;
     delete[] hb;
@@ -473,8 +504,8 @@ static int diff_launch(kpx_diff* d, const float* x0, float* u, const int32_t* n,
     if (E == 0) return KPX_OK;
     const long long blocks = (E + kDiffBlock - 1) / kDiffBlock;
     if (blocks > 0x7FFFFFFFll) return KPX_ERR_ARG;
-    const size_t lds = sizeof(float4) * 2 * d->C.n_boxes + sizeof(float) * kMaxBlocks * 12 * kDiffBlock;
-    k_diff<<<(unsigned)blocks, kDiffBlock, lds, d->stream>>>(d->C, d->boxes, x0, u, n, E, loss, grad, polish, lr);
+    k_diff<<<(unsigned)blocks, kDiffBlock, lds_bytes(d->C.n_boxes), d->stream>>>(
+        d->C, d->boxes, x0, u, n, E, loss, grad, polish, lr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         d->err = hipGetErrorString(e);
