@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="quad12",
                     choices=["di6", "quad12", "dubins6", "di6_paper", "quad12_paper", "dubins6_paper",
-                             "batch256"])
+                             "batch256", "diff65536"])
     ap.add_argument("--queries", type=int, default=256, help="queries of the batch256 workload")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch256: skip the sequential per-query comparison")
@@ -109,8 +109,6 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    if a.workload == "batch256":
-        return bench_batch(a)
     K.lib()  # fails loudly when the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -120,6 +118,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.workload == "batch256":
+        return bench_batch(a)
+    if a.workload == "diff65536":
+        return bench_diff(a)
     w = W.make_workload(a.workload, a.seed)
     prob, prm = w.problem, w.params
 
@@ -316,6 +318,143 @@ def bench_batch(a):
         "solved": len(solved), "queries": len(ws),
         "time_to_first_solution_ms_median": round(float(np.median(solved)), 3) if solved else None,
         "solution_cost_median": round(float(np.median(costs)), 4) if costs else None,
+    }
+    print(json.dumps(out))
+
+
+# Algorithmic float32 FLOPs of the differentiable rollout (same counting as
+# above), per RK4 step of one edge:
+#   forward:  the RK4 step (324), the nearest-box scan (19 per box: 6 for q,
+#             2 max for max q, 3 max and 3 FMA for the key, 1 min, 1 compare)
+#             and the penalty at the new state (26: the box's signed distance
+#             with its square root, softplus with one exp and one log);
+#   adjoint:  the three stage states (3 evaluations of f, 126, and 36 FMA),
+#             four vector-Jacobian products of f (120 each: 6 sin/cos, 1 rcp
+#             and about 56 mul/FMA), the stage-adjoint combinations (144) and
+#             the penalty gradient (30), 852 in all; plus one RK4 step of
+#             recomputation for every step that does not start at a checkpoint.
+DIFF_RK4, DIFF_SCAN_PER_BOX, DIFF_PENALTY, DIFF_ADJOINT = 324, 19, 26, 852
+DIFF_CKPT = 8
+
+
+def diff_flops(n, n_boxes, grad):
+    n = np.asarray(n, np.int64)
+    fwd = n * (DIFF_RK4 + DIFF_SCAN_PER_BOX * n_boxes + DIFF_PENALTY)
+    if not grad:
+        return float(fwd.sum())
+    recompute = n - (n + DIFF_CKPT - 1) // DIFF_CKPT
+    return float((fwd + n * DIFF_ADJOINT + recompute * DIFF_RK4).sum())
+
+
+def diff_traffic():
+    """HBM bytes per loss-and-gradient launch from the committed counter
+    summary, or None when absent or taken on other kernel sources."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "diff_quad12_65536_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    with open(os.path.join(ROOT, "paper_2602_02846_amd/csrc/kpx_diff.hip"), "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            k, sep, v = line.partition(":")
+            if sep:
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != digest:
+        return None
+    try:
+        return int(fields["diff_hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bench_diff(a):
+    """Loss and control gradient of 65,536 quadrotor edges (20..40 RK4 steps,
+    4 control segments, 64-box wall scene) per step, then 3 projected-gradient
+    polish steps on the same edges; HIP events on the launching stream."""
+    import torch
+
+    import paper_2602_02846_amd as K
+    import workloads as W
+    from paper_2602_02846_amd.diff import Rollout
+
+    K.lib()
+    torch.cuda.set_device(0)
+    b = W.diff_workload(a.seed, n_edges=65536)
+    E = b.n.size
+    R = Rollout(b.problem, b.dt)
+    x0 = torch.from_numpy(np.ascontiguousarray(b.x0.T)).cuda()
+    u = torch.from_numpy(np.ascontiguousarray(b.u.T)).cuda()
+    n = torch.from_numpy(np.ascontiguousarray(b.n)).cuda()
+    loss = torch.empty(E, dtype=torch.float32, device="cuda")
+    grad = torch.empty((16, E), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(k):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3 / max(k, 1)
+
+    step = lambda: R.loss_grad_into(x0, u, n, loss, grad)  # noqa: E731
+    for _ in range(a.warmup):
+        step()
+    elapsed, kern_s = timed(step, a.steps)
+    loss_only = lambda: R.loss_grad_into(x0, u, n, loss, None)  # noqa: E731
+    loss_only()
+    _, kern_loss_s = timed(loss_only, max(1, a.steps // 2))
+    _, bad0 = R.polish(x0, u.clone(), n, steps=0, validity=True)
+    up = u.clone()
+    res = {}
+    _, polish_s = timed(lambda: res.setdefault("r", R.polish(x0, up, n, steps=3, lr=0.01, loss=loss,
+                                                             validity=True)), 1)
+    valid_before, valid_after = int((bad0 == 0).sum()), int((res["r"][1] == 0).sum())
+
+    nb = int(np.asarray(b.problem.boxes).reshape(-1, 6).shape[0])
+    fl = diff_flops(b.n, nb, grad=True)
+    achieved = fl / kern_s / 1e12
+    value = E * a.steps / elapsed if elapsed > 0 else 0.0
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+
+        D = O.DiffProblem(b.problem, b.dt)
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < a.cpu_seconds and done < E:
+            O.diff_loss(D, b.x0[done], b.u[done], int(b.n[done]))
+            O.diff_grad(D, b.x0[done], b.u[done], int(b.n[done]))
+            done += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": round(done / el, 1) if el > 0 else None, "unit": "edges/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"the first {done} edges of the same batch, loss and complex-step gradient "
+                         f"(16 complex rollouts per edge), float64, one thread, {el:.1f} s"}
+    R.close()
+    out = {
+        "metric": "edge loss+gradient evaluations/s", "value": round(value, 1), "unit": "edges/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(elapsed * 1e3 / max(a.steps, 1), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"diff65536: {E} quadrotor edges, {int(b.n.min())}..{int(b.n.max())} RK4 steps "
+                               f"of dt {b.dt}, 4 control segments, {nb} boxes; loss and gradient per step",
+                   "seed": a.seed, "edges_per_step": E, "rk4_steps_per_step": int(b.n.sum())},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": diff_traffic(), "flops_per_launch": fl},
+        "kernel_ms": {"loss_grad": round(kern_s * 1e3, 4), "loss": round(kern_loss_s * 1e3, 4),
+                      "polish3": round(polish_s * 1e3, 4)},
+        "polish": {"steps": 3, "lr": 0.01, "valid_edges_before": valid_before,
+                   "valid_edges_after": valid_after},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 

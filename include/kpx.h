@@ -323,7 +323,7 @@ const char* kpx_batch_last_error(const kpx_batch* b);
 
 /* ------------------------------------------------------ differentiable edges
  * An extension past the paper, which cites gradient-based trajectory
- * optimization only as related work (Sec. II): loss and control gradient of
+ * optimization only as related work (Sec. I-A): loss and control gradient of
  * quadrotor edges (the Sec. V model and the planner's RK4 integrator), for
  * local refinement of edges.  A batch holds E independent edges, each n RK4 steps of
  * size dt (4 <= n <= 40) from x0 under 4 piecewise-constant control segments,
@@ -347,6 +347,8 @@ typedef struct kpx_diff_problem {
     float goal[3];
     float w_ctrl, w_obst, k_obst, d_safe, w_goal;
     float u_lo[4], u_hi[4];   /* control box for kpx_diff_polish's projection */
+    float x_lo[12], x_hi[12]; /* state bounds (may be +-INFINITY), for validity */
+    float ws_lo[3], ws_hi[3]; /* workspace, for validity */
 } kpx_diff_problem;
 
 typedef struct kpx_diff kpx_diff;
@@ -367,10 +369,14 @@ int kpx_diff_loss_grad(kpx_diff* d, const float* x0, const float* u, const int32
 
 /* Enqueues `steps` projected gradient steps u <- clamp(u - lr grad, u_lo, u_hi)
  * on every edge, in place on u (device, 16 x E), and writes the loss of the
- * final controls to loss (device, E).  steps = 0 only evaluates the loss.
+ * final controls to loss (device, E).  When first_invalid (device, E) is not
+ * NULL it receives, for the final controls, the first step k in 1..n whose
+ * state x_k leaves the valid set (outside the state bounds or the closed
+ * workspace, or inside a closed box), 0 when all are valid, -1 for an
+ * unsupported n.  steps = 0 only evaluates the loss (and validity).
  * KPX_ERR_ARG for steps < 0, lr < 0 or NaN, or as kpx_diff_loss_grad. */
 int kpx_diff_polish(kpx_diff* d, const float* x0, float* u, const int32_t* n, int64_t E, int32_t steps, float lr,
-                    float* loss);
+                    float* loss, int32_t* first_invalid);
 
 /* Waits for the object's work and releases it.  NULL is ok. */
 int kpx_diff_destroy(kpx_diff* d);

@@ -34,6 +34,7 @@ struct DiffConst {
     float goal[3];
     float w_ctrl, w_obst, k_obst, d_safe, w_goal;
     float u_lo[4], u_hi[4];
+    float x_lo[12], x_hi[12], ws_lo[3], ws_hi[3];
     int n_boxes;
 };
 
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
                                                      const float* __restrict__ x0g, float* __restrict__ ug,
                                                      const int* __restrict__ ng, long long E,
                                                      float* __restrict__ loss, float* __restrict__ grad,
-                                                     int polish, float lr)
+                                                     int polish, float lr, int* __restrict__ fbad)
 {
     extern __shared__ float4 lds[];
     float4* sbox = lds;
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
     if (e >= E) return;
     float* ck = sck + threadIdx.x;  // component i of slot b at ck[(b * 12 + i) * kDiffBlock]
     unsigned short* nbox = sidx + threadIdx.x;  // nearest box of x_{k+1} at nbox[k * kDiffBlock]
-    const int nb = C.w_obst != 0.f ? C.n_boxes : 0;
+    const int nb = C.w_obst != 0.f || fbad ? C.n_boxes : 0;
     const int n = ng[e];
     float u[16];
 #pragma unroll
@@ -302,12 +303,14 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
         if (grad)
 #pragma unroll
             for (int i = 0; i < 16; ++i) grad[(long long)i * E + e] = 0.f;
+        if (fbad) fbad[e] = -1;
         return;
     }
     const int b1 = n / 4, b2 = n / 2, b3 = (3 * n) / 4;  // segment boundaries
     const int n_blk = (n + kCkpt - 1) / kCkpt;
     const int rounds = polish > 0 ? polish + 1 : 1;
     float L = 0.f;
+    int first_bad = 0;
     for (int round = 0; round < rounds; ++round) {
         const bool need_grad = grad != nullptr || round + 1 < rounds;
         // forward, keeping x_k at slot k / 8 for k = 0, 8, ..
@@ -325,6 +328,19 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
             const int bi = nearest_box(sbox + 2 * C.n_boxes, nb, x);
             if (need_grad) nbox[k * kDiffBlock] = (unsigned short)bi;
             pen += penalty(C, sbox, bi, x, nullptr);
+            if (fbad && round + 1 == rounds && first_bad == 0) {  // validity of x_{k+1}
+                bool ok = true;
+#pragma unroll
+                for (int i = 0; i < 12; ++i) ok = ok && x[i] >= C.x_lo[i] && x[i] <= C.x_hi[i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ok = ok && x[a] >= C.ws_lo[a] && x[a] <= C.ws_hi[a];
+                if (bi >= 0) {  // a box holding x holds it nearest
+                    const float4 lo = sbox[2 * bi], hi = sbox[2 * bi + 1];
+                    ok = ok && !(x[0] >= lo.x && x[0] <= hi.x && x[1] >= lo.y && x[1] <= hi.y &&
+                                 x[2] >= lo.z && x[2] <= hi.z);
+                }
+                if (!ok) first_bad = k + 1;
+            }
         }
         float u2 = 0.f;
 #pragma unroll
@@ -396,6 +412,7 @@ __global__ __launch_bounds__(kDiffBlock) void k_diff(DiffConst C, const float4* 
         }
     }
     loss[e] = L;
+    if (fbad) fbad[e] = first_bad;
     if (polish > 0)
 #pragma unroll
         for (int i = 0; i < 16; ++i) ug[(long long)i * E + e] = u[i];
@@ -458,6 +475,14 @@ int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out)
         C.u_lo[c] = p->u_lo[c];
         C.u_hi[c] = p->u_hi[c];
     }
+    for (int i = 0; i < 12; ++i) {
+        C.x_lo[i] = p->x_lo[i];
+        C.x_hi[i] = p->x_hi[i];
+    }
+    for (int a = 0; a < 3; ++a) {
+        C.ws_lo[a] = p->ws_lo[a];
+        C.ws_hi[a] = p->ws_hi[a];
+    }
     C.n_boxes = p->n_boxes;
     d->stream = (hipStream_t)hip_stream;
     const size_t nb = (size_t)(p->n_boxes > 0 ? p->n_boxes : 1);
@@ -498,14 +523,14 @@ int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out)
 }
 
 static int diff_launch(kpx_diff* d, const float* x0, float* u, const int32_t* n, int64_t E, float* loss,
-                       float* grad, int polish, float lr)
+                       float* grad, int polish, float lr, int32_t* first_invalid)
 {
     if (!d || E < 0 || (E > 0 && (!x0 || !u || !n || !loss))) return KPX_ERR_ARG;
     if (E == 0) return KPX_OK;
     const long long blocks = (E + kDiffBlock - 1) / kDiffBlock;
     if (blocks > 0x7FFFFFFFll) return KPX_ERR_ARG;
     k_diff<<<(unsigned)blocks, kDiffBlock, lds_bytes(d->C.n_boxes), d->stream>>>(
-        d->C, d->boxes, x0, u, n, E, loss, grad, polish, lr);
+        d->C, d->boxes, x0, u, n, E, loss, grad, polish, lr, first_invalid);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         d->err = hipGetErrorString(e);
@@ -517,14 +542,14 @@ static int diff_launch(kpx_diff* d, const float* x0, float* u, const int32_t* n,
 int kpx_diff_loss_grad(kpx_diff* d, const float* x0, const float* u, const int32_t* n, int64_t E, float* loss,
                        float* grad)
 {
-    return diff_launch(d, x0, const_cast<float*>(u), n, E, loss, grad, 0, 0.f);
+    return diff_launch(d, x0, const_cast<float*>(u), n, E, loss, grad, 0, 0.f, nullptr);
 }
 
 int kpx_diff_polish(kpx_diff* d, const float* x0, float* u, const int32_t* n, int64_t E, int32_t steps, float lr,
-                    float* loss)
+                    float* loss, int32_t* first_invalid)
 {
     if (steps < 0 || !(lr >= 0.f)) return KPX_ERR_ARG;
-    return diff_launch(d, x0, u, n, E, loss, nullptr, steps, lr);
+    return diff_launch(d, x0, u, n, E, loss, nullptr, steps, lr, first_invalid);
 }
 
 int kpx_diff_destroy(kpx_diff* d)

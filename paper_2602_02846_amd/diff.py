@@ -24,7 +24,9 @@ class DiffProblemC(C.Structure):
                 ("boxes", C.POINTER(C.c_float)), ("n_boxes", C.c_int32),
                 ("goal", C.c_float * 3), ("w_ctrl", C.c_float), ("w_obst", C.c_float),
                 ("k_obst", C.c_float), ("d_safe", C.c_float), ("w_goal", C.c_float),
-                ("u_lo", C.c_float * 4), ("u_hi", C.c_float * 4)]
+                ("u_lo", C.c_float * 4), ("u_hi", C.c_float * 4),
+                ("x_lo", C.c_float * 12), ("x_hi", C.c_float * 12),
+                ("ws_lo", C.c_float * 3), ("ws_hi", C.c_float * 3)]
 
 
 _bound = False
@@ -37,7 +39,7 @@ def _lib():
         i32, i64 = C.c_int32, C.c_int64
         L.kpx_diff_create.argtypes = [C.POINTER(DiffProblemC), _vp, C.POINTER(_vp)]
         L.kpx_diff_loss_grad.argtypes = [_vp, _vp, _vp, _vp, i64, _vp, _vp]
-        L.kpx_diff_polish.argtypes = [_vp, _vp, _vp, _vp, i64, i32, C.c_float, _vp]
+        L.kpx_diff_polish.argtypes = [_vp, _vp, _vp, _vp, i64, i32, C.c_float, _vp, _vp]
         L.kpx_diff_destroy.argtypes = [_vp]
         L.kpx_diff_last_error.argtypes = [_vp]
         L.kpx_diff_last_error.restype = C.c_char_p
@@ -61,6 +63,10 @@ def diff_problem_struct(problem, dt, goal=None, w_ctrl=0.1, w_obst=1.0, k_obst=5
     s.w_ctrl, s.w_obst, s.k_obst, s.d_safe, s.w_goal = w_ctrl, w_obst, k_obst, d_safe, w_goal
     s.u_lo = _f(problem.u_lo, 4)
     s.u_hi = _f(problem.u_hi, 4)
+    s.x_lo = _f(problem.x_lo, 12)
+    s.x_hi = _f(problem.x_hi, 12)
+    s.ws_lo = _f(problem.ws_lo, 3)
+    s.ws_hi = _f(problem.ws_hi, 3)
     return s, boxes
 
 
@@ -125,16 +131,19 @@ class Rollout:
                                               loss.data_ptr(),
                                               None if grad is None else grad.data_ptr()))
 
-    def polish(self, x0, u, n, steps: int = 3, lr: float = 1e-3, loss=None):
-        """Projected gradient steps on u in place; returns the final losses."""
+    def polish(self, x0, u, n, steps: int = 3, lr: float = 1e-3, loss=None, validity: bool = False):
+        """Projected gradient steps on u in place; returns the final losses, and
+        with validity=True also the first invalid step of every edge (int32)."""
         import torch
 
         E = self._args(x0, u, n)
         if loss is None:
             loss = torch.empty(E, dtype=torch.float32, device=self.device)
+        bad = torch.empty(E, dtype=torch.int32, device=self.device) if validity else None
         self._check(_lib().kpx_diff_polish(self.h, x0.data_ptr(), u.data_ptr(), n.data_ptr(), E,
-                                           int(steps), float(lr), loss.data_ptr()))
-        return loss
+                                           int(steps), float(lr), loss.data_ptr(),
+                                           None if bad is None else bad.data_ptr()))
+        return (loss, bad) if validity else loss
 
     def close(self):
         if getattr(self, "h", None):

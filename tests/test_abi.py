@@ -128,6 +128,6 @@ def test_diff_null_arguments(kpx):
     L = diff._lib()
     assert L.kpx_diff_create(None, None, None) == -1
     assert L.kpx_diff_loss_grad(None, None, None, None, 1, None, None) == -1
-    assert L.kpx_diff_polish(None, None, None, None, 1, 1, 0.1, None) == -1
+    assert L.kpx_diff_polish(None, None, None, None, 1, 1, 0.1, None, None) == -1
     assert L.kpx_diff_destroy(None) == 0
     assert L.kpx_diff_last_error(None) == b""

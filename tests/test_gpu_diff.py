@@ -213,3 +213,64 @@ def test_polish_matches_oracle_steps(scene, ora):
         assert abs(after[e] - ref) <= 1e-5 * max(1.0, abs(ref))
     assert (after <= before + 1e-5 * np.maximum(1.0, np.abs(before))).all()
     assert after.mean() < before.mean()
+
+
+def _margin(ora, b, x):
+    """Distance of state x to the nearest boundary of the valid set (state
+    bounds, workspace, box faces): where it is below float32 resolution the
+    float32 and float64 rollouts may judge the step differently."""
+    p = b.problem
+    lo, hi = np.asarray(p.x_lo[:12], np.float64), np.asarray(p.x_hi[:12], np.float64)
+    d = [np.min(np.abs(x - lo)), np.min(np.abs(x - hi)),
+         np.min(np.abs(x[:3] - np.asarray(p.ws_lo[:3], np.float64))),
+         np.min(np.abs(x[:3] - np.asarray(p.ws_hi[:3], np.float64)))]
+    d += [abs(ora.box_sd(bx, x[:3])) for bx in np.asarray(p.boxes).reshape(-1, 6)]
+    return min(d)
+
+
+def _check_validity(ora, D, b, u, n, bad, idx):
+    exact = 0
+    for e in idx:
+        ref = ora.diff_first_invalid(D, b.x0[e], u[e], int(n[e]))
+        if bad[e] == ref:
+            exact += 1
+            continue
+        _, st = ora.diff_loss(D, b.x0[e], u[e], int(n[e]), states=True)
+        k = min(k for k in (int(bad[e]), ref) if k > 0)
+        assert _margin(ora, b, st[k]) < 1e-5, (e, int(bad[e]), ref)
+    return exact
+
+
+def test_validity_matches_oracle(scene, ora):
+    import torch
+
+    b, R, D = scene
+    x0, u, n = _dev(b.x0, b.u, b.n)
+    loss, bad = R.polish(x0, u, n, steps=0, validity=True)
+    ref_loss, _ = R.loss_grad(x0, u, n, want_grad=False)
+    torch.cuda.synchronize()
+    assert torch.equal(loss, ref_loss)
+    bad = bad.cpu().numpy()
+    assert ((bad >= 0) & (bad <= b.n)).all()
+    assert 0 < (bad > 0).sum() < len(bad)  # both kinds occur in the workload
+    exact = _check_validity(ora, D, b, b.u, b.n, bad, range(E_PARITY))
+    assert exact >= E_PARITY - 2
+
+
+def test_polished_edges_are_rejudged_by_the_oracle(scene, ora):
+    import torch
+
+    b, R, D = scene
+    m = 400
+    x0, u, n = _dev(b.x0[:m], b.u[:m], b.n[:m])
+    nn = b.n[:m].copy()
+    nn[5] = 2  # unsupported: -1
+    n = torch.from_numpy(nn).cuda()
+    loss, bad = R.polish(x0, u, n, steps=3, lr=LR, validity=True)
+    torch.cuda.synchronize()
+    bad, up = bad.cpu().numpy(), u.cpu().numpy().T
+    assert bad[5] == -1 and np.isnan(loss[5].item())
+    keep = [e for e in range(m) if e != 5]
+    exact = _check_validity(ora, D, b, up, nn, bad, keep)
+    assert exact >= len(keep) - 2
+    print(f"valid after 3 polish steps: {(bad[keep] == 0).sum()} of {len(keep)}")
