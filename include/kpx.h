@@ -209,7 +209,7 @@ int kpx_workspace_bytes(const kpx_problem* prob, const kpx_params* prm, size_t* 
  * survivors one iteration can add), copies them, allocates the tree, region
  * table and per-iteration buffers on the device (or carves them from
  * `workspace`, a device buffer of `workspace_bytes` >= kpx_workspace_bytes,
- * which the caller keeps alive until kpx_destroy), and runs Alg. 1 lines 1-5:
+ * which the caller keeps alive until kpx_destroy), and runs the initialisation of Alg. 1:
  * root = x_init (active), every region at infinite cost except the root's,
  * which holds (0, root), no solution.  hip_stream: a hipStream_t or NULL.
  * Errors: KPX_ERR_ARG, KPX_ERR_INVALID_START (checked on the host before any
@@ -231,7 +231,7 @@ int kpx_sync(kpx_handle* h);
 /* Waits and copies the device counters to *out (host). */
 int kpx_counters_read(kpx_handle* h, kpx_counters* out);
 
-/* Waits, then returns the best goal node's trajectory (Alg. 4 lines 5-7):
+/* Waits, then returns the best goal node's trajectory (Alg. 4):
  * states (n_edges + 1) x KPX_MAX_STATE row-major starting at x_init,
  * controls n_edges x KPX_MAX_CONTROL, steps n_edges (host buffers, may be NULL).
  * If capacity_edges < n_edges only *info is filled and KPX_ERR_BUFFER is returned. */

@@ -74,7 +74,7 @@ void ora_philox_many(const uint32_t* counter_key, int64_t n, uint32_t* out)
         ora_philox4x32_10(&counter_key[6 * i], &counter_key[6 * i + 4], &out[4 * i]);
 }
 
-/* Random control and duration of one expansion (Alg. 2 line 3; Alg. 6 line 4).
+/* Random control and duration of one expansion (Alg. 2; Alg. 6).
  * Reading: counter = (iteration, slot, query, block), key = (seed low, seed
  * high).  Block b yields words 4b..4b+3.  Control i takes word i; the step
  * count takes word m (m = control dimension).  A word w maps to the uniform
@@ -170,7 +170,7 @@ void ora_deriv(const ora_problem* P, const double* z, const double* u, double* z
 }
 
 /* Classical four-stage Runge-Kutta step of size h on z = (x, length).
- * Reading: PropagateODE (Alg. 2 line 4) is not specified; RK4 with a fixed
+ * Reading: PropagateODE (Alg. 2) is not specified; RK4 with a fixed
  * step dt is used. */
 void ora_rk4_step(const ora_problem* P, double* z, const double* u, double h)
 {
@@ -254,7 +254,7 @@ int ora_point_status(const ora_problem* P, const double* x, double margin, doubl
     return invalid | (amb << 1);
 }
 
-/* Region of a state (Alg. 2 line 6).  Reading: a uniform grid over the
+/* Region of a state (Alg. 2).  Reading: a uniform grid over the
  * workspace, grid[a] cells per position axis, clamped at the far faces,
  * row-major over (x, y, z); with sign bins, three bits (velocity >= 0) are
  * appended.  A coordinate within band of an interior face is ambiguous; there a
@@ -311,7 +311,7 @@ int64_t ora_cell_of(const ora_problem* P, const double* x, const int64_t* hint, 
     return cell;
 }
 
-/* Goal set (Alg. 4 line 5).  Reading: a closed ball over the position
+/* Goal set (Alg. 4).  Reading: a closed ball over the position
  * coordinates, tested at the end state of each edge. */
 int ora_goal_test(const ora_problem* P, const double* x, double radius, const uint8_t* hint,
                   uint32_t* flags)
@@ -330,7 +330,7 @@ int ora_goal_test(const ora_problem* P, const double* x, double radius, const ui
     return in;
 }
 
-/* One expansion (Alg. 2 lines 4-5): integrate n RK4 steps of size dt from x0
+/* One expansion (Alg. 2): integrate n RK4 steps of size dt from x0
  * with the constant control u, testing validity after every step.
  * Reading: validity is checked at the substep end points x_1..x_n (x_0 is a
  * tree node and already valid) and integration stops at the first invalid
@@ -433,7 +433,7 @@ static int key_less(double c1, int64_t i1, double c2, int64_t i2)
     return i1 < i2;
 }
 
-/* Alg. 1 lines 1-5.  Reading: the root's region holds cost 0 and the root id,
+/* Initialisation of Alg. 1.  Reading: the root's region holds cost 0 and the root id,
  * so that the root counts as its region's best node. */
 int ora_init(const ora_problem* P, ora_tree* T)
 {
@@ -535,7 +535,7 @@ void ora_prune(const ora_problem* P, ora_tree* T)
 {
     for (int64_t i = 0; i < T->n_tree; ++i) {
         const int best = T->tbl_id[T->cell[i]] == i;
-        /* lines 3-7: a dormant region-best node counts up and wakes past I_max */
+        /* Alg. 3: a dormant region-best node counts up and wakes past I_max */
         if (best && T->status[i] == ORA_INACTIVE) {
             T->icount[i] += 1;
             if (T->icount[i] > P->i_max) {
@@ -543,14 +543,14 @@ void ora_prune(const ora_problem* P, ora_tree* T)
                 continue;
             }
         }
-        /* lines 8-9: a woken region-best node is left alone */
+        /* Alg. 3: a woken region-best node is left alone */
         if (T->icount[i] > P->i_max && best) continue;
-        /* lines 10-12: beaten in its region -> terminal */
+        /* Alg. 3: beaten in its region -> terminal */
         if (!best) {
             T->status[i] = ORA_TERMINAL;
             continue;
         }
-        /* lines 13-15: an ancestor beaten in its own region -> inactive */
+        /* Alg. 3: an ancestor beaten in its own region -> inactive */
         for (int64_t p = T->parent[i]; p >= 0; p = T->parent[p]) {
             if (T->tbl_id[T->cell[p]] != p) {
                 T->status[i] = ORA_INACTIVE;
@@ -566,7 +566,7 @@ static int near_tie(double a, double b, double rel)
     return fabs(a - b) <= rel * s;
 }
 
-/* One iteration of Alg. 1 (lines 7-9): Propagate, PruneNodes, UpdateTree.
+/* One iteration of Alg. 1: Propagate, PruneNodes, UpdateTree.
  * Reading: before anything else, if n_tree plus the most survivors one
  * iteration can add exceeds the capacity, nothing is done and ORA_FULL is
  * returned (the paper only notes that overflowing t_e would fault). */
@@ -593,7 +593,7 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
     C->k = K;
     C->substeps_total = 0;
 
-    /* Alg. 2 lines 1-7: each of the K expansions of each selected node */
+    /* Alg. 2: each of the K expansions of each selected node */
     int64_t n_valid = 0;
     for (int64_t s = 0; s < n_slots; ++s) {
         const int64_t par = sel[s / K];
@@ -621,7 +621,7 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
         ++n_valid;
         uint32_t fl = 0;
         C->cell[s] = ora_cell_of(P, e.xn, (H && H->cell) ? &H->cell[s] : NULL, &fl);
-        /* Alg. 2 line 7: additive cost; TIME counts steps, PATH adds length */
+        /* Alg. 2: additive cost; TIME counts steps, PATH adds length */
         const double edge_cost = P->cost == ORA_COST_TIME ? (double)n : e.length;
         C->cost[s] = T->cost[par] + edge_cost;
         C->goal[s] = (uint8_t)ora_goal_test(P, e.xn, (double)P->goal_radius - (double)P->margin,
@@ -629,7 +629,7 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
         C->flags[s] |= fl;
     }
 
-    /* Alg. 2 line 8: region minimum over this iteration's arrivals; the
+    /* Alg. 2: region minimum over this iteration's arrivals; the
      * arrival id of slot s is n_tree + s */
     double* old_cost = (double*)malloc(sizeof(double) * (size_t)T->n_cells);
     int64_t* old_id = (int64_t*)malloc(sizeof(int64_t) * (size_t)T->n_cells);
@@ -706,7 +706,7 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
         T->tbl_id[C->cell[s]] = i;
         C->survivor[s] = 1;
         C->new_index[s] = i;
-        /* Alg. 4 lines 5-7: a goal node that beats the solution replaces it */
+        /* Alg. 4: a goal node that beats the solution replaces it */
         if (C->goal[s] && key_less(C->cost[s], i, T->sol_cost, T->sol_id)) {
             if (T->sol_id < 0) T->first_sol_iter = T->iter;
             T->sol_cost = C->cost[s];

@@ -7,7 +7,7 @@
 //                  with the valid-set test after each, region map, additive
 //                  cost, packed (cost | id) 64-bit atomicMin on the region
 //                  table (Alg. 2, Alg. 6); the lane that takes a region from
-//                  a tree node marks that node terminal (Alg. 3 lines 10-12).
+//                  a tree node marks that node terminal (Alg. 3).
 //   2. prune+flags blocks [0, P): Alg. 3 for each region's owner (the live
 //                  nodes are exactly the region owners, so prune walks the
 //                  region table instead of the whole tree); blocks [P, P+Q):
@@ -132,7 +132,7 @@ __global__ void k_fill_table(unsigned long long* tbl, uint8_t* act, int n, int n
         act[c] = 0;
 }
 
-// Alg. 1 lines 1-5: the root is x_init, active; its region holds (0, root).
+// Initialisation of Alg. 1: the root is x_init, active; its region holds (0, root).
 template <int DYN>
 __global__ void k_init_root(DevProblem P, DevPtrs T, DevState* st, const float* x_init)
 {
@@ -534,7 +534,7 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
                 uint8_t s = T.status[o];
                 const int ic0 = T.icount[o];
                 int4 A = T.anc[2 * o], B = T.anc[2 * o + 1];
-                if (s == kInactive) {  // lines 3-7
+                if (s == kInactive) {  // Alg. 3: a dormant node counts up and wakes past I_max
                     const int ic = ic0 + 1;
                     T.icount[o] = (uint8_t)ic;
                     if (ic > P.i_max) {
@@ -542,7 +542,7 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
                         T.status[o] = kActive;
                     }
                 } else if (s == kActive && ic0 <= P.i_max) {
-                    // lines 13-15: any ancestor beaten in its region (or below
+                    // Alg. 3: any ancestor beaten in its region (or below
                     // one); eight ancestors per step from the stored lists, the
                     // next list fetched together with this step's flags
                     bool beaten = false;
@@ -568,7 +568,7 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
                         T.status[o] = kInactive;
                         T.dead[o] = 1;
                     }
-                }  // lines 8-9: a woken region-best node is left alone
+                }  // Alg. 3: a woken region-best node is left alone
                 a = s == kActive;
             }
         }
@@ -880,7 +880,7 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
         T.dead[i] = 0;
         const unsigned long long nk = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)i;
         T.tbl[c] = nk;
-        if (flag & 2) atomicMin(&st->sol, nk);  // Alg. 4 lines 5-7
+        if (flag & 2) atomicMin(&st->sol, nk);  // Alg. 4: a goal node competes for the solution
     }
 }
 

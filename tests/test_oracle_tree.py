@@ -50,7 +50,7 @@ def test_prune_inactive_counts_then_wakes(ora):
     assert tr.status[2] == I and tr.icount[2] == 2
     tr.prune()
     assert tr.status[2] == A and tr.icount[2] == 3
-    # woken and still best: left alone although its parent stays beaten (lines 8-9)
+    # woken and still best: left alone although its parent stays beaten (Alg. 3)
     tr.prune()
     assert tr.status[2] == A and tr.icount[2] == 3
 
