@@ -281,6 +281,29 @@ int kpx_philox(const uint32_t* counter_key, int64_t n, uint32_t* out);
 /* Releases what the library allocated (not a caller workspace).  NULL is ok. */
 int kpx_destroy(kpx_handle* h);
 
+/* Edge polish of inserted nodes, an extension past the paper (which cites
+ * gradient-based trajectory optimization only as related work, Sec. I-A).
+ * With steps > 0, every iteration ends its insertion by polishing each node
+ * it inserted: the node's control u takes `steps` projected gradient steps
+ *   u <- clamp(u - lr grad L(u, u, u, u), control box)
+ * on the loss of the differentiable edges below (all 4 segments tied to u,
+ * the margin-grown boxes, the goal centre, the given weights).  The polished
+ * edge, integrated and checked as propagate does, replaces the node's edge
+ * when it is valid, ends in the node's region and keeps a goal node in the
+ * goal; a node that enters the goal competes for the solution (Alg. 4).
+ * Regions, costs (the step count) and statuses do not change. */
+typedef struct kpx_polish {
+    int32_t steps;           /* 0 = off (also NULL); at most 16 */
+    float lr;                /* >= 0 */
+    float w_ctrl, w_obst, k_obst, d_safe, w_goal;
+} kpx_polish;
+
+/* Sets edge polish for later iterations.  KPX_ERR_ARG unless the handle is a
+ * KPX_QUAD12 problem with KPX_COST_TIME and steps_max <= 64, or for steps
+ * outside 0..16, lr < 0 or non-finite values; KPX_ERR_DEVICE if the kernel
+ * cannot get its shared memory.  Handles with polish on cannot be batched. */
+int kpx_set_polish(kpx_handle* h, const kpx_polish* p);
+
 /* Static message for a status code. */
 const char* kpx_status_string(int status);
 
@@ -298,7 +321,7 @@ typedef struct kpx_batch kpx_batch;
 /* Groups n host-array handles (not copied; the caller keeps them alive and
  * destroys them after the batch).  They must be distinct, share one stream,
  * have run the same number of iterations modulo 2, have candidate recording
- * off, and have at most 262144 regions each.  KPX_ERR_ARG otherwise;
+ * and edge polish off, and have at most 262144 regions each.  KPX_ERR_ARG otherwise;
  * KPX_ERR_OOM / KPX_ERR_DEVICE on allocation or runtime failure. */
 int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out);
 

@@ -10,6 +10,7 @@
  * is silent are marked "Reading:".
  */
 #include "kpx_oracle.h"
+#include "kpx_oracle_diff.h"
 
 #include <math.h>
 #include <stdlib.h>
@@ -566,6 +567,76 @@ static int near_tie(double a, double b, double rel)
     return fabs(a - b) <= rel * s;
 }
 
+/* Edge polish of one inserted node i (an extension, not in the paper): the
+ * node's control u takes `polish_steps` projected gradient steps
+ *   u <- clamp(u - lr grad L(u, u, u, u), U)
+ * on the tied loss of kpx_oracle_diff.h (complex-step gradient) over the
+ * margin-grown boxes, towards the goal centre.  The polished edge replaces the
+ * node's edge when the planner's own propagation finds it valid, it ends in
+ * the node's region, and a goal node stays in the goal; a node that enters
+ * the goal competes for the solution.  Its cost (TIME: the step count) does
+ * not change.  Where a decision of the polished edge is flagged within band,
+ * the hint (the other side's accept decision) is adopted. */
+static void polish_node(const ora_problem* P, ora_tree* T, int64_t i, int was_goal, const float* grown,
+                        const uint8_t* hint)
+{
+    orad_problem D;
+    memset(&D, 0, sizeof(D));
+    D.mass = P->dyn_params[0];
+    D.jx = P->dyn_params[1];
+    D.jy = P->dyn_params[2];
+    D.jz = P->dyn_params[3];
+    D.grav = P->dyn_params[4];
+    D.dt = P->dt;
+    D.boxes = grown;
+    D.n_boxes = P->n_boxes;
+    for (int a = 0; a < 3; ++a) D.goal[a] = P->goal_center[a];
+    D.w_ctrl = P->polish_w_ctrl;
+    D.w_obst = P->polish_w_obst;
+    D.k_obst = P->polish_k_obst;
+    D.d_safe = P->polish_d_safe;
+    D.w_goal = P->polish_w_goal;
+    const double* x0 = &T->x[T->parent[i] * ORA_MAX_STATE];
+    const int32_t n = T->steps[i];
+    double u[4];
+    for (int c = 0; c < 4; ++c) u[c] = (double)T->u[i * ORA_MAX_CONTROL + c];
+    for (int r = 0; r < P->polish_steps; ++r) {
+        double u16[16], g[4];
+        for (int j = 0; j < 4; ++j)
+            for (int c = 0; c < 4; ++c) u16[4 * j + c] = u[c];
+        orad_grad_tied(&D, x0, u16, n, 1e-20, g);
+        for (int c = 0; c < 4; ++c) {
+            const double v = u[c] - P->polish_lr * g[c];
+            u[c] = v < (double)P->u_lo[c] ? (double)P->u_lo[c] : v > (double)P->u_hi[c] ? (double)P->u_hi[c] : v;
+        }
+    }
+    float uf[ORA_MAX_CONTROL];
+    for (int c = 0; c < 4; ++c) uf[c] = (float)u[c];
+    ora_edge e;
+    ora_propagate_edge(P, x0, uf, n, -1, &e);
+    uint32_t fl = e.flags;
+    double xe[ORA_MAX_STATE + 1];
+    if (e.first_invalid == 0) {
+        memcpy(xe, e.xn, sizeof(double) * ORA_MAX_STATE);
+    } else {  /* the end state all the same, for an adopted decision */
+        double ud[ORA_MAX_CONTROL];
+        for (int c = 0; c < ORA_MAX_CONTROL; ++c) ud[c] = (double)uf[c];
+        ora_integrate(P, x0, ud, n, (double)P->dt, xe);
+    }
+    const int64_t cell = ora_cell_of(P, xe, NULL, &fl);
+    const int goal_now = ora_goal_test(P, xe, (double)P->goal_radius - (double)P->margin, NULL, &fl);
+    int accept = e.first_invalid == 0 && cell == T->cell[i] && (!was_goal || goal_now);
+    if (fl && hint) accept = *hint != 0;
+    if (!accept) return;
+    for (int k = 0; k < ORA_MAX_STATE; ++k) T->x[i * ORA_MAX_STATE + k] = xe[k];
+    for (int c = 0; c < 4; ++c) T->u[i * ORA_MAX_CONTROL + c] = uf[c];
+    if (!was_goal && goal_now && key_less(T->cost[i], i, T->sol_cost, T->sol_id)) {
+        if (T->sol_id < 0) T->first_sol_iter = T->iter;
+        T->sol_cost = T->cost[i];
+        T->sol_id = i;
+    }
+}
+
 /* One iteration of Alg. 1: Propagate, PruneNodes, UpdateTree.
  * Reading: before anything else, if n_tree plus the most survivors one
  * iteration can add exceeds the capacity, nothing is done and ORA_FULL is
@@ -712,6 +783,17 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
             T->sol_cost = C->cost[s];
             T->sol_id = i;
         }
+    }
+    if (P->polish_steps > 0 && P->dynamics == ORA_QUAD12 && P->cost == ORA_COST_TIME) {
+        float* grown = (float*)malloc(sizeof(float) * 6 * (size_t)(P->n_boxes > 0 ? P->n_boxes : 1));
+        for (int32_t b = 0; b < P->n_boxes; ++b)
+            for (int a = 0; a < 3; ++a) {
+                grown[6 * b + a] = P->boxes[6 * b + a] - P->margin;
+                grown[6 * b + 3 + a] = P->boxes[6 * b + 3 + a] + P->margin;
+            }
+        for (int64_t t = 0; t < n_surv; ++t)
+            polish_node(P, T, n_tree + t, C->goal[I[t]], grown, (H && H->polished) ? &H->polished[t] : NULL);
+        free(grown);
     }
     T->n_tree = n_tree + n_surv;
     T->cursor = cursor_next;

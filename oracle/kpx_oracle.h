@@ -70,6 +70,11 @@ typedef struct {
     uint64_t seed;
     uint32_t query_id;
     double band;               /* flag band for decisions (1e-5) */
+    /* edge polish of every inserted node (QUAD12, TIME cost; steps 0 = off):
+     * projected gradient steps on the node's control of the tied loss of
+     * kpx_oracle_diff.h over the margin-grown boxes */
+    int32_t polish_steps;
+    double polish_lr, polish_w_ctrl, polish_w_obst, polish_k_obst, polish_d_safe, polish_w_goal;
 } ora_problem;
 
 typedef struct {
@@ -122,6 +127,7 @@ typedef struct {
     const int64_t* cell;
     const uint8_t* goal;
     const uint8_t* survivor;
+    const uint8_t* polished;   /* per node inserted this iteration, in insertion order */
 } ora_hints;
 
 typedef struct {

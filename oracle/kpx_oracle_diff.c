@@ -142,6 +142,17 @@ void orad_grad(const orad_problem* D, const double* x0, const double* u, int32_t
     }
 }
 
+void orad_grad_tied(const orad_problem* D, const double* x0, const double* u, int32_t n, double h,
+                    double* grad)
+{
+    for (int c = 0; c < 4; ++c) {
+        cplx uc[16];
+        for (int i = 0; i < 16; ++i) uc[i] = u[i];
+        for (int j = 0; j < 4; ++j) uc[4 * j + c] += I * h;
+        grad[c] = cimag(loss_c(D, x0, uc, n, NULL)) / h;
+    }
+}
+
 int32_t orad_first_invalid(const orad_problem* D, const double* x0, const double* u, int32_t n,
                            const double* x_lo, const double* x_hi, const double* ws_lo,
                            const double* ws_hi)

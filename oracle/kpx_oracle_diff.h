@@ -40,6 +40,12 @@ double orad_loss(const orad_problem* D, const double* x0, const double* u, int32
 /* Complex-step gradient of orad_loss with respect to the 16 controls. */
 void orad_grad(const orad_problem* D, const double* x0, const double* u, int32_t n, double h, double* grad);
 
+/* Complex-step gradient of orad_loss with the 4 segments tied to one control
+ * (u has 16 entries, all segments equal): perturbing control c of every
+ * segment at once gives dL/du_c of the tied loss L(u, u, u, u) (4 values). */
+void orad_grad_tied(const orad_problem* D, const double* x0, const double* u, int32_t n, double h,
+                    double* grad);
+
 /* First step (1..n) whose state leaves the valid set: a position inside a
  * closed box or outside the closed workspace, or a state outside the closed
  * bounds; 0 when every state x_1 .. x_n is valid. */

@@ -48,6 +48,9 @@ class ProblemC(C.Structure):
         ("samples_per_node", C.c_int32),
         ("tree_cap", C.c_int64), ("i_max", C.c_int32), ("seed", C.c_uint64),
         ("query_id", C.c_uint32), ("band", C.c_double),
+        ("polish_steps", C.c_int32), ("polish_lr", C.c_double), ("polish_w_ctrl", C.c_double),
+        ("polish_w_obst", C.c_double), ("polish_k_obst", C.c_double), ("polish_d_safe", C.c_double),
+        ("polish_w_goal", C.c_double),
     ]
 
 
@@ -73,7 +76,8 @@ class CandsC(C.Structure):
 
 
 class HintsC(C.Structure):
-    _fields_ = [("first_invalid", _i32p), ("cell", _i64p), ("goal", _u8p), ("survivor", _u8p)]
+    _fields_ = [("first_invalid", _i32p), ("cell", _i64p), ("goal", _u8p), ("survivor", _u8p),
+                ("polished", _u8p)]
 
 
 class EdgeC(C.Structure):
@@ -149,7 +153,7 @@ def _ptr(a: np.ndarray, ct):
 class Problem:
     """Oracle view of a problem + parameters (keeps the box array alive)."""
 
-    def __init__(self, problem, params, band: float = 1e-5):
+    def __init__(self, problem, params, band: float = 1e-5, polish: Optional[dict] = None):
         self.problem, self.params = problem, params
         self.boxes = np.ascontiguousarray(problem.boxes, dtype=np.float32).reshape(-1, 6)
         s = ProblemC()
@@ -173,6 +177,15 @@ class Problem:
         s.seed = params.seed
         s.query_id = params.query_id
         s.band = band
+        if polish:  # float32 values widened, as the device receives them
+            f = lambda v: float(np.float32(v))  # noqa: E731
+            s.polish_steps = int(polish.get("steps", 3))
+            s.polish_lr = f(polish.get("lr", 0.01))
+            s.polish_w_ctrl = f(polish.get("w_ctrl", 0.1))
+            s.polish_w_obst = f(polish.get("w_obst", 1.0))
+            s.polish_k_obst = f(polish.get("k_obst", 50.0))
+            s.polish_d_safe = f(polish.get("d_safe", 0.02))
+            s.polish_w_goal = f(polish.get("w_goal", 1.0))
         self.c = s
         self.d = {"DI6": 6, "QUAD12": 12, "DUBINS6": 6}[problem.dynamics]
         self.m = {"DI6": 3, "QUAD12": 4, "DUBINS6": 3}[problem.dynamics]
@@ -369,7 +382,8 @@ class Tree:
         if hints is not None:
             hc = HintsC()
             for name, dt, ct in (("first_invalid", np.int32, _i32p), ("cell", np.int64, _i64p),
-                                 ("goal", np.uint8, _u8p), ("survivor", np.uint8, _u8p)):
+                                 ("goal", np.uint8, _u8p), ("survivor", np.uint8, _u8p),
+                                 ("polished", np.uint8, _u8p)):
                 if hints.get(name) is not None:
                     a = np.ascontiguousarray(hints[name], dtype=dt)
                     keep.append(a)
@@ -472,6 +486,8 @@ def _diff_lib():
         L.orad_loss.restype = C.c_double
         L.orad_grad.argtypes = [pp, _f64p, _f64p, C.c_int32, C.c_double, _f64p]
         L.orad_grad.restype = None
+        L.orad_grad_tied.argtypes = [pp, _f64p, _f64p, C.c_int32, C.c_double, _f64p]
+        L.orad_grad_tied.restype = None
         L.orad_first_invalid.argtypes = [pp, _f64p, _f64p, C.c_int32, _f64p, _f64p, _f64p, _f64p]
         L.orad_first_invalid.restype = C.c_int32
         _dlib = L
@@ -525,6 +541,14 @@ def diff_grad(D, x0, u, n, h=1e-20):
     uu = np.ascontiguousarray(u, dtype=np.float64).reshape(16)
     g = np.zeros(16, np.float64)
     _diff_lib().orad_grad(D.ref, _ptr(x, _f64p), _ptr(uu, _f64p), int(n), float(h), _ptr(g, _f64p))
+    return g
+
+
+def diff_grad_tied(D, x0, u, n, h=1e-20):
+    x = np.ascontiguousarray(x0, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64).reshape(16)
+    g = np.zeros(4, np.float64)
+    _diff_lib().orad_grad_tied(D.ref, _ptr(x, _f64p), _ptr(uu, _f64p), int(n), float(h), _ptr(g, _f64p))
     return g
 
 

@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "kpx.hip")
 SRC_DIFF = os.path.join(HERE, "csrc", "kpx_diff.hip")
 DEPS = [SRC, SRC_DIFF, os.path.join(HERE, "csrc", "kpx_device.hpp"),
+        os.path.join(HERE, "csrc", "kpx_diff_device.hpp"),
         os.path.join(os.path.dirname(HERE), "include", "kpx.h")]
 LIB = os.path.join(HERE, "libkpx.so")
 

@@ -21,6 +21,7 @@
 //                  in region order from a rotating cursor, at most n_select).
 #include "../../include/kpx.h"
 #include "kpx_device.hpp"
+#include "kpx_diff_device.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -890,6 +891,99 @@ __global__ __launch_bounds__(kBlock) void k_insert(DevProblem P, DevPtrs T, DevS
     insert_body<DYN>(P, T, st, blockIdx.x);
 }
 
+// Edge polish of the nodes this iteration inserted (QUAD12, TIME cost), an
+// extension past the paper: each node's control takes `steps` projected
+// gradient steps u <- clamp(u - lr grad L(u, u, u, u), U) on the tied loss of
+// kpx_diff_device.hpp (grown boxes, goal centre).  The polished edge is then
+// integrated as propagate integrates an edge (integration units, closed state
+// bounds and boxes after every step) and replaces the node's edge when it is
+// valid, ends in the node's region and keeps a goal node in the goal; a node
+// that enters the goal competes for the solution.  Region and cost (the step
+// count) are unchanged, so no region minimum or status moves.  One thread per
+// new node; dynamic LDS: boxes as lo, hi and as centre, half extent, then the
+// adjoint's checkpoints and nearest-box records of every thread.
+constexpr int kPolishBlock = 64;
+constexpr int kPolishCkpt = 8;  // checkpoint blocks: edges of at most 64 steps
+
+size_t polish_lds_bytes(int n_boxes)
+{
+    return sizeof(float4) * 4 * (size_t)n_boxes + sizeof(float) * kPolishCkpt * 12 * kPolishBlock +
+           sizeof(unsigned short) * kPolishCkpt * kpxd::kCkpt * kPolishBlock;
+}
+
+__global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T, DevState* st, kpxd::DiffConst C,
+                                                         int steps, float lr)
+{
+    extern __shared__ float4 plds[];
+    const int nb = P.n_boxes;
+    float4* sbox = plds;
+    float4* sce = plds + 2 * nb;
+    float* sck = reinterpret_cast<float*>(plds + 4 * nb);
+    unsigned short* snb = reinterpret_cast<unsigned short*>(sck + kPolishCkpt * 12 * kPolishBlock);
+    for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) sbox[i] = T.boxes[i];
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const float4 lo = sbox[2 * b], hi = sbox[2 * b + 1];
+        sce[2 * b] = make_float4(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z), 0.f);
+        sce[2 * b + 1] = make_float4(0.5f * (hi.x - lo.x), 0.5f * (hi.y - lo.y), 0.5f * (hi.z - lo.z), 0.f);
+    }
+    __syncthreads();
+    const int K = P.K > 0 ? P.K : st->k;
+    if (st->full || st->n_sel * K == 0) return;  // insert wrote no survivor count
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= st->n_surv) return;
+    const long long i = st->n_tree + t;
+    const int p = T.parent[i];
+    const int n = T.steps[i];
+    float x0[12], u[4], xo[3];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) x0[q] = T.x[(long long)q * P.cap + p];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = T.u[(long long)q * P.cap + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xo[a] = T.x[(long long)a * P.cap + i];
+    const bool was_goal = in_goal(P, xo);
+    const int nb_pen = C.w_obst != 0.f ? nb : 0;
+    for (int r = 0; r < steps; ++r) {
+        float uu[16], gu[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) uu[q] = u[q & 3];
+        int unused = 0;
+        kpxd::edge_pass(C, sbox, sce, nb_pen, x0, uu, n, sck + threadIdx.x, snb + threadIdx.x, kPolishBlock,
+                        true, gu, false, unused);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float g = (gu[c] + gu[4 + c]) + (gu[8 + c] + gu[12 + c]);
+            u[c] = fminf(fmaxf(u[c] - lr * g, C.u_lo[c]), C.u_hi[c]);
+        }
+    }
+    // the polished edge as propagate integrates and checks an edge
+    const Hot<kQUAD12> H = make_hot<kQUAD12>(P);
+    float x[12], ur[4], len = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) x[c] = x0[c] * (rev_state(kQUAD12, c) ? kInv2Pi : 1.f);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ur[c] = u[c] * (rev_control(kQUAD12, c) ? kInv2Pi : 1.f);
+    bool ok = true;
+    for (int k = 0; k < n && ok; ++k) {
+        rk4<kQUAD12, kTIME>(H, x, ur, len);
+        ok = in_bounds<kQUAD12>(H, x, P.os_lo, P.os_hi);
+        for (int b = 0; b < nb; ++b) ok = ok && !in_box(sbox + 2 * b, x[0], x[1], x[2]);
+    }
+    if (!ok) return;
+    float xe[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xe[c] = x[c] * (rev_state(kQUAD12, c) ? k2Pi : 1.f);
+    const bool goal_now = in_goal(P, xe);
+    if (cell_of(P, xe, xe + 6) != T.cell[i] || (was_goal && !goal_now)) return;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) T.x[(long long)q * P.cap + i] = xe[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) T.u[(long long)q * P.cap + i] = u[q];
+    if (goal_now && !was_goal)
+        atomicMin(&st->sol, ((unsigned long long)T.cost[i] << 32) | (unsigned long long)(uint32_t)i);
+}
+
 // Closes the iteration and selects the next iteration's nodes in one block
 // (regions in more blocks than the many-block kernel below handles).
 __global__ __launch_bounds__(kSelectThreads) void k_finalize_select_one(DevProblem P, DevPtrs T, const DevState* st,
@@ -1556,6 +1650,9 @@ struct kpx_handle {
     int full_cached = 0;
     int n_prune_blocks = 0;
     int cur = 0;                              // which device state is current
+    int polish_steps = 0;                     // edge polish of inserted nodes (0: off)
+    float polish_lr = 0.f;
+    kpxd::DiffConst polish_c{};
     std::string err;
 };
 
@@ -1980,6 +2077,10 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
              })) != KPX_OK)
             return rc;
         if ((rc = timed_launch(h, 2, [&] { insert(h, T); })) != KPX_OK) return rc;
+        if (h->polish_steps > 0)
+            k_polish<<<(h->P.surv_max + kPolishBlock - 1) / kPolishBlock, kPolishBlock,
+                       polish_lds_bytes(h->P.n_boxes), h->stream>>>(h->P, T, cur_state(h), h->polish_c,
+                                                                     h->polish_steps, h->polish_lr);
         if ((rc = timed_launch(h, 3, [&] {
                  if (h->n_prune_blocks <= kSelBlocksMax)
                      k_finalize_select<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
@@ -2179,6 +2280,53 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* v, int64_t* n_slots)
     return KPX_OK;
 }
 
+int kpx_set_polish(kpx_handle* h, const kpx_polish* p)
+{
+    if (!h) return KPX_ERR_ARG;
+    if (!p || p->steps == 0) {
+        h->polish_steps = 0;
+        return KPX_OK;
+    }
+    if (p->steps < 0 || p->steps > 16 || !(p->lr >= 0.f) || !std::isfinite(p->lr))
+        return fail(h, KPX_ERR_ARG, "polish: steps in 0..16 and a finite lr >= 0");
+    const float w[5] = {p->w_ctrl, p->w_obst, p->k_obst, p->d_safe, p->w_goal};
+    for (float v : w)
+        if (!std::isfinite(v)) return fail(h, KPX_ERR_ARG, "polish: finite weights");
+    if (h->P.dyn != kQUAD12 || h->P.cost != kTIME)
+        return fail(h, KPX_ERR_ARG, "polish: the quadrotor model with the TIME cost only");
+    if (h->prm.steps_max > kPolishCkpt * kpxd::kCkpt)
+        return fail(h, KPX_ERR_ARG, "polish: edges of at most 64 steps");
+    KPX_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_polish),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)polish_lds_bytes(h->P.n_boxes)));
+    kpxd::DiffConst& C = h->polish_c;
+    C = kpxd::DiffConst{};
+    const float* dp = h->prob.dyn_params;
+    C.inv_m = 1.0f / dp[0];
+    C.inv_j[0] = 1.0f / dp[1];
+    C.inv_j[1] = 1.0f / dp[2];
+    C.inv_j[2] = 1.0f / dp[3];
+    C.gyro[0] = dp[3] - dp[2];
+    C.gyro[1] = dp[1] - dp[3];
+    C.gyro[2] = dp[2] - dp[1];
+    C.grav = dp[4];
+    C.dt = h->prm.dt;
+    for (int a = 0; a < 3; ++a) C.goal[a] = h->prob.goal_center[a];
+    C.w_ctrl = p->w_ctrl;
+    C.w_obst = p->w_obst;
+    C.k_obst = p->k_obst;
+    C.d_safe = p->d_safe;
+    C.w_goal = p->w_goal;
+    for (int c = 0; c < 4; ++c) {
+        C.u_lo[c] = h->prob.u_lo[c];
+        C.u_hi[c] = h->prob.u_hi[c];
+    }
+    C.n_boxes = h->P.n_boxes;
+    h->polish_steps = p->steps;
+    h->polish_lr = p->lr;
+    return KPX_OK;
+}
+
 int kpx_set_timing(kpx_handle* h, int32_t kernel_mask)
 {
     if (!h || kernel_mask < 0 || kernel_mask > 15) return KPX_ERR_ARG;
@@ -2307,7 +2455,7 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
     for (int q = 0; q < n; ++q) {
         const kpx_handle* h = handles[q];
         if (!h || h->stream != handles[0]->stream || h->cur != handles[0]->cur || h->dump_on ||
-            h->n_prune_blocks > kSelBlocksMax)
+            h->n_prune_blocks > kSelBlocksMax || h->polish_steps > 0)
             return KPX_ERR_ARG;
         for (int r = 0; r < q; ++r)
             if (handles[r] == h) return KPX_ERR_ARG;
@@ -2412,7 +2560,8 @@ int kpx_batch_iterate(kpx_batch* b, int32_t n_iters)
 {
     if (!b || n_iters < 0) return KPX_ERR_ARG;
     for (kpx_handle* h : b->hs)
-        if (h->cur != b->cur || h->dump_on) return bfail(b, KPX_ERR_STATE, "a handle left the batch's step");
+        if (h->cur != b->cur || h->dump_on || h->polish_steps > 0)
+            return bfail(b, KPX_ERR_STATE, "a handle left the batch's step or has edge polish on");
     if (n_iters == 0) return KPX_OK;
     // order the batch stream after the work already on the handles' stream
     if (hipEventRecord(b->ev_in, b->user) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess)

@@ -101,6 +101,11 @@ STATS_DTYPE = np.dtype([
     ("substeps", np.int64), ("solution_key", np.uint64), ("t_begin", np.uint64),
     ("t_end", np.uint64)])
 
+class PolishC(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("lr", C.c_float), ("w_ctrl", C.c_float), ("w_obst", C.c_float),
+                ("k_obst", C.c_float), ("d_safe", C.c_float), ("w_goal", C.c_float)]
+
+
 _lib = None
 
 
@@ -124,6 +129,7 @@ def lib():
         L.kpx_set_dump.argtypes = [_vp, i32]
         L.kpx_read_dump.argtypes = [_vp, C.POINTER(DumpViewC), C.POINTER(i64)]
         L.kpx_set_timing.argtypes = [_vp, i32]
+        L.kpx_set_polish.argtypes = [_vp, C.POINTER(PolishC)]
         L.kpx_read_timing.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(i64)]
         L.kpx_stats_capacity.argtypes = [_vp, C.POINTER(i64)]
         L.kpx_read_stats.argtypes = [_vp, i64, i64, C.POINTER(IterStatsC)]
@@ -145,7 +151,7 @@ def lib():
                      "kpx_read_dump", "kpx_set_timing", "kpx_read_timing", "kpx_stats_capacity",
                      "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy",
                      "kpx_batch_create", "kpx_batch_set_graph", "kpx_batch_iterate",
-                     "kpx_batch_destroy"):
+                     "kpx_batch_destroy", "kpx_set_polish"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -362,6 +368,12 @@ class Planner:
         out["control"] = a["control"][: self.m, :k]
         out["n_slots"] = k
         return out
+
+    def set_polish(self, steps: int = 3, lr: float = 0.01, w_ctrl: float = 0.1, w_obst: float = 1.0,
+                   k_obst: float = 50.0, d_safe: float = 0.02, w_goal: float = 1.0):
+        """Edge polish of the nodes each later iteration inserts (steps = 0: off)."""
+        p = PolishC(int(steps), lr, w_ctrl, w_obst, k_obst, d_safe, w_goal)
+        self._check(lib().kpx_set_polish(self.h, C.byref(p)))
 
     def set_timing(self, enable=True):
         """True times all four kernels, False none; an int is the kernel bit mask."""

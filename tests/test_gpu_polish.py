@@ -1,0 +1,100 @@
+"""Edge polish of inserted nodes (kpx_set_polish) through the C ABI against
+the float64 oracle: lockstep iterations in which both sides polish every
+inserted quadrotor node (the oracle adopting the GPU's accept decision only
+where its own is within the flag band), argument checks, and re-verification
+of a polished plan by the oracle."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+from oracle import parity
+
+pytestmark = pytest.mark.gpu
+
+LOCK = dict(n_select=260, samples=9, tree_cap=1 << 16, grid=(8, 8, 8))
+POLISH = dict(steps=3, lr=0.01)
+
+
+@pytest.fixture(scope="module")
+def kpx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_02846_amd as K
+
+    K.lib()
+    return K
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_lockstep_with_polish(kpx, ora, seed):
+    w = W.make_workload("quad12", seed, **LOCK)
+    P = ora.Problem(w.problem, w.params, polish=POLISH)
+    pl = kpx.Planner(w.problem, w.params)
+    pl.set_polish(**POLISH)
+    rep = parity.lockstep(ora, P, pl, 20)
+    print(seed, rep)
+    assert rep["iterations"] == 20
+    assert rep["polished"] > 0
+    pl.close()
+
+
+def test_polish_arguments(kpx):
+    di = W.make_workload("di6", 0)
+    pd = kpx.Planner(di.problem, di.params)
+    with pytest.raises(kpx.KPXError):
+        pd.set_polish(3)
+    pd.set_polish(0)  # off is always accepted
+    pd.close()
+    qp = W.make_workload("quad12", 0, cost="PATH_LENGTH", **LOCK)
+    pp = kpx.Planner(qp.problem, qp.params)
+    with pytest.raises(kpx.KPXError):
+        pp.set_polish(3)
+    pp.close()
+    q = W.make_workload("quad12", 0, **LOCK)
+    pq = kpx.Planner(q.problem, q.params)
+    for bad in (dict(steps=17), dict(steps=-1), dict(steps=3, lr=-1.0), dict(steps=3, lr=float("nan")),
+                dict(steps=3, w_goal=float("inf"))):
+        with pytest.raises(kpx.KPXError):
+            pq.set_polish(**bad)
+    pq.set_polish(**POLISH)
+    with pytest.raises(kpx.KPXError):
+        kpx.Batch([pq])
+    pq.set_polish(0)
+    b = kpx.Batch([pq])
+    b.close()
+    pq.close()
+
+
+def test_polish_off_is_the_plain_planner(kpx):
+    w = W.make_workload("quad12", 7, **LOCK)
+    a = kpx.Planner(w.problem, w.params)
+    b = kpx.Planner(w.problem, w.params)
+    b.set_polish(**POLISH)
+    b.set_polish(0)
+    a.iterate(10)
+    b.iterate(10)
+    sa, sb = a.snapshot(), b.snapshot()
+    for k in ("state", "control", "parent", "cell", "status"):
+        np.testing.assert_array_equal(sa[k], sb[k])
+    a.close()
+    b.close()
+
+
+def test_polished_plan_reverifies(kpx, ora):
+    w = W.make_workload("quad12", 1)  # full size: 4096 nodes x 32 samples
+    P = ora.Problem(w.problem, w.params)
+    pl = kpx.Planner(w.problem, w.params)
+    pl.set_polish(**POLISH)
+    pl.iterate(200)
+    c = pl.counters()
+    print("polished run:", c["n_tree"], "nodes, first solution at iteration", c["first_solution_iteration"])
+    sol = pl.solution()
+    if not sol["found"]:
+        pytest.skip("no solution within 200 iterations for this seed")
+    rep = ora.verify(P, sol["controls"], sol["steps"], sol["states"], float(sol["cost_field"]))
+    assert rep["ok"], rep
+    pl.close()

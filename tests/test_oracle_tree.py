@@ -100,8 +100,8 @@ def test_select_takes_all_when_few_are_active(ora):
     assert sel.tolist() == [1] and cur == 4
 
 
-def _run_with_invariants(ora, w, iterations):
-    P = ora.Problem(w.problem, w.params)
+def _run_with_invariants(ora, w, iterations, polish=None, on_step=None):
+    P = ora.Problem(w.problem, w.params, polish=polish)
     tr = ora.Tree(P)
     assert tr.init() == ora.OK
     nc = P.n_cells
@@ -182,6 +182,8 @@ def _run_with_invariants(ora, w, iterations):
         if tr.c.sol_id >= 0:
             sols.append(int(tr.c.sol_id))
             assert ora.goal_test(P, tr.x[tr.c.sol_id, : P.d])[0]
+        if on_step:
+            on_step(tr, c, n0, n1)
     return P, tr, sols
 
 
@@ -201,6 +203,50 @@ def test_full_run_invariants_double_integrator(ora, cost):
 def test_full_run_invariants_quadrotor_small(ora):
     w = W.make_workload("quad12", 2, n_select=48, samples=6, grid=(8, 8, 8), tree_cap=1 << 15)
     _run_with_invariants(ora, w, 40)
+
+
+def test_polish_keeps_the_invariants_and_lowers_the_loss(ora):
+    """Edge polish of inserted quadrotor nodes: every invariant above still
+    holds (stored edges re-integrate exactly to the stored states, regions and
+    costs unchanged by construction), some nodes are polished, and each
+    polished control has a lower tied loss than the sampled one."""
+    import copy
+
+    w = W.make_workload("quad12", 2, n_select=48, samples=6, grid=(8, 8, 8), tree_cap=1 << 15)
+    grown = copy.deepcopy(w.problem)
+    b = np.asarray(w.problem.boxes, np.float32).reshape(-1, 6)
+    m = np.float32(w.problem.margin)
+    grown.boxes = np.concatenate([b[:, :3] - m, b[:, 3:] + m], axis=1).astype(np.float32)
+    D = ora.DiffProblem(grown, w.params.dt)
+    seen = {"new": 0, "polished": 0}
+
+    def check(tr, c, n0, n1):
+        for s in np.flatnonzero(c["survivor"]):
+            i = int(c["new_index"][s])
+            seen["new"] += 1
+            u0 = c["u"][s, :4].astype(np.float64)
+            u1 = tr.u[i, :4].astype(np.float64)
+            if np.array_equal(u0, u1):
+                continue
+            seen["polished"] += 1
+            x0 = tr.x[tr.parent[i]]
+            n = int(tr.steps[i])
+            assert ora.diff_loss(D, x0, np.tile(u1, 4), n) < ora.diff_loss(D, x0, np.tile(u0, 4), n)
+            lo, hi = np.asarray(w.problem.u_lo[:4]), np.asarray(w.problem.u_hi[:4])
+            assert np.all(u1 >= lo) and np.all(u1 <= hi)
+
+    _run_with_invariants(ora, w, 25, polish=dict(steps=3, lr=0.01), on_step=check)
+    assert seen["polished"] > seen["new"] // 4, seen
+
+
+def test_polish_tied_gradient_is_the_sum_over_segments(ora):
+    b = W.diff_workload(5, n_edges=3)
+    D = ora.DiffProblem(b.problem, b.dt)
+    for e in range(3):
+        u = np.tile(b.u[e, :4].astype(np.float64), 4)
+        g16 = ora.diff_grad(D, b.x0[e], u, int(b.n[e]))
+        g4 = ora.diff_grad_tied(D, b.x0[e], u, int(b.n[e]))
+        np.testing.assert_allclose(g4, g16.reshape(4, 4).sum(0), rtol=1e-12, atol=1e-12)
 
 
 def test_full_run_invariants_uncapped_form(ora):
