@@ -87,6 +87,8 @@ def parse():
                     help="queries (seeds) for the median time to first solution and cost")
     ap.add_argument("--solution-iters", type=int, default=200,
                     help="iteration budget of each of those queries")
+    ap.add_argument("--polish", type=int, default=0,
+                    help="edge polish steps of every inserted node (quadrotor, TIME cost); 0 = plain")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--time-all", action="store_true",
                     help="HIP events around all four kernels (default: propagate only)")
@@ -126,6 +128,8 @@ def main():
     prob, prm = w.problem, w.params
 
     planner = K.Planner(prob, prm, device="cuda:0")
+    if a.polish:
+        planner.set_polish(a.polish)
     print(f"[bench] {a.workload}: {prm.n_select} x {prm.samples_per_node} slots, "
           f"{prm.n_cells} regions, cap {prm.tree_cap}; warmup {a.warmup}", file=sys.stderr,
           flush=True)
@@ -178,7 +182,8 @@ def main():
         t_first = float((int(all_st["t_end"][first_it]) - int(all_st["t_begin"][0])) / rate * 1e3)
 
     planner.close()
-    sols = solution_medians(K, W, a) if a.solution_seeds > 0 else None
+    sols = solution_medians(K, W, a, a.polish) if a.solution_seeds > 0 else None
+    sols_plain = solution_medians(K, W, a, 0) if a.solution_seeds > 0 and a.polish else None
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -193,7 +198,8 @@ def main():
                    + (f"{prm.n_select}x{prm.samples_per_node} expansions/iteration, "
                       if prm.samples_per_node else
                       f"every active node sharing {prm.n_select} expansion slots per iteration, ")
-                   + f"{prm.n_cells} regions, cap {prm.tree_cap}",
+                   + f"{prm.n_cells} regions, cap {prm.tree_cap}"
+                   + (f", edge polish {a.polish} steps per inserted node" if a.polish else ""),
                    "seed": a.seed, "iterations_timed": done, "edges_timed": edges,
                    "substeps_timed": substeps, "cost": prob.cost},
         "roofline": roofline,
@@ -202,31 +208,56 @@ def main():
         "first_solution_iteration": first_it,
         "solution_cost": sol["cost"] if sol["found"] else None,
         "solutions": sols,
+        "solutions_plain": sols_plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
-def solution_medians(K, W, a):
-    """Median device-timed time to first solution and median solution cost of
-    the plain planner over seeds 0 .. solution_seeds - 1 of the workload, each
-    run for solution_iters iterations (or until its tree is full)."""
+BUDGETS_MS = (5.0, 10.0, 20.0, 40.0)
+
+
+def solution_medians(K, W, a, polish=0):
+    """Median device-timed time to first solution and median solution cost
+    over seeds 0 .. solution_seeds - 1 of the workload, each run for
+    solution_iters iterations (or until its tree is full), with edge polish
+    of `polish` steps (0: the plain planner).  Also the cost of the best plan
+    known at fixed device-time budgets (median over all seeds, an unsolved
+    seed counting as infinite) and the number of seeds solved by then."""
     from paper_2602_02846_amd.autotune import first_solution_ms
 
     times, costs = [], []
+    at_budget = {b: [] for b in BUDGETS_MS}
+    dt = None
     for seed in range(a.solution_seeds):
         w = W.make_workload(a.workload, seed)
+        dt = w.params.dt
         p = K.Planner(w.problem, w.params)
+        if polish:
+            p.set_polish(polish)
         p.iterate(a.solution_iters)
         p.sync()
         t = first_solution_ms(p, a.solution_iters)
         if t is not None:
             times.append(t)
             costs.append(p.solution()["cost"])
+        c = p.counters()
+        st = p.stats(0, min(int(c["iteration"]), 65536))
+        rate = p.clock_rate_khz() * 1e3
+        t_ms = (st["t_end"].astype(np.float64) - float(st["t_begin"][0])) / rate * 1e3 if st.size else np.zeros(0)
+        for b in BUDGETS_MS:
+            keys = st["solution_key"][t_ms <= b]
+            best = int(keys.min()) if keys.size else (1 << 64) - 1
+            at_budget[b].append(np.inf if best == (1 << 64) - 1 else (best >> 32) * dt)
         p.close()
-    return {"queries": a.solution_seeds, "iterations": a.solution_iters, "solved": len(times),
+    return {"queries": a.solution_seeds, "iterations": a.solution_iters, "polish_steps": polish,
+            "solved": len(times),
             "time_to_first_solution_ms_median": round(float(np.median(times)), 3) if times else None,
             "cost_median": round(float(np.median(costs)), 4) if costs else None,
+            "cost_at_budget_median": {f"{b:g}ms": (None if not np.isfinite(np.median(v)) else
+                                                   round(float(np.median(v)), 4))
+                                      for b, v in at_budget.items()},
+            "solved_at_budget": {f"{b:g}ms": int(np.isfinite(v).sum()) for b, v in at_budget.items()},
             "cost_unit": "s" if W.make_workload(a.workload, 0).problem.cost == "TIME" else "length"}
 
 
