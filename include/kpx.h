@@ -108,6 +108,9 @@ typedef struct kpx_problem {
  *   tree_cap                  t_e: capacity of the tree
  *   i_max                     inactivity threshold I_max (0..254)
  *   seed, query_id            Philox4x32-10 key and counter field
+ *   refine_max                the largest total factor per axis by which
+ *                             kpx_refine may later divide the grid cells
+ *                             (0 or 1: never); region arrays are sized for it
  */
 typedef struct kpx_params {
     float dt;
@@ -121,7 +124,7 @@ typedef struct kpx_params {
     int64_t tree_cap;
     uint64_t seed;
     uint32_t query_id;
-    uint32_t reserved;
+    uint32_t refine_max;
 } kpx_params;
 
 typedef struct kpx_handle kpx_handle;
@@ -280,6 +283,20 @@ int kpx_philox(const uint32_t* counter_key, int64_t n, uint32_t* out);
 
 /* Releases what the library allocated (not a caller workspace).  NULL is ok. */
 int kpx_destroy(kpx_handle* h);
+
+/* Adaptive decomposition (the paper's remark on non-uniform and adaptive
+ * decompositions, Sec. IV, which defers their analysis): between iterations,
+ * divides every grid cell of R into factor^3 cells (the grid becomes
+ * grid * factor per axis; velocity-sign classes are kept).  Every node's
+ * region is recomputed from its state; the region table is rebuilt from the
+ * nodes that are not terminal (at most one per old region, so at most one per
+ * new one: each stays its region's best); terminal nodes stay terminal; the
+ * selection cursor moves to the first new cell of its old cell; the tree is
+ * marked full when the larger survivor bound no longer fits; the next
+ * iteration's nodes are selected again over the refined regions.
+ * KPX_ERR_ARG for factor < 2 or a total factor beyond params.refine_max.
+ * Batches made before a refinement refuse to run. */
+int kpx_refine(kpx_handle* h, int32_t factor);
 
 /* Edge polish of inserted nodes, an extension past the paper (which cites
  * gradient-based trajectory optimization only as related work, Sec. I-A).

@@ -808,6 +808,44 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
     return ORA_OK;
 }
 
+/* Adaptive decomposition (the remark on non-uniform and adaptive
+ * decompositions, Sec. IV; their analysis is deferred there).  Reading: the
+ * grid is divided by an integer factor per axis between iterations; live
+ * nodes (not terminal) are unique per old region and so per new region, and
+ * each owns its new region; terminal nodes stay terminal; the cursor moves
+ * to the first new cell of its old one, and the next selection is made over
+ * the refined regions from there. */
+int ora_refine(const ora_problem* P, ora_tree* T, int32_t factor, const int64_t* hint_cell)
+{
+    if (factor < 2) return ORA_ERR_ARG;
+    const int64_t nc = n_cells_of(P);
+    T->n_cells = nc;
+    for (int64_t c = 0; c < nc; ++c) {
+        T->tbl_cost[c] = INFINITY;
+        T->tbl_id[c] = -1;
+    }
+    for (int64_t i = 0; i < T->n_tree; ++i) {
+        const int64_t c = ora_cell_of(P, &T->x[i * ORA_MAX_STATE], hint_cell ? &hint_cell[i] : NULL, NULL);
+        T->cell[i] = c;
+        if (T->status[i] != ORA_TERMINAL && key_less(T->cost[i], i, T->tbl_cost[c], T->tbl_id[c])) {
+            T->tbl_cost[c] = T->cost[i];
+            T->tbl_id[c] = i;
+        }
+    }
+    /* cursor: old region -> its first cell in the refined grid */
+    int64_t c = T->cursor, bits = 0;
+    if (P->vel_sign_bins) {
+        bits = c % 8;
+        c /= 8;
+    }
+    const int64_t og1 = P->grid[1] / factor, og2 = P->grid[2] / factor;
+    const int64_t iz = c % og2, iy = (c / og2) % og1, ix = c / (og2 * og1);
+    const int64_t s2 = ((ix * factor) * P->grid[1] + iy * factor) * P->grid[2] + iz * factor;
+    T->cursor = P->vel_sign_bins ? s2 * 8 + bits : s2;
+    if (T->n_tree + survivors_bound(P) > T->cap) T->full = 1;
+    return ORA_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Trajectory check: re-integrate the controls open loop from x_init in      */
 /* float64, test every substep against the exact valid set (no margin),      */

@@ -181,6 +181,14 @@ int64_t ora_select(const ora_problem* P, const ora_tree* T, int64_t* sel, int64_
 void ora_prune(const ora_problem* P, ora_tree* T);
 int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H);
 
+/* Adaptive decomposition: P already holds the refined grid (factor times the
+ * old one per axis) and T's region arrays hold its regions.  Every node's
+ * region is recomputed; the region table is rebuilt from the nodes that are
+ * not terminal; the cursor moves to the first refined cell of its old cell;
+ * the tree is marked full when the survivor bound no longer fits.  hint_cell
+ * (optional, per node) is adopted where a region decision is within band. */
+int ora_refine(const ora_problem* P, ora_tree* T, int32_t factor, const int64_t* hint_cell);
+
 int ora_verify(const ora_problem* P, int32_t n_edges, const float* controls, const int32_t* steps,
                const float* states, double reported_cost, ora_verify_report* rep);
 

@@ -138,6 +138,7 @@ def lib():
         L.ora_prune.argtypes = [C.POINTER(ProblemC), C.POINTER(TreeC)]
         L.ora_step.argtypes = [C.POINTER(ProblemC), C.POINTER(TreeC), C.POINTER(CandsC),
                                C.POINTER(HintsC)]
+        L.ora_refine.argtypes = [C.POINTER(ProblemC), C.POINTER(TreeC), C.c_int32, _i64p]
         L.ora_step.restype = C.c_int
         L.ora_verify.argtypes = [C.POINTER(ProblemC), C.c_int32, _f32p, _i32p, _f32p, C.c_double,
                                  C.POINTER(VerifyC)]
@@ -342,10 +343,10 @@ class Cands:
 class Tree:
     """The oracle's float64 tree (caller-owned numpy storage)."""
 
-    def __init__(self, P: Problem, cap: Optional[int] = None):
+    def __init__(self, P: Problem, cap: Optional[int] = None, cells_cap: Optional[int] = None):
         self.P = P
         cap = int(P.params.tree_cap if cap is None else cap)
-        nc = P.n_cells
+        nc = max(P.n_cells, int(cells_cap or 0))  # region arrays; refinement may grow the count
         self.x = np.zeros((cap, MAX_STATE), np.float64)
         self.u = np.zeros((cap, MAX_CONTROL), np.float32)
         self.steps = np.zeros(cap, np.int32)
@@ -358,7 +359,7 @@ class Tree:
         self.tbl_id = np.full(nc, -1, np.int64)
         s = TreeC()
         s.cap = cap
-        s.n_cells = nc
+        s.n_cells = P.n_cells
         for name, ct in (("x", _f64p), ("u", _f32p), ("steps", _i32p), ("parent", _i64p),
                          ("cost", _f64p), ("cell", _i64p), ("status", _u8p), ("icount", _i32p),
                          ("tbl_cost", _f64p), ("tbl_id", _i64p)):
@@ -390,6 +391,19 @@ class Tree:
                     setattr(hc, name, _ptr(a, ct))
             h = C.byref(hc)
         return lib().ora_step(self.P.ref, C.byref(self.c), C.byref(self.cands.c), h)
+
+    def refine(self, P_new: Problem, factor: int, hint_cell=None) -> int:
+        """Adaptive decomposition: P_new is the problem with the refined grid
+        (see ora_refine); hint_cell (optional, per node) is the other side's
+        region of each node."""
+        assert len(self.tbl_id) >= P_new.n_cells
+        self.P = P_new
+        h = None
+        if hint_cell is not None:
+            h = np.ascontiguousarray(hint_cell, dtype=np.int64)
+        rc = lib().ora_refine(P_new.ref, C.byref(self.c), int(factor), _ptr(h, _i64p) if h is not None else None)
+        self._keep_hint = h
+        return rc
 
     def select(self):
         sel = np.zeros(max(1, self.P.params.n_select), np.int64)

@@ -31,11 +31,11 @@ def field_to_cost(field, cost_kind):
     return f.astype(np.float64) if cost_kind == "TIME" else f.view(np.float32).astype(np.float64)
 
 
-def oracle_tree_from_snapshot(O, P, snap):
+def oracle_tree_from_snapshot(O, P, snap, cells_cap=None):
     """An oracle Tree holding exactly the GPU's tree (float32 widened)."""
     c = snap["counters"]
     n = int(c["n_tree"])
-    tr = O.Tree(P)
+    tr = O.Tree(P, cells_cap=cells_cap)
     kind = P.problem.cost
     tr.x[:n, : P.d] = snap["state"].T.astype(np.float64)
     tr.u[:n, : P.m] = snap["control"].T
@@ -46,7 +46,7 @@ def oracle_tree_from_snapshot(O, P, snap):
     tr.status[:n] = snap["status"]
     tr.icount[:n] = snap["icount"]
     tbl = snap["cell_table"]
-    reached = tbl != EMPTY
+    reached = np.flatnonzero(tbl != EMPTY)
     tr.tbl_id[:] = -1
     tr.tbl_cost[:] = np.inf
     tr.tbl_id[reached] = (tbl[reached] & np.uint64(0xFFFFFFFF)).astype(np.int64)
@@ -138,15 +138,16 @@ def compare_trees(P, tr, snap, report, polished=None):
     err = np.abs(xs - tr.x[:n, : P.d]) / np.maximum(1.0, np.abs(tr.x[:n, : P.d]))
     assert err.max() <= STATE_RTOL
     tbl = snap["cell_table"]
+    assert int(tr.c.n_cells) == len(tbl), (int(tr.c.n_cells), len(tbl))
     reached = tbl != EMPTY
-    np.testing.assert_array_equal(reached, tr.tbl_id >= 0)
-    np.testing.assert_array_equal((tbl[reached] & np.uint64(0xFFFFFFFF)).astype(np.int64),
-                                  tr.tbl_id[reached])
+    tid, tco = tr.tbl_id[: len(tbl)], tr.tbl_cost[: len(tbl)]
+    np.testing.assert_array_equal(reached, tid >= 0)
+    np.testing.assert_array_equal((tbl[reached] & np.uint64(0xFFFFFFFF)).astype(np.int64), tid[reached])
     kc = key_cost(tbl[reached], kind)
     if kind == "TIME":
-        np.testing.assert_array_equal(kc, tr.tbl_cost[reached])
+        np.testing.assert_array_equal(kc, tco[reached])
     else:
-        assert np.all(np.abs(kc - tr.tbl_cost[reached]) <= PATH_RTOL * np.maximum(1.0, kc))
+        assert np.all(np.abs(kc - tco[reached]) <= PATH_RTOL * np.maximum(1.0, kc))
     sol = np.uint64(c["solution_key"])
     if sol == EMPTY:
         assert tr.c.sol_id == -1

@@ -133,6 +133,52 @@ __global__ void k_fill_table(unsigned long long* tbl, uint8_t* act, int n, int n
         act[c] = 0;
 }
 
+// ------------------------------------------------------------ refinement
+
+// Region of every node under the refined grid; the nodes that are not
+// terminal claim their new regions (one per old region, so one per new one),
+// and the active ones mark their regions for the selection.
+__global__ void k_refine_nodes(DevProblem P, DevPtrs T, const DevState* st)
+{
+    const long long n_tree = st->n_tree;
+    const int vi = P.dyn == kQUAD12 ? 6 : 3;  // first velocity component (unused without sign bins)
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_tree;
+         i += (long long)gridDim.x * blockDim.x) {
+        float p[3], v[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p[a] = T.x[(long long)a * P.cap + i];
+            v[a] = P.vel_sign_bins ? T.x[(long long)(vi + a) * P.cap + i] : 0.f;
+        }
+        const int c = cell_of(P, p, v);
+        T.cell[i] = c;
+        const uint8_t s = T.status[i];
+        if (s != kTerminal) {
+            atomicMin(&T.tbl[c], ((unsigned long long)T.cost[i] << 32) | (unsigned long long)(uint32_t)i);
+            if (s == kActive) T.act[c] = 1;  // the region's owner is active: it may be selected
+        }
+    }
+}
+
+// A region index of the old grid (og, f times coarser per axis) -> the first
+// of its cells in the refined grid (velocity-sign bits kept).
+__device__ __forceinline__ int refine_index(const DevProblem& P, int c, int og1, int og2, int f)
+{
+    const int bits = P.vel_sign_bins ? (c & 7) : 0;
+    const int sp = P.vel_sign_bins ? (c >> 3) : c;
+    const int iz = sp % og2, iy = (sp / og2) % og1, ix = sp / (og2 * og1);
+    const int s2 = ((ix * f) * P.grid[1] + iy * f) * P.grid[2] + iz * f;
+    return P.vel_sign_bins ? s2 * 8 + bits : s2;
+}
+
+__global__ void k_refine_state(DevProblem P, DevState* st, int og1, int og2, int f)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    st->cursor = refine_index(P, st->cursor, og1, og2, f);
+    st->cursor_next = refine_index(P, st->cursor_next, og1, og2, f);
+    if (st->n_tree + P.surv_max > P.cap) st->full = 1;
+}
+
 // Initialisation of Alg. 1: the root is x_init, active; its region holds (0, root).
 template <int DYN>
 __global__ void k_init_root(DevProblem P, DevPtrs T, DevState* st, const float* x_init)
@@ -1277,6 +1323,7 @@ struct Sizes {
     int d, m;
     long long cap;
     int n_cells, s_max, n_tiles, n_boxes;
+    int n_cells_cap;      // regions the arrays hold: n_cells * refine_max^3
     int n_act;            // activity bytes, padded to whole words
     int gb_n[3];          // box grid cells per axis
     int gb_entries;       // total list entries of the box grid
@@ -1297,7 +1344,7 @@ void for_each_array(const Sizes& z, F&& f)
     f("icount", cap);
     f("dead", cap);
     f("anc", sizeof(int4) * 2 * cap);
-    f("tbl", sizeof(unsigned long long) * (size_t)z.n_cells);
+    f("tbl", sizeof(unsigned long long) * (size_t)z.n_cells_cap);
     f("sel", sizeof(int) * S);
     f("ckey", sizeof(unsigned long long) * S);
     f("ccell", sizeof(int) * S);
@@ -1310,7 +1357,7 @@ void for_each_array(const Sizes& z, F&& f)
     f("gcell", sizeof(int2) * (size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2]);
     f("glist", sizeof(uint16_t) * (size_t)(z.gb_entries > 0 ? z.gb_entries : 1));
     f("st", 2 * sizeof(DevState));  // double-buffered by iteration parity
-    f("bcount", sizeof(int2) * (size_t)((z.n_cells + kBlock - 1) / kBlock));
+    f("bcount", sizeof(int2) * (size_t)((z.n_cells_cap + kBlock - 1) / kBlock));
     f("stats", sizeof(kpx_iter_stats) * kStatsCap);
     f("d_parent", sizeof(int) * S);
     f("d_u", sizeof(float) * z.m * S);
@@ -1481,6 +1528,10 @@ int validate(const kpx_problem* p, const kpx_params* q, Sizes* z, std::string* w
     if (q->vel_sign_bins && p->dynamics == KPX_DUBINS6) return bad("sign bins need a velocity state");
     if (q->vel_sign_bins) nc *= 8;
     if (nc > (1ll << 30)) return bad("too many regions");
+    if (q->refine_max > 8) return bad("refine_max out of 0..8");
+    const long long rf = q->refine_max > 1 ? q->refine_max : 1;
+    const long long nc_cap = nc * rf * rf * rf;
+    if (nc_cap > (1ll << 30)) return bad("too many regions after refinement");
     if (q->n_select < 1 || q->samples_per_node < 0) return bad("n_select / samples_per_node");
     // candidate slots per iteration: n_select * K, or n_select (the buffer the
     // uncapped form shares out) when samples_per_node = 0
@@ -1495,10 +1546,11 @@ int validate(const kpx_problem* p, const kpx_params* q, Sizes* z, std::string* w
         z->m = m;
         z->cap = q->tree_cap;
         z->n_cells = (int)nc;
+        z->n_cells_cap = (int)nc_cap;
         z->s_max = (int)S;
         z->n_tiles = (int)((S + kTile - 1) / kTile);
         z->n_boxes = p->n_boxes;
-        z->n_act = (int)((nc + 4095) & ~4095ll);
+        z->n_act = (int)((nc_cap + 4095) & ~4095ll);
         BoxGrid g;
         build_box_grid(p, &g);
         for (int a = 0; a < 3; ++a) z->gb_n[a] = g.n[a];
@@ -1650,6 +1702,7 @@ struct kpx_handle {
     int full_cached = 0;
     int n_prune_blocks = 0;
     int cur = 0;                              // which device state is current
+    int refined = 1;                          // total refinement factor per axis so far
     int polish_steps = 0;                     // edge polish of inserted nodes (0: off)
     float polish_lr = 0.f;
     kpxd::DiffConst polish_c{};
@@ -1877,6 +1930,7 @@ struct kpx_batch {
     int cur = 0;
     bool graph_on = false;
     hipGraphExec_t exec[2] = {nullptr, nullptr};  // two iterations from state parity 0 / 1
+    std::vector<int> cells;         // each handle's region count when the batch was made
     std::string err;
 };
 
@@ -2280,6 +2334,39 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* v, int64_t* n_slots)
     return KPX_OK;
 }
 
+int kpx_refine(kpx_handle* h, int32_t factor)
+{
+    if (!h || factor < 2) return KPX_ERR_ARG;
+    const long long rf_max = h->prm.refine_max > 1 ? h->prm.refine_max : 1;
+    if ((long long)h->refined * factor > rf_max) return fail(h, KPX_ERR_ARG, "refine: beyond refine_max");
+    int og[3];
+    long long nc = h->prm.vel_sign_bins ? 8 : 1;
+    for (int a = 0; a < 3; ++a) {
+        og[a] = h->prm.grid[a];
+        nc *= (long long)og[a] * factor;
+    }
+    if (nc > h->z.n_cells_cap) return fail(h, KPX_ERR_ARG, "refine: more regions than allocated");
+    h->refined *= factor;
+    for (int a = 0; a < 3; ++a) {
+        h->prm.grid[a] = og[a] * factor;
+        h->P.grid[a] = h->prm.grid[a];
+        h->P.cell_scale[a] = (float)h->prm.grid[a] / (h->prob.ws_hi[a] - h->prob.ws_lo[a]);
+    }
+    h->z.n_cells = (int)nc;
+    h->P.n_cells = (int)nc;
+    h->P.surv_max = (int)std::min<long long>(nc, h->z.s_max);
+    h->n_prune_blocks = (int)((nc + kBlock - 1) / kBlock);
+    const DevPtrs T = kernel_ptrs(h);
+    k_fill_table<<<std::min(1024, (h->z.n_act + kBlock - 1) / kBlock), kBlock, 0, h->stream>>>(
+        T.tbl, T.act, h->z.n_cells, h->z.n_act);
+    k_refine_nodes<<<1024, kBlock, 0, h->stream>>>(h->P, T, cur_state(h));
+    k_refine_state<<<1, 64, 0, h->stream>>>(h->P, cur_state(h), og[1], og[2], factor);
+    // the pending selection again, over the refined regions from the moved cursor
+    k_select<<<1, kSelectThreads, 0, h->stream>>>(h->P, T, cur_state(h));
+    KPX_HIP(h, hipGetLastError());
+    return KPX_OK;
+}
+
 int kpx_set_polish(kpx_handle* h, const kpx_polish* p)
 {
     if (!h) return KPX_ERR_ARG;
@@ -2463,6 +2550,7 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
     kpx_batch* b = new (std::nothrow) kpx_batch;
     if (!b) return KPX_ERR_OOM;
     b->hs.assign(handles, handles + n);
+    for (int q = 0; q < n; ++q) b->cells.push_back(handles[q]->z.n_cells);
     b->user = handles[0]->stream;
     b->cur = handles[0]->cur;
     int dev = 0, lds_max = 0;
@@ -2562,6 +2650,8 @@ int kpx_batch_iterate(kpx_batch* b, int32_t n_iters)
     for (kpx_handle* h : b->hs)
         if (h->cur != b->cur || h->dump_on || h->polish_steps > 0)
             return bfail(b, KPX_ERR_STATE, "a handle left the batch's step or has edge polish on");
+    for (size_t q = 0; q < b->hs.size(); ++q)
+        if (b->hs[q]->z.n_cells != b->cells[q]) return bfail(b, KPX_ERR_STATE, "a handle was refined");
     if (n_iters == 0) return KPX_OK;
     // order the batch stream after the work already on the handles' stream
     if (hipEventRecord(b->ev_in, b->user) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess)

@@ -49,7 +49,7 @@ class ParamsC(C.Structure):
         ("dt", C.c_float), ("steps_min", C.c_int32), ("steps_max", C.c_int32),
         ("grid", C.c_int32 * 3), ("vel_sign_bins", C.c_int32), ("n_select", C.c_int32),
         ("samples_per_node", C.c_int32), ("i_max", C.c_int32), ("tree_cap", C.c_int64),
-        ("seed", C.c_uint64), ("query_id", C.c_uint32), ("reserved", C.c_uint32),
+        ("seed", C.c_uint64), ("query_id", C.c_uint32), ("refine_max", C.c_uint32),
     ]
 
 
@@ -130,6 +130,7 @@ def lib():
         L.kpx_read_dump.argtypes = [_vp, C.POINTER(DumpViewC), C.POINTER(i64)]
         L.kpx_set_timing.argtypes = [_vp, i32]
         L.kpx_set_polish.argtypes = [_vp, C.POINTER(PolishC)]
+        L.kpx_refine.argtypes = [_vp, i32]
         L.kpx_read_timing.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(i64)]
         L.kpx_stats_capacity.argtypes = [_vp, C.POINTER(i64)]
         L.kpx_read_stats.argtypes = [_vp, i64, i64, C.POINTER(IterStatsC)]
@@ -151,7 +152,7 @@ def lib():
                      "kpx_read_dump", "kpx_set_timing", "kpx_read_timing", "kpx_stats_capacity",
                      "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy",
                      "kpx_batch_create", "kpx_batch_set_graph", "kpx_batch_iterate",
-                     "kpx_batch_destroy", "kpx_set_polish"):
+                     "kpx_batch_destroy", "kpx_set_polish", "kpx_refine"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -202,6 +203,7 @@ def params_struct(params):
     s.tree_cap = params.tree_cap
     s.seed = params.seed
     s.query_id = params.query_id
+    s.refine_max = int(getattr(params, "refine_max", 0))
     return s
 
 
@@ -252,6 +254,7 @@ class Planner:
         self.d = {"DI6": 6, "QUAD12": 12, "DUBINS6": 6}[problem.dynamics]
         self.m = {"DI6": 3, "QUAD12": 4, "DUBINS6": 3}[problem.dynamics]
         self.n_cells = params.n_cells
+        self.grid = tuple(int(g) for g in params.grid)
         self._ps, self._boxes = problem_struct(problem)
         self._qs = params_struct(params)
         self.device = torch.device(device)
@@ -374,6 +377,12 @@ class Planner:
         """Edge polish of the nodes each later iteration inserts (steps = 0: off)."""
         p = PolishC(int(steps), lr, w_ctrl, w_obst, k_obst, d_safe, w_goal)
         self._check(lib().kpx_set_polish(self.h, C.byref(p)))
+
+    def refine(self, factor: int = 2):
+        """Divides every region cell by `factor` per axis (adaptive decomposition)."""
+        self._check(lib().kpx_refine(self.h, int(factor)))
+        self.grid = tuple(int(g) * int(factor) for g in self.grid)
+        self.n_cells *= int(factor) ** 3
 
     def set_timing(self, enable=True):
         """True times all four kernels, False none; an int is the kernel bit mask."""

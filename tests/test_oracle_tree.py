@@ -300,3 +300,63 @@ def test_init_rejects_bad_problems(ora):
     w = W.make_workload("dubins6", 0)
     w.params.vel_sign_bins = 1
     assert ora.Tree(ora.Problem(w.problem, w.params)).init() == ora.ERR_ARG
+
+
+def _coarse(cell, grid_new, f, vel):
+    bits = cell % 8 if vel else 0
+    s = cell // 8 if vel else cell
+    gz, gy = grid_new[2], grid_new[1]
+    iz, iy, ix = s % gz, (s // gz) % gy, s // (gz * gy)
+    s0 = ((ix // f) * (gy // f) + iy // f) * (gz // f) + iz // f
+    return s0 * 8 + bits if vel else s0
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("di6", dict(n_select=100, samples=7, tree_cap=1 << 15, grid=(8, 8, 8))),
+    ("quad12", dict(n_select=90, samples=9, tree_cap=1 << 15, grid=(4, 4, 4))),
+])
+def test_refine_keeps_the_invariants(ora, name, kw):
+    """Adaptive decomposition: after 12 iterations the grid is halved per
+    axis; every node's region is its state's region in the new grid and lies
+    inside its old one, the live nodes own their new regions one each, the
+    table holds nothing else, the cursor moved to the first new cell of its
+    old one, and 12 more iterations keep one live owner per region."""
+    import dataclasses
+
+    w = W.make_workload(name, 3, **kw)
+    w.params.refine_max = 2
+    vel = bool(w.params.vel_sign_bins)
+    P = ora.Problem(w.problem, w.params)
+    P2 = ora.Problem(w.problem, dataclasses.replace(w.params, grid=tuple(2 * g for g in w.params.grid)))
+    tr = ora.Tree(P, cells_cap=P2.n_cells)
+    assert tr.init() == ora.OK
+    for _ in range(12):
+        assert tr.step() == ora.OK
+    n = tr.n_tree
+    old_cell = tr.cell[:n].copy()
+    old_status = tr.status[:n].copy()
+    old_cursor = int(tr.c.cursor)
+    assert tr.refine(P2, 2) == ora.OK
+    assert int(tr.c.n_cells) == P2.n_cells == 8 * P.n_cells
+    for i in range(n):
+        c = int(tr.cell[i])
+        assert c == ora.cell_of(P2, tr.x[i, : P.d])[0]
+        assert _coarse(c, P2.params.grid, 2, vel) == old_cell[i]
+    np.testing.assert_array_equal(tr.status[:n], old_status)
+    live = np.flatnonzero(tr.status[:n] != T)
+    assert len(set(tr.cell[live].tolist())) == len(live)
+    np.testing.assert_array_equal(tr.tbl_id[tr.cell[live]], live)
+    np.testing.assert_array_equal(tr.tbl_cost[tr.cell[live]], tr.cost[live])
+    assert int((tr.tbl_id[: P2.n_cells] >= 0).sum()) == len(live)
+    assert _coarse(int(tr.c.cursor), P2.params.grid, 2, vel) == old_cursor
+    for _ in range(12):
+        rc = tr.step()
+        if rc == ora.FULL:
+            break
+        m = tr.n_tree
+        live = np.flatnonzero(tr.status[:m] != T)
+        assert len(set(tr.cell[live].tolist())) == len(live)
+        np.testing.assert_array_equal(tr.tbl_id[tr.cell[live]], live)
+        for i in range(n, m):
+            assert tr.cell[i] == ora.cell_of(P2, tr.x[i, : P.d])[0]
+    assert tr.n_tree > n

@@ -91,6 +91,7 @@ class Params:
     i_max: int
     seed: int
     query_id: int = 0
+    refine_max: int = 0  # largest total grid refinement factor per axis (0/1: none)
 
     @property
     def n_cells(self) -> int:
