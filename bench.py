@@ -89,6 +89,8 @@ def parse():
                     help="iteration budget of each of those queries")
     ap.add_argument("--polish", type=int, default=0,
                     help="edge polish steps of every inserted node (quadrotor, TIME cost); 0 = plain")
+    ap.add_argument("--refine-at", type=int, default=0,
+                    help="solution runs: halve the region cells per axis after this many iterations")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--time-all", action="store_true",
                     help="HIP events around all four kernels (default: propagate only)")
@@ -182,8 +184,9 @@ def main():
         t_first = float((int(all_st["t_end"][first_it]) - int(all_st["t_begin"][0])) / rate * 1e3)
 
     planner.close()
-    sols = solution_medians(K, W, a, a.polish) if a.solution_seeds > 0 else None
-    sols_plain = solution_medians(K, W, a, 0) if a.solution_seeds > 0 and a.polish else None
+    sols = solution_medians(K, W, a, a.polish, a.refine_at) if a.solution_seeds > 0 else None
+    sols_plain = (solution_medians(K, W, a, 0) if a.solution_seeds > 0 and (a.polish or a.refine_at)
+                  else None)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -217,25 +220,41 @@ def main():
 BUDGETS_MS = (5.0, 10.0, 20.0, 40.0)
 
 
-def solution_medians(K, W, a, polish=0):
+def solution_medians(K, W, a, polish=0, refine_at=0):
     """Median device-timed time to first solution and median solution cost
     over seeds 0 .. solution_seeds - 1 of the workload, each run for
     solution_iters iterations (or until its tree is full), with edge polish
     of `polish` steps (0: the plain planner).  Also the cost of the best plan
     known at fixed device-time budgets (median over all seeds, an unsolved
-    seed counting as infinite) and the number of seeds solved by then."""
+    seed counting as infinite) and the number of seeds solved by then.  With
+    refine_at > 0 the region grid is halved per axis after that many
+    iterations (adaptive decomposition)."""
     from paper_2602_02846_amd.autotune import first_solution_ms
 
-    times, costs = [], []
+    times, costs, refine_ms = [], [], []
     at_budget = {b: [] for b in BUDGETS_MS}
     dt = None
     for seed in range(a.solution_seeds):
         w = W.make_workload(a.workload, seed)
         dt = w.params.dt
+        if refine_at:
+            w.params.refine_max = 2
         p = K.Planner(w.problem, w.params)
         if polish:
             p.set_polish(polish)
-        p.iterate(a.solution_iters)
+        if 0 < refine_at < a.solution_iters:
+            import torch
+
+            p.iterate(refine_at)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            p.refine(2)
+            e1.record()
+            p.iterate(a.solution_iters - refine_at)
+            torch.cuda.synchronize()
+            refine_ms.append(e0.elapsed_time(e1))
+        else:
+            p.iterate(a.solution_iters)
         p.sync()
         t = first_solution_ms(p, a.solution_iters)
         if t is not None:
@@ -251,6 +270,8 @@ def solution_medians(K, W, a, polish=0):
             at_budget[b].append(np.inf if best == (1 << 64) - 1 else (best >> 32) * dt)
         p.close()
     return {"queries": a.solution_seeds, "iterations": a.solution_iters, "polish_steps": polish,
+            "refine_at": refine_at,
+            "refine_ms_median": round(float(np.median(refine_ms)), 4) if refine_ms else None,
             "solved": len(times),
             "time_to_first_solution_ms_median": round(float(np.median(times)), 3) if times else None,
             "cost_median": round(float(np.median(costs)), 4) if costs else None,
