@@ -406,8 +406,11 @@ def diff_traffic():
     path = os.path.join(ROOT, "profiles", "diff_quad12_65536_traffic.txt")
     if not os.path.exists(path):
         return None
-    with open(os.path.join(ROOT, "paper_2602_02846_amd/csrc/kpx_diff.hip"), "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
+    h = hashlib.sha256()
+    for f in ("paper_2602_02846_amd/csrc/kpx_diff.hip", "paper_2602_02846_amd/csrc/kpx_diff_device.hpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()
     fields = {}
     with open(path) as fh:
         for line in fh:
