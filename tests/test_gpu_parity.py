@@ -45,6 +45,8 @@ LOCKSTEP = {
     "di6_path": (dict(n_select=300, samples=9, tree_cap=1 << 16, cost="PATH_LENGTH"), 30),
     "quad12": (dict(n_select=260, samples=9, tree_cap=1 << 16, grid=(8, 8, 8)), 25),
     "dubins6": (dict(n_select=230, samples=11, tree_cap=1 << 16, grid=(16, 16, 8)), 25),
+    "quad12_path": (dict(n_select=260, samples=9, tree_cap=1 << 16, grid=(8, 8, 8), cost="PATH_LENGTH"), 20),
+    "dubins6_path": (dict(n_select=230, samples=11, tree_cap=1 << 16, grid=(16, 16, 8), cost="PATH_LENGTH"), 20),
 }
 
 
