@@ -90,3 +90,24 @@ def test_batch_rejects_bad_groupings(kpx):
         kpx.Batch(ps)
     for p in ps:
         p.close()
+
+
+def test_autotuner_scores_every_candidate(kpx):
+    """The samples-per-node autotuner runs each candidate on a sample of each
+    model's queries and keeps the one with the lowest median time to a first
+    solution; with_samples keeps N*K and fits an iteration in half the tree."""
+    from paper_2602_02846_amd.autotune import autotune_samples, with_samples
+
+    ws = _small_batch(8, 3)
+    chosen, scores = autotune_samples(ws, candidates=(4, 8), iterations=12, sample=3)
+    assert set(chosen) == {w.problem.dynamics for w in ws}
+    for model, k in chosen.items():
+        assert set(scores[model]) == {4, 8}
+        assert all(v > 0 for v in scores[model].values())
+        assert scores[model][k] == min(scores[model].values())
+    for w in ws:
+        w2 = with_samples(w, 8)
+        assert w2.params.samples_per_node == 8
+        assert w2.params.n_select * 8 <= max(8, w.params.n_select * w.params.samples_per_node)
+        assert w2.params.n_select * 8 <= w.params.tree_cap // 2 or w2.params.n_select == 1
+        assert w.params.samples_per_node != 8 or w2.params.n_select == w.params.n_select
