@@ -16,6 +16,10 @@
  *     stream (the caller's, or the default stream when NULL is passed).
  *   - Node status codes: 0 = active (V_A), 1 = inactive (V_I),
  *     2 = terminal (V_T); V_U is the per-iteration survivor mask (Sec. IV).
+ *   - Beside the planner: batches of independent queries (kpx_batch_*), the
+ *     adaptive decomposition (kpx_refine), and the differentiable quadrotor
+ *     edge rollout with its gradient (kpx_diff_*), also used to polish the
+ *     planner's inserted edges (kpx_set_polish).
  */
 #ifndef KPX_H
 #define KPX_H
@@ -257,6 +261,7 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* view, int64_t* n_slots);
 /* Brackets the kernels of every following iteration with HIP events on the
  * handle's stream: bit k of kernel_mask (0..15) times kernel k (numbered as
  * in kpx_read_timing); 0 stops.  Each call clears the accumulated times.
+ * The edge-polish kernel (kpx_set_polish) is not among them.
  * KPX_ERR_ARG for a mask outside 0..15. */
 int kpx_set_timing(kpx_handle* h, int32_t kernel_mask);
 
