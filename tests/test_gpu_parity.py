@@ -149,3 +149,21 @@ def test_lockstep_uncapped_form(kpx, ora, case):
     print(case, rep)
     assert rep["iterations"] == iters and rep["valid"] > 0
     pl.close()
+
+
+@pytest.mark.parametrize("name,iters", [("quad12", 200), ("dubins6", 300)])
+def test_full_size_solution_verifies(kpx, ora, name, iters):
+    """A full-size plan of the quadrotor and Dubins workloads, re-integrated
+    open loop by the oracle in float64 against the exact sets (no margin)."""
+    w = W.make_workload(name, 0)
+    P = ora.Problem(w.problem, w.params)
+    pl = _planner(kpx, w)
+    pl.iterate(iters)
+    sol = pl.solution()
+    print(name, "first solution at iteration", pl.counters()["first_solution_iteration"],
+          "cost", sol["cost"] if sol["found"] else None)
+    assert sol["found"], pl.counters()
+    rep = ora.verify(P, sol["controls"], sol["steps"], sol["states"], float(sol["cost_field"])
+                     if w.problem.cost == "TIME" else float(sol["cost"]))
+    assert rep["ok"], rep
+    pl.close()
