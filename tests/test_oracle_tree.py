@@ -360,3 +360,30 @@ def test_refine_keeps_the_invariants(ora, name, kw):
         for i in range(n, m):
             assert tr.cell[i] == ora.cell_of(P2, tr.x[i, : P.d])[0]
     assert tr.n_tree > n
+
+
+def test_polish_closed_form_without_scene_terms(ora):
+    """With the obstacle and goal terms off the tied loss is n dt + 4 w_ctrl |u|^2,
+    so each projected step scales the control by 1 - 8 lr w_ctrl (the box
+    contains the scaled control: thrust >= 0, torques symmetric); every
+    polished node's control is the sampled one times that factor cubed."""
+    w = W.make_workload("quad12", 2, n_select=48, samples=6, grid=(8, 8, 8), tree_cap=1 << 15)
+    pol = dict(steps=3, lr=0.01, w_obst=0.0, w_goal=0.0)
+    P = ora.Problem(w.problem, w.params, polish=pol)
+    f32 = lambda v: float(np.float32(v))  # noqa: E731
+    factor = (1.0 - 8.0 * f32(0.01) * f32(0.1)) ** 3
+    tr = ora.Tree(P)
+    assert tr.init() == ora.OK
+    checked = 0
+    for _ in range(8):
+        assert tr.step() == ora.OK
+        c = tr.cands.view()
+        for s in np.flatnonzero(c["survivor"]):
+            i = int(c["new_index"][s])
+            u0 = c["u"][s, :4].astype(np.float64)
+            u1 = tr.u[i, :4]
+            if np.array_equal(u0.astype(np.float32), u1):
+                continue  # rejected: left its region or became invalid
+            np.testing.assert_array_equal(u1, (u0 * factor).astype(np.float32))
+            checked += 1
+    assert checked > 20
