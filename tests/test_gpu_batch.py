@@ -111,3 +111,28 @@ def test_autotuner_scores_every_candidate(kpx):
         assert w2.params.n_select * 8 <= max(8, w.params.n_select * w.params.samples_per_node)
         assert w2.params.n_select * 8 <= w.params.tree_cap // 2 or w2.params.n_select == 1
         assert w.params.samples_per_node != 8 or w2.params.n_select == w.params.n_select
+
+
+def test_batch_of_uncapped_queries_matches_each_alone(kpx):
+    """Queries in the uncapped form (every active node, lambda per iteration
+    from the device state) batched with capped ones."""
+    ws = _small_batch(6, 11)
+    for w in ws[::2]:
+        w.params.samples_per_node = 0
+        w.params.n_select = 600
+    alone = []
+    for w in ws:
+        p = kpx.Planner(w.problem, w.params)
+        p.iterate(15)
+        p.sync()
+        alone.append(p.snapshot())
+        p.close()
+    ps = [kpx.Planner(w.problem, w.params) for w in ws]
+    b = kpx.Batch(ps, graph=True)
+    b.iterate(15)
+    b.sync()
+    for q, (p, a) in enumerate(zip(ps, alone)):
+        _same(p.snapshot(), a, f"query {q}")
+    b.close()
+    for p in ps:
+        p.close()

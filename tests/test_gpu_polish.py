@@ -98,3 +98,28 @@ def test_polished_plan_reverifies(kpx, ora):
     rep = ora.verify(P, sol["controls"], sol["steps"], sol["states"], float(sol["cost_field"]))
     assert rep["ok"], rep
     pl.close()
+
+
+def test_lockstep_polish_with_uncapped_form_and_refinement(kpx, ora):
+    """Polish in the uncapped form (lambda from the device state), across a
+    refinement of the regions."""
+    import dataclasses
+
+    w = W.make_workload("quad12", 9, n_select=1100, samples=0, tree_cap=1 << 15, grid=(4, 4, 4))
+    w.params.refine_max = 2
+    P = ora.Problem(w.problem, w.params, polish=POLISH)
+    P2 = ora.Problem(w.problem, dataclasses.replace(w.params, grid=(8, 8, 8)), polish=POLISH)
+    pl = kpx.Planner(w.problem, w.params)
+    pl.set_polish(**POLISH)
+    rep = parity.lockstep(ora, P, pl, 8)
+    pre = pl.snapshot()
+    pl.refine(2)
+    post = pl.snapshot()
+    tr = parity.oracle_tree_from_snapshot(ora, P, pre, cells_cap=P2.n_cells)
+    assert tr.refine(P2, 2, hint_cell=post["cell"]) == ora.OK
+    np.testing.assert_array_equal(post["cell"], tr.cell[: len(post["cell"])])
+    rep2 = parity.lockstep(ora, P2, pl, 8)
+    print(rep, rep2)
+    assert rep["iterations"] == 8 and rep2["iterations"] == 8
+    assert rep["polished"] + rep2["polished"] > 0
+    pl.close()
