@@ -126,7 +126,14 @@ class Rollout:
 
     def loss_grad_into(self, x0, u, n, loss, grad=None):
         """As loss_grad, into caller tensors (no allocation)."""
-        E = int(n.numel())
+        import torch
+
+        E = self._args(x0, u, n)
+        if loss.dtype != torch.float32 or loss.device != self.device or loss.numel() != E or not loss.is_contiguous():
+            raise ValueError(f"loss must be a contiguous float32 tensor of {E} entries on {self.device}")
+        if grad is not None and (grad.dtype != torch.float32 or grad.device != self.device
+                                 or tuple(grad.shape) != (16, E) or not grad.is_contiguous()):
+            raise ValueError(f"grad must be a contiguous (16, {E}) float32 tensor on {self.device}")
         self._check(_lib().kpx_diff_loss_grad(self.h, x0.data_ptr(), u.data_ptr(), n.data_ptr(), E,
                                               loss.data_ptr(),
                                               None if grad is None else grad.data_ptr()))
@@ -139,6 +146,8 @@ class Rollout:
         E = self._args(x0, u, n)
         if loss is None:
             loss = torch.empty(E, dtype=torch.float32, device=self.device)
+        elif loss.dtype != torch.float32 or loss.device != self.device or loss.numel() != E or not loss.is_contiguous():
+            raise ValueError(f"loss must be a contiguous float32 tensor of {E} entries on {self.device}")
         bad = torch.empty(E, dtype=torch.int32, device=self.device) if validity else None
         self._check(_lib().kpx_diff_polish(self.h, x0.data_ptr(), u.data_ptr(), n.data_ptr(), E,
                                            int(steps), float(lr), loss.data_ptr(),

@@ -274,3 +274,25 @@ def test_polished_edges_are_rejudged_by_the_oracle(scene, ora):
     exact = _check_validity(ora, D, b, up, nn, bad, keep)
     assert exact >= len(keep) - 2
     print(f"valid after 3 polish steps: {(bad[keep] == 0).sum()} of {len(keep)}")
+
+
+def test_rejects_tensors_that_do_not_fit(scene):
+    import torch
+
+    b, R, _ = scene
+    x0, u, n = _dev(b.x0[:100], b.u[:100], b.n[:100])
+    loss = torch.empty(100, device="cuda")
+    grad = torch.empty((16, 100), device="cuda")
+    for bad in ((x0[:, :50], u, n), (x0, u[:8], n), (x0.T.contiguous().T, u, n),
+                (x0.double(), u, n), (x0, u, n.long())):
+        with pytest.raises(ValueError):
+            R.loss_grad_into(*bad, loss, grad)
+    with pytest.raises(ValueError):
+        R.loss_grad_into(x0, u, n, loss[:50], grad)
+    with pytest.raises(ValueError):
+        R.loss_grad_into(x0, u, n, loss, grad[:, :50])
+    with pytest.raises(ValueError):
+        R.polish(x0, u.clone(), n, steps=1, loss=loss[:10])
+    R.loss_grad_into(x0, u, n, loss, grad)  # the right shapes still run
+    torch.cuda.synchronize()
+    assert torch.isfinite(loss).all()
