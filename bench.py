@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--refine-at", type=int, default=0,
                     help="solution runs: halve the region cells per axis after this many iterations")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--timing-every", type=int, default=8,
+                    help="bracket the kernels with HIP events in every n-th timed iteration")
     ap.add_argument("--time-all", action="store_true",
                     help="HIP events around all four kernels (default: propagate only)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -140,8 +142,9 @@ def main():
     snap_start = planner.snapshot() if not a.no_cpu_baseline else None
     c0 = planner.counters()
     if not a.no_timing:
-        # HIP events around propagate (the roofline kernel), or all four kernels
-        planner.set_timing(15 if a.time_all else 1)
+        # HIP events around propagate (the roofline kernel), or all four
+        # kernels, in every timing_every-th iteration of the timed region
+        planner.set_timing(15 if a.time_all else 1, every=a.timing_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     planner.iterate(a.steps)
@@ -165,8 +168,11 @@ def main():
         kernel_ms = {name: (ms[i] / launches[i] if launches[i] else None)
                      for i, name in enumerate(["propagate", "prune_flags", "insert",
                                                "finalize_select"]) if launches[i]}
-        if launches[0]:
-            fl = FLOPS_PER_SUBSTEP[(prob.dynamics, prob.cost)] * substeps / launches[0]
+        if launches[0] and done:
+            # the FLOPs of the launches the events bracketed (every
+            # timing_every-th timed iteration, from the first), over their time
+            sampled = st["substeps"][:: max(1, a.timing_every)][: launches[0]]
+            fl = FLOPS_PER_SUBSTEP[(prob.dynamics, prob.cost)] * float(sampled.sum()) / launches[0]
             avg_s = ms[0] / launches[0] / 1e3
             achieved = fl / avg_s / 1e12
             roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,

@@ -265,6 +265,11 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* view, int64_t* n_slots);
  * KPX_ERR_ARG for a mask outside 0..15. */
 int kpx_set_timing(kpx_handle* h, int32_t kernel_mask);
 
+/* Times the selected kernels only in every period-th iteration from now on
+ * (1, the default: every iteration), so that the events' own cost stays
+ * small in long runs.  KPX_ERR_ARG for period < 1. */
+int kpx_set_timing_every(kpx_handle* h, int32_t period);
+
 /* Waits and returns, per kernel (0 propagate, 1 prune + survivor flags,
  * 2 insert, 3 close of the iteration + next selection), the summed
  * milliseconds and the number of launches timed since timing was enabled. */

@@ -1693,6 +1693,8 @@ struct kpx_handle {
     bool owns = false;
     bool dump_on = false;
     int timing_mask = 0;                      // bit k: kernel k is timed
+    int timing_every = 1;                     // ... in every timing_every-th iteration
+    long long timing_iter = 0;                // iterations since timing was set
     struct Timed {
         int kernel;
         hipEvent_t begin, end;
@@ -1877,7 +1879,7 @@ hipEvent_t take_event(kpx_handle* h)
 template <typename F>
 int timed_launch(kpx_handle* h, int k, F&& launch)
 {
-    if (!(h->timing_mask & (1 << k))) {
+    if (!(h->timing_mask & (1 << k)) || h->timing_iter % h->timing_every != 0) {
         launch();
         return KPX_OK;
     }
@@ -2145,6 +2147,7 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
              })) != KPX_OK)
             return rc;
         h->cur ^= 1;  // the state the close of this iteration wrote is current
+        ++h->timing_iter;
     }
     KPX_HIP(h, hipGetLastError());
     return KPX_OK;
@@ -2424,6 +2427,15 @@ int kpx_set_timing(kpx_handle* h, int32_t kernel_mask)
     }
     h->timed.clear();
     h->timing_mask = kernel_mask;
+    h->timing_iter = 0;
+    return KPX_OK;
+}
+
+int kpx_set_timing_every(kpx_handle* h, int32_t period)
+{
+    if (!h || period < 1) return KPX_ERR_ARG;
+    h->timing_every = period;
+    h->timing_iter = 0;
     return KPX_OK;
 }
 

@@ -129,6 +129,7 @@ def lib():
         L.kpx_set_dump.argtypes = [_vp, i32]
         L.kpx_read_dump.argtypes = [_vp, C.POINTER(DumpViewC), C.POINTER(i64)]
         L.kpx_set_timing.argtypes = [_vp, i32]
+        L.kpx_set_timing_every.argtypes = [_vp, i32]
         L.kpx_set_polish.argtypes = [_vp, C.POINTER(PolishC)]
         L.kpx_refine.argtypes = [_vp, i32]
         L.kpx_read_timing.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(i64)]
@@ -152,7 +153,7 @@ def lib():
                      "kpx_read_dump", "kpx_set_timing", "kpx_read_timing", "kpx_stats_capacity",
                      "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy",
                      "kpx_batch_create", "kpx_batch_set_graph", "kpx_batch_iterate",
-                     "kpx_batch_destroy", "kpx_set_polish", "kpx_refine"):
+                     "kpx_batch_destroy", "kpx_set_polish", "kpx_refine", "kpx_set_timing_every"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -384,10 +385,12 @@ class Planner:
         self.grid = tuple(int(g) * int(factor) for g in self.grid)
         self.n_cells *= int(factor) ** 3
 
-    def set_timing(self, enable=True):
-        """True times all four kernels, False none; an int is the kernel bit mask."""
+    def set_timing(self, enable=True, every: int = 1):
+        """True times all four kernels, False none; an int is the kernel bit
+        mask.  Only every `every`-th iteration is timed."""
         mask = (15 if enable else 0) if isinstance(enable, bool) else int(enable)
         self._check(lib().kpx_set_timing(self.h, mask))
+        self._check(lib().kpx_set_timing_every(self.h, int(every)))
 
     def read_timing(self):
         ms = (C.c_double * 4)()

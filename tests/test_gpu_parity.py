@@ -127,8 +127,14 @@ def test_stats_ring_and_timing(kpx):
     pl.iterate(5)
     ms, launches = pl.read_timing()
     assert launches == [5, 0, 0, 0] and ms[0] > 0 and ms[1:] == [0.0, 0.0, 0.0]
+    pl.set_timing(15, every=4)  # iterations 0, 4, 8 of the next 10
+    pl.iterate(10)
+    ms, launches = pl.read_timing()
+    assert launches == [3, 3, 3, 3] and all(t > 0 for t in ms)
     with pytest.raises(kpx.KPXError):
         pl.set_timing(16)
+    with pytest.raises(kpx.KPXError):
+        pl.set_timing(1, every=0)
     pl.close()
 
 
