@@ -160,6 +160,8 @@ def _run_with_invariants(ora, w, iterations, polish=None, on_step=None):
             ec = tr.steps[i] if w.problem.cost == "TIME" else None
             z = ora.integrate(P, tr.x[p, : P.d], tr.u[i, : P.m].astype(float), int(tr.steps[i]))
             assert np.array_equal(z[: P.d], tr.x[i, : P.d])
+            # the stored edge is valid in the planning set (substep by substep)
+            assert ora.propagate_edge(P, tr.x[p, : P.d], tr.u[i, : P.m], int(tr.steps[i]))["first_invalid"] == 0
             if ec is not None:
                 assert tr.cost[i] == tr.cost[p] + ec
             else:
@@ -387,3 +389,74 @@ def test_polish_closed_form_without_scene_terms(ora):
             np.testing.assert_array_equal(u1, (u0 * factor).astype(np.float32))
             checked += 1
     assert checked > 20
+
+
+def _grown(problem):
+    import copy
+
+    g = copy.deepcopy(problem)
+    b = np.asarray(problem.boxes, np.float32).reshape(-1, 6)
+    m = np.float32(problem.margin)
+    g.boxes = np.concatenate([b[:, :3] - m, b[:, 3:] + m], axis=1).astype(np.float32)
+    return g
+
+
+@pytest.mark.parametrize("lr", [0.01, 3.0])
+def test_polish_steps_replayed_from_the_tied_gradient(ora, lr):
+    """Each polished node's control equals projected steps replayed here from
+    the complex-step tied gradient of the loss with the given weights (over the
+    grown boxes, towards the goal centre).  lr = 3 overshoots the control box,
+    so the projection decides most components."""
+    w = W.make_workload("quad12", 4, n_select=48, samples=6, grid=(8, 8, 8), tree_cap=1 << 15)
+    pol = dict(steps=2, lr=lr, w_ctrl=0.2, w_obst=0.5, k_obst=40.0, d_safe=0.03, w_goal=2.0)
+    P = ora.Problem(w.problem, w.params, polish=pol)
+    f = lambda v: float(np.float32(v))  # noqa: E731
+    D = ora.DiffProblem(_grown(w.problem), w.params.dt, w_ctrl=0.2, w_obst=0.5, k_obst=40.0, d_safe=0.03,
+                        w_goal=2.0)
+    lo = np.asarray(w.problem.u_lo[:4], np.float64)
+    hi = np.asarray(w.problem.u_hi[:4], np.float64)
+    tr = ora.Tree(P)
+    assert tr.init() == ora.OK
+    checked = clamped = 0
+    for _ in range(12):
+        assert tr.step() == ora.OK
+        c = tr.cands.view()
+        for s in np.flatnonzero(c["survivor"]):
+            i = int(c["new_index"][s])
+            u0 = c["u"][s, :4].astype(np.float64)
+            if np.array_equal(u0.astype(np.float32), tr.u[i, :4]):
+                continue
+            u = u0.copy()
+            x0 = tr.x[tr.parent[i]]
+            for _ in range(2):
+                g = ora.diff_grad_tied(D, x0, np.tile(u, 4), int(tr.steps[i]))
+                u = np.clip(u - f(lr) * g, lo, hi)
+            clamped += int(np.sum((u == lo) | (u == hi)))
+            np.testing.assert_allclose(tr.u[i, :4], u, rtol=1e-6, atol=1e-7)
+            checked += 1
+    assert checked >= 8
+    if lr > 1:
+        assert clamped > checked
+
+
+def test_refinement_that_outgrows_the_capacity_stops_the_tree(ora):
+    """Refining grows the survivor bound min(regions, slots); when the tree can
+    no longer take one more iteration's bound it is full, and the next step
+    reports FULL without changing anything."""
+    import dataclasses
+
+    w = W.make_workload("di6", 3, n_select=100, samples=7, tree_cap=1 << 15, grid=(8, 8, 8))
+    w.params.refine_max = 2
+    P = ora.Problem(w.problem, w.params)
+    tr = ora.Tree(P, cells_cap=8 * P.n_cells)
+    assert tr.init() == ora.OK
+    for _ in range(3):
+        assert tr.step() == ora.OK
+    n = tr.n_tree
+    # a capacity between n + 512 (the bound before) and n + 700 (after: 100 x 7 slots)
+    tr.c.cap = n + 600
+    P2 = ora.Problem(w.problem, dataclasses.replace(w.params, grid=(16, 16, 16)))
+    assert tr.refine(P2, 2) == ora.OK
+    assert tr.c.full == 1
+    assert tr.step() == ora.FULL
+    assert tr.n_tree == n
