@@ -1933,6 +1933,12 @@ struct kpx_batch {
     bool graph_on = false;
     hipGraphExec_t exec[2] = {nullptr, nullptr};  // two iterations from state parity 0 / 1
     std::vector<int> cells;         // each handle's region count when the batch was made
+    // groups after the first run their propagate and insert on side streams
+    // forked from and joined back to the batch stream, so that the models'
+    // kernels overlap (each is bound by its longest edge, not by the machine)
+    std::vector<hipStream_t> side;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     std::string err;
 };
 
@@ -1945,32 +1951,61 @@ int bfail(kpx_batch* b, int code, const std::string& msg)
 }
 
 template <int DYN, int COST>
-void kb_propagate_launch(const kpx_batch* b, const kpx_batch::Group& g, int par)
+void kb_propagate_launch(const kpx_batch* b, const kpx_batch::Group& g, int par, hipStream_t s)
 {
-    kb_propagate<DYN, COST><<<g.n_prop, kPropBlock, g.lds, b->stream>>>(b->d_P, b->d_T, g.prop, par);
+    kb_propagate<DYN, COST><<<g.n_prop, kPropBlock, g.lds, s>>>(b->d_P, b->d_T, g.prop, par);
 }
 
-// Enqueues one iteration of every query on the batch stream, at state parity par.
+// Stream of group gi: the batch stream for the first, a side stream otherwise.
+hipStream_t group_stream(const kpx_batch* b, size_t gi) { return gi == 0 ? b->stream : b->side[gi - 1]; }
+
+// The side streams start after the work already on the batch stream ...
+void batch_fork(const kpx_batch* b)
+{
+    if (b->side.empty()) return;
+    (void)hipEventRecord(b->ev_fork, b->stream);
+    for (hipStream_t s : b->side) (void)hipStreamWaitEvent(s, b->ev_fork, 0);
+}
+
+// ... and the batch stream continues after theirs.
+void batch_join(const kpx_batch* b)
+{
+    for (size_t j = 0; j < b->side.size(); ++j) {
+        (void)hipEventRecord(b->ev_join[j], b->side[j]);
+        (void)hipStreamWaitEvent(b->stream, b->ev_join[j], 0);
+    }
+}
+
+// Enqueues one iteration of every query, at state parity par: the groups'
+// propagate and insert kernels run side by side, prune and select once.
 void batch_enqueue(const kpx_batch* b, int par)
 {
-    for (const auto& g : b->groups) {
+    batch_fork(b);
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const auto& g = b->groups[gi];
+        const hipStream_t s = group_stream(b, gi);
         switch (g.dyn * 2 + g.cost) {
-        case 0: kb_propagate_launch<kDI6, kTIME>(b, g, par); break;
-        case 1: kb_propagate_launch<kDI6, kPATH>(b, g, par); break;
-        case 2: kb_propagate_launch<kQUAD12, kTIME>(b, g, par); break;
-        case 3: kb_propagate_launch<kQUAD12, kPATH>(b, g, par); break;
-        case 4: kb_propagate_launch<kDUBINS6, kTIME>(b, g, par); break;
-        default: kb_propagate_launch<kDUBINS6, kPATH>(b, g, par); break;
+        case 0: kb_propagate_launch<kDI6, kTIME>(b, g, par, s); break;
+        case 1: kb_propagate_launch<kDI6, kPATH>(b, g, par, s); break;
+        case 2: kb_propagate_launch<kQUAD12, kTIME>(b, g, par, s); break;
+        case 3: kb_propagate_launch<kQUAD12, kPATH>(b, g, par, s); break;
+        case 4: kb_propagate_launch<kDUBINS6, kTIME>(b, g, par, s); break;
+        default: kb_propagate_launch<kDUBINS6, kPATH>(b, g, par, s); break;
         }
     }
+    batch_join(b);
     kb_prune_flags<<<b->n_prune, kBlock, 0, b->stream>>>(b->d_P, b->d_T, b->prune, par);
-    for (const auto& g : b->groups) {
+    batch_fork(b);
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const auto& g = b->groups[gi];
+        const hipStream_t s = group_stream(b, gi);
         switch (g.dyn) {
-        case kDI6: kb_insert<kDI6><<<g.n_ins, kBlock, 0, b->stream>>>(b->d_P, b->d_T, g.ins, par); break;
-        case kQUAD12: kb_insert<kQUAD12><<<g.n_ins, kBlock, 0, b->stream>>>(b->d_P, b->d_T, g.ins, par); break;
-        default: kb_insert<kDUBINS6><<<g.n_ins, kBlock, 0, b->stream>>>(b->d_P, b->d_T, g.ins, par); break;
+        case kDI6: kb_insert<kDI6><<<g.n_ins, kBlock, 0, s>>>(b->d_P, b->d_T, g.ins, par); break;
+        case kQUAD12: kb_insert<kQUAD12><<<g.n_ins, kBlock, 0, s>>>(b->d_P, b->d_T, g.ins, par); break;
+        default: kb_insert<kDUBINS6><<<g.n_ins, kBlock, 0, s>>>(b->d_P, b->d_T, g.ins, par); break;
         }
     }
+    batch_join(b);
     kb_finalize_select<<<b->n_fin, kBlock, 0, b->stream>>>(b->d_P, b->d_T, b->fin, par);
 }
 
@@ -2002,6 +2037,12 @@ void batch_free(kpx_batch* b)
     if (b->mem) (void)hipFree(b->mem);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    for (hipStream_t s : b->side) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t e : b->ev_join) (void)hipEventDestroy(e);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -2607,6 +2648,26 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
             batch_free(b);
             return rc;
         }
+    }
+    // one side stream (default priority) and join event per group after the first
+    if (b->groups.size() > 1 && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        b->ev_fork = nullptr;
+        batch_free(b);
+        return KPX_ERR_DEVICE;
+    }
+    for (size_t i = 1; i < b->groups.size(); ++i) {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            batch_free(b);
+            return KPX_ERR_DEVICE;
+        }
+        b->side.push_back(s);
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            batch_free(b);
+            return KPX_ERR_DEVICE;
+        }
+        b->ev_join.push_back(e);
     }
     size_t n4 = prune.size() + fin.size();
     for (size_t i = 0; i < b->groups.size(); ++i) n4 += prop[i].size() + ins[i].size();
