@@ -40,6 +40,16 @@ def test_status_strings(kpx):
     assert kpx.status_string(99) == "unknown status"
 
 
+def test_workspace_bytes_hold_the_refined_regions(kpx):
+    a = W.make_workload("quad12", 0)
+    b = W.make_workload("quad12", 0)
+    b.params.refine_max = 2
+    na = kpx.workspace_bytes(a.problem, a.params)
+    nb = kpx.workspace_bytes(b.problem, b.params)
+    # the region table (8 B), activity byte and block counts for 8x the regions
+    assert nb - na >= 7 * a.params.n_cells * 9
+
+
 def test_workspace_bytes_scale_with_capacity(kpx):
     a = W.make_workload("quad12", 0)
     b = W.make_workload("quad12", 0, tree_cap=1 << 22)
@@ -78,6 +88,11 @@ def test_invalid_arguments_are_rejected(kpx):
     def start_too_fast(w):
         w.problem.x_init[3] = 1.0  # on the bound, inside the clearance margin
     assert _bad(kpx, edit=start_too_fast) == ERR_START
+    assert _bad(kpx, edit=lambda w: setattr(w.params, "refine_max", 9)) == ERR_ARG
+    def refine_too_far(w):  # 256^3 regions refined 8x per axis exceed 2^30 regions
+        w.params.grid = (256, 256, 256)
+        w.params.refine_max = 8
+    assert _bad(kpx, edit=refine_too_far) == ERR_ARG
 
 
 def test_null_arguments(kpx):
@@ -91,6 +106,9 @@ def test_null_arguments(kpx):
     assert L.kpx_batch_set_graph(None, 1) == -1
     assert L.kpx_batch_iterate(None, 1) == -1
     assert L.kpx_batch_destroy(None) == 0
+    assert L.kpx_refine(None, 2) == -1
+    assert L.kpx_set_polish(None, None) == -1
+    assert L.kpx_set_timing_every(None, 1) == -1
 
 
 def test_diff_invalid_arguments_are_rejected(kpx):
