@@ -89,6 +89,9 @@ def parse():
                     help="iteration budget of each of those queries")
     ap.add_argument("--polish", type=int, default=0,
                     help="edge polish steps of every inserted node (quadrotor, TIME cost); 0 = plain")
+    ap.add_argument("--cost-first", action="store_true",
+                    help="propagate in the exact cost-first form (obstacle tests only for edges "
+                         "that can still be their region's minimum)")
     ap.add_argument("--refine-at", type=int, default=0,
                     help="solution runs: halve the region cells per axis after this many iterations")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -134,6 +137,8 @@ def main():
     planner = K.Planner(prob, prm, device="cuda:0")
     if a.polish:
         planner.set_polish(a.polish)
+    if a.cost_first:
+        planner.set_cost_first(True)
     print(f"[bench] {a.workload}: {prm.n_select} x {prm.samples_per_node} slots, "
           f"{prm.n_cells} regions, cap {prm.tree_cap}; warmup {a.warmup}", file=sys.stderr,
           flush=True)
@@ -177,7 +182,8 @@ def main():
             achieved = fl / avg_s / 1e12
             roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                        "traffic": measured_traffic(a.workload)}
+                        # the counters were taken on the plain form's kernel
+                        "traffic": None if a.cost_first else measured_traffic(a.workload)}
 
     # time to first solution and cost, from device timestamps of this query
     it_done = int(c1["iteration"])
@@ -208,7 +214,8 @@ def main():
                       if prm.samples_per_node else
                       f"every active node sharing {prm.n_select} expansion slots per iteration, ")
                    + f"{prm.n_cells} regions, cap {prm.tree_cap}"
-                   + (f", edge polish {a.polish} steps per inserted node" if a.polish else ""),
+                   + (f", edge polish {a.polish} steps per inserted node" if a.polish else "")
+                   + (", cost-first propagate" if a.cost_first else ""),
                    "seed": a.seed, "iterations_timed": done, "edges_timed": edges,
                    "substeps_timed": substeps, "cost": prob.cost},
         "roofline": roofline,
@@ -248,6 +255,8 @@ def solution_medians(K, W, a, polish=0, refine_at=0):
         p = K.Planner(w.problem, w.params)
         if polish:
             p.set_polish(polish)
+        if a.cost_first:
+            p.set_cost_first(True)
         if 0 < refine_at < a.solution_iters:
             import torch
 

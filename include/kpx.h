@@ -187,7 +187,8 @@ typedef struct kpx_dump_view {
     float* control;        /* KPX_MAX_CONTROL x capacity */
     int32_t* steps;
     float* state;          /* end state, KPX_MAX_STATE x capacity (valid slots) */
-    int32_t* first_invalid;/* 0 when valid, else the first invalid substep (1-based) */
+    int32_t* first_invalid;/* 0 when valid, else the first invalid substep (1-based);
+                            * -1: obstacle test skipped (kpx_set_cost_first) */
     int32_t* cell;         /* -1 when invalid */
     uint64_t* key;         /* (cost field << 32) | (n_tree + s); all ones when invalid */
     uint8_t* goal;
@@ -257,6 +258,20 @@ int kpx_set_dump(kpx_handle* h, int32_t enable);
  * slot count (n_select * K).  KPX_ERR_STATE when recording is off;
  * KPX_ERR_BUFFER when view->capacity < n_slots. */
 int kpx_read_dump(kpx_handle* h, kpx_dump_view* view, int64_t* n_slots);
+
+/* Propagate in the cost-first form of the App. A remark (enable = 1) or the
+ * plain form (0, the default) from the next iteration on.  The form is exact:
+ * an edge is integrated with the state and workspace bounds only, and its
+ * obstacle test is run (by integrating it again) only when its key
+ * (cost << 32 | index) is not above its region's entry in the table at that
+ * moment, so the tree, the table, the statuses and the solution are those of
+ * the plain form.  What differs is recorded per slot: an edge whose obstacle
+ * test was skipped has first_invalid -1 in kpx_read_dump and counts as
+ * invalid in n_valid; an edge that leaves the bounds after entering a box
+ * reports the bound's substep; kpx_iter_stats.substeps counts the substeps of
+ * both passes.  The batched form (kpx_batch_*) always propagates in the plain
+ * form.  KPX_ERR_ARG for enable outside 0..1. */
+int kpx_set_cost_first(kpx_handle* h, int32_t enable);
 
 /* Brackets the kernels of every following iteration with HIP events on the
  * handle's stream: bit k of kernel_mask (0..15) times kernel k (numbered as

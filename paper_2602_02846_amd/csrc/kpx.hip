@@ -261,7 +261,19 @@ __device__ __forceinline__ void stage_lds(const int4* s0, int4* d0, int n0, cons
 
 // One block's share of propagate: block `blk` of `nblk` working for the
 // problem P (state `st`).
-template <int DYN, int COST>
+//
+// CF selects the cost-first form of the App. A remark, which is exact: an
+// edge is first integrated with the state and workspace bounds only; its
+// region and key then follow from the end state, and when the region table
+// already holds a smaller key the edge cannot be the region's minimum (the
+// table only decreases during propagate, and a skipped edge that is valid
+// still lies above the final minimum), so its obstacle test is skipped
+// (first_invalid -1).  Otherwise the lane integrates the edge again from the
+// parent with the obstacle test, bit for bit as the plain form does.  The
+// table value is loaded when the first pass ends and compared after the next
+// trip, so that its latency hides under one RK4 step.
+constexpr short kSkipped = -1;
+template <int DYN, int COST, bool CF = false>
 __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtrs& T, DevState* st, int blk,
                                                int nblk)
 {
@@ -390,6 +402,9 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         float x[D], u[M];
         float len = 0.f;
         int li = -1, n = 0, k = 0;
+        int pjl = 0;                        // the lane's parent row
+        bool chk = !CF, pend = false;       // obstacle test on; table value in flight
+        unsigned long long ckey = 0, ctv = 0;
         int gcur = -1, gstart = 0, gcount = 0;
         float gclr = 0.f;
         // safe ball: no box is within sqrt(r2) of (rx, ry, rz), the last
@@ -421,6 +436,9 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                         len = 0.f;
                         gcur = -1;
                         r2 = -1.f;
+                        pjl = pj;
+                        chk = !CF;
+                        pend = false;
                     }
                 }
             }
@@ -428,9 +446,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             if (li >= 0) {
                 rk4<DYN, COST>(H, x, u, len);
                 ++k;
+                if constexpr (CF) ++my_steps;  // substeps actually integrated, both passes
                 bool ok = in_bounds<DYN>(H, x, s_os[0], s_os[1]);
                 const float dx = x[0] - rx, dy = x[1] - ry, dz = x[2] - rz;
-                if (ok && __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)) >= r2) {
+                if (ok && chk && __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)) >= r2) {
                     const int g = box_grid_cell(H, x);
                     if (g != gcur) {
                         const int2 e = sgc[g];
@@ -465,7 +484,36 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                     rz = x[2];
                     r2 = r * r * 0.99998f;
                 }
-                if (!ok || k == n) {
+                if constexpr (CF) {
+                    if (pend) {  // the region's key, loaded one trip ago
+                        pend = false;
+                        if (ckey > ctv) {
+                            s_fi[li] = kSkipped;
+                            li = -1;
+                        }
+                    }
+                    if (li >= 0 && !chk && ok && k == n) {
+                        // first pass within bounds: the edge's region and key
+                        const float pe[3] = {x[0], x[1], x[2]};
+                        const float ve[3] = {x[VI], x[VI + 1], x[VI + 2]};
+                        const int c = cell_of(P, pe, ve);
+                        uint32_t cf;
+                        if constexpr (COST == kTIME) cf = s_pcost[pjl] + (uint32_t)n;
+                        else cf = __float_as_uint(__uint_as_float(s_pcost[pjl]) + len);
+                        ckey = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)(n_tree + base + li);
+                        ctv = __hip_atomic_load(&T.tbl[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        pend = true;
+                        chk = true;
+#pragma unroll
+                        for (int q = 0; q < D; ++q)
+                            x[q] = spx[q * kParMax + pjl] * (rev_state(DYN, q) ? kInv2Pi : 1.f);
+                        k = 0;
+                        len = 0.f;
+                        gcur = -1;
+                        r2 = -1.f;
+                    }
+                }
+                if (li >= 0 && (!ok || k == n)) {
                     s_fi[li] = (short)(ok ? 0 : k);
                     if (ok) {
                         if constexpr (COST == kPATH) s_len[li] = len;
@@ -498,7 +546,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             const int fi = s_fi[lj];
             const int nn = s_n[lj];
             const int pj = s / K - r0;
-            my_steps += fi ? fi : nn;
+            if constexpr (!CF) my_steps += fi ? fi : nn;
             if (fi == 0) {
                 ++my_valid;
                 const float pe[3] = {s_xe[0][lj], s_xe[1][lj], s_xe[2][lj]};
@@ -549,10 +597,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     }
 }
 
-template <int DYN, int COST>
+template <int DYN, int COST, bool CF>
 __global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs T, DevState* st)
 {
-    propagate_body<DYN, COST>(P, T, st, blockIdx.x, gridDim.x);
+    propagate_body<DYN, COST, CF>(P, T, st, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ prune + survivor flags
@@ -1707,6 +1755,7 @@ struct kpx_handle {
     int refined = 1;                          // total refinement factor per axis so far
     int polish_steps = 0;                     // edge polish of inserted nodes (0: off)
     float polish_lr = 0.f;
+    bool cost_first = false;                  // propagate in the cost-first form
     kpxd::DiffConst polish_c{};
     std::string err;
 };
@@ -1809,8 +1858,11 @@ size_t propagate_lds_bytes(const Sizes& z, int d)
 template <int DYN, int COST>
 void launch_propagate(kpx_handle* h, const DevPtrs& T)
 {
-    k_propagate<DYN, COST><<<h->P.n_cu, kPropBlock, propagate_lds_bytes(h->z, Dims<DYN>::D), h->stream>>>(
-        h->P, T, cur_state(h));
+    const size_t lds = propagate_lds_bytes(h->z, Dims<DYN>::D);
+    if (h->cost_first)
+        k_propagate<DYN, COST, true><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
+    else
+        k_propagate<DYN, COST, false><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
 }
 
 // Allows `dynamic` bytes of dynamic LDS for a propagate kernel, after checking
@@ -1826,16 +1878,23 @@ int allow_lds(const void* kernel, size_t dynamic, int lds_max)
     return KPX_OK;
 }
 
-// The propagate kernel for a (model, cost) pair, single-query or batched.
-const void* propagate_kernel(int dyn, int cost, bool batched)
+// The propagate kernel for a (model, cost) pair: batched, or single-query in
+// the plain or the cost-first form.
+template <int DYN, int COST>
+const void* propagate_kernel_t(bool batched, bool cf)
+{
+    if (batched) return (const void*)kb_propagate<DYN, COST>;
+    return cf ? (const void*)k_propagate<DYN, COST, true> : (const void*)k_propagate<DYN, COST, false>;
+}
+const void* propagate_kernel(int dyn, int cost, bool batched, bool cf = false)
 {
     switch (dyn * 2 + cost) {
-    case 0: return batched ? (const void*)kb_propagate<kDI6, kTIME> : (const void*)k_propagate<kDI6, kTIME>;
-    case 1: return batched ? (const void*)kb_propagate<kDI6, kPATH> : (const void*)k_propagate<kDI6, kPATH>;
-    case 2: return batched ? (const void*)kb_propagate<kQUAD12, kTIME> : (const void*)k_propagate<kQUAD12, kTIME>;
-    case 3: return batched ? (const void*)kb_propagate<kQUAD12, kPATH> : (const void*)k_propagate<kQUAD12, kPATH>;
-    case 4: return batched ? (const void*)kb_propagate<kDUBINS6, kTIME> : (const void*)k_propagate<kDUBINS6, kTIME>;
-    default: return batched ? (const void*)kb_propagate<kDUBINS6, kPATH> : (const void*)k_propagate<kDUBINS6, kPATH>;
+    case 0: return propagate_kernel_t<kDI6, kTIME>(batched, cf);
+    case 1: return propagate_kernel_t<kDI6, kPATH>(batched, cf);
+    case 2: return propagate_kernel_t<kQUAD12, kTIME>(batched, cf);
+    case 3: return propagate_kernel_t<kQUAD12, kPATH>(batched, cf);
+    case 4: return propagate_kernel_t<kDUBINS6, kTIME>(batched, cf);
+    default: return propagate_kernel_t<kDUBINS6, kPATH>(batched, cf);
     }
 }
 
@@ -2094,7 +2153,10 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
             return KPX_ERR_DEVICE;
         }
         h->P.n_cu = std::max(1, n_cu);
-        const int rc = allow_lds(propagate_kernel(h->P.dyn, h->P.cost, false), propagate_lds_bytes(z, z.d), lds_max);
+        int rc = KPX_OK;
+        for (bool cf : {false, true})  // both forms, so that kpx_set_cost_first needs no device call
+            if (rc == KPX_OK)
+                rc = allow_lds(propagate_kernel(h->P.dyn, h->P.cost, false, cf), propagate_lds_bytes(z, z.d), lds_max);
         if (rc != KPX_OK) {
             delete h;
             return rc;
@@ -2469,6 +2531,13 @@ int kpx_set_timing(kpx_handle* h, int32_t kernel_mask)
     h->timed.clear();
     h->timing_mask = kernel_mask;
     h->timing_iter = 0;
+    return KPX_OK;
+}
+
+int kpx_set_cost_first(kpx_handle* h, int32_t enable)
+{
+    if (!h || (enable != 0 && enable != 1)) return KPX_ERR_ARG;
+    h->cost_first = enable == 1;
     return KPX_OK;
 }
 

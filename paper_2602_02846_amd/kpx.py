@@ -130,6 +130,7 @@ def lib():
         L.kpx_read_dump.argtypes = [_vp, C.POINTER(DumpViewC), C.POINTER(i64)]
         L.kpx_set_timing.argtypes = [_vp, i32]
         L.kpx_set_timing_every.argtypes = [_vp, i32]
+        L.kpx_set_cost_first.argtypes = [_vp, i32]
         L.kpx_set_polish.argtypes = [_vp, C.POINTER(PolishC)]
         L.kpx_refine.argtypes = [_vp, i32]
         L.kpx_read_timing.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(i64)]
@@ -153,7 +154,8 @@ def lib():
                      "kpx_read_dump", "kpx_set_timing", "kpx_read_timing", "kpx_stats_capacity",
                      "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy",
                      "kpx_batch_create", "kpx_batch_set_graph", "kpx_batch_iterate",
-                     "kpx_batch_destroy", "kpx_set_polish", "kpx_refine", "kpx_set_timing_every"):
+                     "kpx_batch_destroy", "kpx_set_polish", "kpx_refine", "kpx_set_timing_every",
+                     "kpx_set_cost_first"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -384,6 +386,11 @@ class Planner:
         self._check(lib().kpx_refine(self.h, int(factor)))
         self.grid = tuple(int(g) * int(factor) for g in self.grid)
         self.n_cells *= int(factor) ** 3
+
+    def set_cost_first(self, enable: bool = True):
+        """Propagates in the exact cost-first form (obstacle tests only for
+        edges that can still be their region's minimum) or the plain form."""
+        self._check(lib().kpx_set_cost_first(self.h, 1 if enable else 0))
 
     def set_timing(self, enable=True, every: int = 1):
         """True times all four kernels, False none; an int is the kernel bit

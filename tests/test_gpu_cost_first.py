@@ -1,0 +1,159 @@
+"""The cost-first form of propagate (kpx_set_cost_first, the App. A remark)
+through the C ABI.  It is exact, so a cost-first planner and a plain one run
+side by side must hold the same tree, region table, statuses, cursor and
+solution after every iteration, and the plain one is replayed in the float64
+oracle at the same time.  Slot by slot the two dumps may differ only where
+the form allows: a skipped obstacle test (first_invalid -1) on a slot that is
+no survivor and, if valid, lies above its region's final key; an invalid
+edge's first bad substep found later (the bound after a box)."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+from oracle import parity
+
+pytestmark = pytest.mark.gpu
+
+# (workload, cost, overrides, iterations)
+CASES = {
+    "di6_time": ("di6", "TIME", dict(n_select=300, samples=9, tree_cap=1 << 16), 14),
+    "di6_path": ("di6", "PATH_LENGTH", dict(n_select=300, samples=9, tree_cap=1 << 16), 14),
+    "quad12_time": ("quad12", "TIME", dict(n_select=260, samples=9, tree_cap=1 << 16, grid=(6, 6, 6)), 14),
+    "dubins6_path": ("dubins6", "PATH_LENGTH", dict(n_select=200, samples=7, tree_cap=1 << 16,
+                                                    grid=(12, 12, 6)), 14),
+}
+
+SAME_COUNTERS = ("n_tree", "iteration", "cursor", "full", "solution_key", "first_solution_iteration",
+                 "n_select", "samples_per_node", "n_survivors")
+
+
+@pytest.fixture(scope="module")
+def kpx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_02846_amd as K
+
+    K.lib()
+    return K
+
+
+def _workload(name, cost, kw, seed=3):
+    w = W.make_workload(name, seed, **kw)
+    if w.problem.cost != cost:
+        w = dataclasses.replace(w, problem=dataclasses.replace(w.problem, cost=cost))
+    return w
+
+
+def _same_tree(a, b):
+    for k in ("state", "control", "steps", "parent", "cost", "cell", "status", "icount", "cell_table"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    for k in SAME_COUNTERS:
+        assert a["counters"][k] == b["counters"][k], k
+
+
+def _check_slots(da, db, post):
+    """da: plain dump, db: cost-first dump of the same iteration; post: the
+    tree after it."""
+    assert da["n_slots"] == db["n_slots"]
+    for k in ("parent", "steps", "control", "survivor"):
+        np.testing.assert_array_equal(da[k], db[k], err_msg=k)
+    fa, fb = da["first_invalid"], db["first_invalid"]
+    skipped = fb == -1
+    tested = ~skipped
+    # a tested edge has the plain form's validity, and when valid its record
+    np.testing.assert_array_equal(fa[tested] == 0, fb[tested] == 0)
+    both = tested & (fa == 0)
+    for k in ("cell", "key", "goal"):
+        np.testing.assert_array_equal(da[k][both], db[k][both], err_msg=k)
+    np.testing.assert_array_equal(da["state"][:, both], db["state"][:, both])
+    # an invalid edge: the same first bad substep, or a later one (a bound
+    # found after the box the plain form stopped at)
+    bad = tested & (fa != 0)
+    assert np.all(fb[bad] >= fa[bad])
+    # a skipped edge never survives; when valid it lies above its region's key
+    assert not np.any(da["survivor"][skipped])
+    sv = skipped & (fa == 0)
+    tbl = post["cell_table"]
+    assert np.all(da["key"][sv] > tbl[da["cell"][sv]])
+    assert np.all(db["key"][skipped] == parity.EMPTY) and np.all(db["cell"][skipped] == -1)
+    return int(skipped.sum()), int(sv.sum()), int(both.sum())
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_cost_first_matches_plain_and_oracle(kpx, ora, case):
+    name, cost, kw, iters = CASES[case]
+    w = _workload(name, cost, kw)
+    P = ora.Problem(w.problem, w.params)
+    a = kpx.Planner(w.problem, w.params)
+    b = kpx.Planner(w.problem, w.params)
+    b.set_cost_first(True)
+    a.set_dump(True)
+    b.set_dump(True)
+    rep = parity.new_report()
+    skipped = skipped_valid = tested_valid = 0
+    for _ in range(iters):
+        pre = a.snapshot()
+        if pre["counters"]["full"]:
+            break
+        a.iterate(1)
+        b.iterate(1)
+        da, db = a.read_dump(), b.read_dump()
+        pa, pb = a.snapshot(), b.snapshot()
+        tr = parity.oracle_tree_from_snapshot(ora, P, pre)
+        rep["n_tree_before"] = tr.n_tree
+        assert tr.step(parity.hints_from_dump(da)) == ora.OK
+        parity.compare_candidates(P, tr, da, rep)
+        parity.compare_trees(P, tr, pa, rep)
+        _same_tree(pa, pb)
+        s, sv, tv = _check_slots(da, db, pa)
+        skipped += s
+        skipped_valid += sv
+        tested_valid += tv
+        rep["iterations"] += 1
+    print(case, rep, dict(skipped=skipped, skipped_valid=skipped_valid, tested_valid=tested_valid))
+    assert rep["iterations"] == iters
+    # the comparison means something: edges were skipped, valid ones among them
+    assert skipped > 0 and skipped_valid > 0 and tested_valid > 0
+    a.close()
+    b.close()
+
+
+def test_cost_first_switches_between_iterations(kpx):
+    """Switching the form on and off between iterations keeps the tree."""
+    name, cost, kw, _ = CASES["quad12_time"]
+    w = _workload(name, cost, kw, seed=11)
+    a = kpx.Planner(w.problem, w.params)
+    b = kpx.Planner(w.problem, w.params)
+    for i in range(12):
+        b.set_cost_first(i % 3 != 1)
+        a.iterate(1)
+        b.iterate(1)
+    _same_tree(a.snapshot(), b.snapshot())
+    with pytest.raises(kpx.KPXError):
+        b._check(kpx.lib().kpx_set_cost_first(b.h, 2))
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("name", ["quad12", "dubins6"])
+def test_cost_first_full_size_same_tree(kpx, name):
+    """At the full workload size, in the launch configuration the benchmark
+    times: the same tree and solution after 40 iterations."""
+    w = W.make_workload(name, 0)
+    a = kpx.Planner(w.problem, w.params)
+    b = kpx.Planner(w.problem, w.params)
+    b.set_cost_first(True)
+    a.iterate(40)
+    b.iterate(40)
+    sa, sb = a.snapshot(), b.snapshot()
+    _same_tree(sa, sb)
+    assert sa["counters"]["n_tree"] > 1000
+    print(name, sa["counters"]["n_tree"], sa["counters"]["solution_key"], b.stats(39, 1))
+    a.close()
+    b.close()
