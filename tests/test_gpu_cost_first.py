@@ -23,6 +23,8 @@ CASES = {
     "di6_time": ("di6", "TIME", dict(n_select=300, samples=9, tree_cap=1 << 16), 14),
     "di6_path": ("di6", "PATH_LENGTH", dict(n_select=300, samples=9, tree_cap=1 << 16), 14),
     "quad12_time": ("quad12", "TIME", dict(n_select=260, samples=9, tree_cap=1 << 16, grid=(6, 6, 6)), 14),
+    # the uncapped form: every active node shares the buffer
+    "quad12_uncapped": ("quad12", "TIME", dict(n_select=1100, samples=0, tree_cap=1 << 15, grid=(8, 8, 8)), 14),
     "dubins6_path": ("dubins6", "PATH_LENGTH", dict(n_select=200, samples=7, tree_cap=1 << 16,
                                                     grid=(12, 12, 6)), 14),
 }
@@ -120,6 +122,25 @@ def test_cost_first_matches_plain_and_oracle(kpx, ora, case):
     assert rep["iterations"] == iters
     # the comparison means something: edges were skipped, valid ones among them
     assert skipped > 0 and skipped_valid > 0 and tested_valid > 0
+    a.close()
+    b.close()
+
+
+def test_cost_first_across_a_refinement(kpx):
+    """The cost-first form reads the region table that a refinement rebuilt."""
+    name, cost, kw, _ = CASES["quad12_time"]
+    w = _workload(name, cost, dict(kw, grid=(4, 4, 4)), seed=8)
+    w.params.refine_max = 2
+    a = kpx.Planner(w.problem, w.params)
+    b = kpx.Planner(w.problem, w.params)
+    b.set_cost_first(True)
+    for pl in (a, b):
+        pl.iterate(8)
+        pl.refine(2)
+        pl.iterate(8)
+    sa = a.snapshot()
+    _same_tree(sa, b.snapshot())
+    assert sa["counters"]["n_tree"] > 50
     a.close()
     b.close()
 
