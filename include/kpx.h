@@ -362,8 +362,8 @@ typedef struct kpx_batch kpx_batch;
 
 /* Groups n host-array handles (not copied; the caller keeps them alive and
  * destroys them after the batch).  They must be distinct, share one stream,
- * have run the same number of iterations modulo 2, have candidate recording
- * and edge polish off, and have at most 262144 regions each.  KPX_ERR_ARG otherwise;
+ * have run the same number of iterations modulo 2, and have candidate
+ * recording and edge polish off.  KPX_ERR_ARG otherwise;
  * KPX_ERR_OOM / KPX_ERR_DEVICE on allocation or runtime failure. */
 int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out);
 

@@ -42,7 +42,9 @@ constexpr int kTile = kBlock;             // survivor slots per tile (one per th
 constexpr int kSelectThreads = 1024;
 constexpr int kSelWords = 8;            // activity words per select thread kept in registers
 constexpr int kSelLds = 8192;            // selections ranked in LDS (more go through global memory)
-constexpr int kSelBlocksMax = 1024;      // region blocks the many-block selection handles
+constexpr int kGroup = 1024;             // tiles, or region blocks, per group of the two-level scans
+constexpr int kDirect = 8 * kGroup;      // at most this many counts are summed in one level
+constexpr int kGroupPad = 32;            // ints per group sum: one 128-byte line each
 constexpr int kSortBins = 64;             // step-count bins of the in-block sort
 constexpr int kBoxGridMax = 16;           // box-grid cells per workspace axis (at most)
 constexpr int kBoxGridBytes = 48 * 1024;  // LDS budget of the box grid, its clearances and lists
@@ -101,6 +103,8 @@ struct DevPtrs {
     DevState* st;        // two states, by iteration parity: the current one is read by every
                          // kernel of an iteration and the close of the iteration writes the other
     int2* bcount;        // per block of kBlock regions: active regions at / after the cursor, before it
+    int2* bgroup;        // 2 x n_bgroups lines, by iteration parity: bcount summed over kGroup region blocks
+    int* tgroup;         // 2 x n_tgroups lines, by iteration parity: tile_count summed over kGroup tiles
     kpx_iter_stats* stats;
     int* d_parent;       // dump (may be null)
     float* d_u;
@@ -121,6 +125,25 @@ __device__ __forceinline__ int wave_sum(int v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
+}
+
+// Two-level scans.  Per-tile survivor counts and per-region-block activity
+// counts are prefix-summed by each consumer block over the counts before it.
+// Up to kDirect counts that is done in one level.  Beyond, the counts form
+// groups of kGroup: the producer blocks add their count to their group's sum
+// (one atomic per block, each group on a line of its own) and a consumer sums
+// the counts of its group before it plus the earlier groups' sums.  The sums
+// are kept per iteration parity; each close clears the other parity's.
+__host__ __device__ constexpr bool grouped(int n_groups) { return n_groups > kDirect / kGroup; }
+
+__device__ __forceinline__ int* tgroup_at(const DevPtrs& T, const DevProblem& P, int par, int g)
+{
+    return T.tgroup + ((size_t)par * P.n_tgroups + g) * kGroupPad;
+}
+
+__device__ __forceinline__ int2* bgroup_at(const DevPtrs& T, const DevProblem& P, int par, int g)
+{
+    return T.bgroup + ((size_t)par * P.n_bgroups + g) * (kGroupPad / 2);
 }
 
 // ------------------------------------------------------------------ init
@@ -682,6 +705,11 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
                 tl += s_w2[w];
             }
             T.bcount[blk] = make_int2(th, tl);
+            if (grouped(P.n_bgroups)) {
+                int2* g = bgroup_at(T, P, (int)(st - T.st), blk / kGroup);
+                if (th) atomicAdd(&g->x, th);
+                if (tl) atomicAdd(&g->y, tl);
+            }
         }
         return;
     }
@@ -708,6 +736,7 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) total += s_w[w];
         T.tile_count[tile] = total;
+        if (grouped(P.n_tgroups) && total) atomicAdd(tgroup_at(T, P, (int)(st - T.st), tile / kGroup), total);
     }
 }
 
@@ -717,28 +746,28 @@ __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T,
     prune_flags_body(P, T, st, blockIdx.x, n_prune_blocks);
 }
 
-// Exclusive scan of three ints per thread over the block, with the totals.
+// Exclusive scan of two ints per thread over the block, with the totals.
 // One barrier: each thread then sums the wave totals below its own wave.
-// `s_w` holds 3 x 16 ints (at most 1024 threads).
-__device__ __forceinline__ void block_scan3(int (&v)[3], int (&ex)[3], int (&tot)[3], int (*s_w)[16])
+// `s_w` holds 2 x 16 ints (at most 1024 threads).
+__device__ __forceinline__ void block_scan2(int (&v)[2], int (&ex)[2], int (&tot)[2], int (*s_w)[16])
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int inc[3] = {v[0], v[1], v[2]};
+    int inc[2] = {v[0], v[1]};
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 2; ++k) {
             const int y = __shfl_up(inc[k], o);
             if (lane >= o) inc[k] += y;
         }
     }
     if (lane == 63) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s_w[k][wid] = inc[k];
+        for (int k = 0; k < 2; ++k) s_w[k][wid] = inc[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 2; ++k) {
         int below = 0, all = 0;
         for (int w = 0; w < nw; ++w) {
             const int t = s_w[k][w];
@@ -750,17 +779,15 @@ __device__ __forceinline__ void block_scan3(int (&v)[3], int (&ex)[3], int (&tot
     }
 }
 
-// Closes an iteration (counters, statistics, capacity check) and selects the
-// next iteration's nodes: regions whose owner is active, in region order
-// rotated to start at the cursor, at most n_select.  One block; each thread
-// owns a run of whole 4-region words of the activity bytes (0/1, zero-padded
-// past the last region).  The survivor count and the two cursor-split counts
-// of active regions share one block scan.
-__device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, const DevState* in, DevState& q,
-                                    bool finalize, int (*s_w)[16], int* s_sel, DevState* out)
+// Selects the nodes of the pending iteration (after create, and again after
+// a refinement): regions whose owner is active, in region order rotated to
+// start at the cursor, at most n_select.  One block; each thread owns a run of
+// whole 4-region words of the activity bytes (0/1, zero-padded past the last
+// region).  The two cursor-split counts of active regions share one block scan.
+__device__ void select_one_block(const DevProblem& P, const DevPtrs& T, DevState* st, DevState& q,
+                                 int (*s_w)[16], int* s_sel)
 {
     // every load of the block is in flight before the first barrier
-    const int t0 = T.tile_count[min((int)threadIdx.x, P.n_tiles - 1)];
     const int nwords = (P.n_cells + 3) >> 2;
     const int per = (nwords + (int)blockDim.x - 1) / (int)blockDim.x;
     const int w0 = min((int)threadIdx.x * per, nwords);
@@ -769,30 +796,19 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, const
     uint32_t wd[kSelWords];
 #pragma unroll
     for (int i = 0; i < kSelWords; ++i) wd[i] = act[min(w0 + i, nwords - 1)];
-    if (threadIdx.x == 0) q = *in;
+    if (threadIdx.x == 0) q = *st;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSelWords; ++i) wd[i] = w0 + i < w1 ? wd[i] & 0x01010101u : 0u;
     const bool in_regs = per <= kSelWords;
-    // what the block needs of the state, read before thread 0 updates it
-    const bool was_full = q.full != 0;
-    const long long n_tree0 = q.n_tree;
-    finalize = finalize && !was_full;
-    // the cursor this selection starts from (closing the iteration moves it)
-    const int cur = finalize ? q.cursor_next : q.cursor;
-    const int k_cur = q.k;
-    const int S = q.n_sel * k_cur;
-    const int tiles = (S + kTile - 1) / kTile;
-    int v[3] = {0, 0, 0};  // survivors of my tiles; active regions at / after the cursor; before it
-    if (finalize) {
-        v[0] = (int)threadIdx.x < tiles ? t0 : 0;
-        for (int j = threadIdx.x + blockDim.x; j < tiles; j += blockDim.x) v[0] += T.tile_count[j];
-    }
+    const bool full = q.full != 0;
+    const int cur = q.cursor;
+    int v[2] = {0, 0};  // active regions at / after the cursor; before it
     auto count = [&](uint32_t w, int c0) {
         const int k = min(max(cur - c0, 0), 4);  // bytes of this word before the cursor
         const uint32_t below = k == 4 ? ~0u : (1u << (8 * k)) - 1u;
-        v[2] += __popc(w & below);
-        v[1] += __popc(w & ~below);
+        v[1] += __popc(w & below);
+        v[0] += __popc(w & ~below);
     };
     if (in_regs) {
 #pragma unroll
@@ -800,40 +816,11 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, const
     } else {
         for (int w = w0; w < w1; ++w) count(act[w] & 0x01010101u, 4 * w);
     }
-    int ex[3], tot[3];
-    block_scan3(v, ex, tot, s_w);
-    if (finalize && threadIdx.x == 0) {
-        const int n_surv = tot[0];
-        const long long it = q.it;
-        const long long n_tree = q.n_tree + n_surv;
-        kpx_iter_stats* r = &T.stats[it & (kStatsCap - 1)];
-        r->iteration = it;
-        r->n_tree = n_tree;
-        r->n_select = q.n_sel;
-        r->n_valid = q.n_valid_acc;
-        r->n_survivors = n_surv;
-        r->samples_per_node = k_cur;
-        r->substeps = (long long)q.substeps_acc;
-        r->solution_key = q.sol;
-        r->t_end = wall_clock64();
-        q.last_n_sel = q.n_sel;
-        q.last_k = k_cur;
-        q.last_n_valid = q.n_valid_acc;
-        q.last_n_surv = n_surv;
-        q.last_substeps = (long long)q.substeps_acc;
-        q.n_valid_acc = 0;
-        q.substeps_acc = 0;
-        if (q.sol != kEmpty && q.first_sol_it < 0) q.first_sol_it = it;
-        q.it = it + 1;
-        q.n_tree = n_tree;
-        q.cursor = cur;
-        q.full = (n_tree + P.surv_max > P.cap) ? 1 : 0;
-    }
-    // the capacity check, from the totals every thread holds
-    const bool full = was_full || (finalize && n_tree0 + tot[0] + P.surv_max > P.cap);
-    const int nsel = full ? 0 : min(tot[1] + tot[2], P.n_select);
+    int ex[2], tot[2];
+    block_scan2(v, ex, tot, s_w);
+    const int nsel = full ? 0 : min(tot[0] + tot[1], P.n_select);
     // ranks: regions at or after the cursor first, then those before it
-    int r_hi = ex[1], r_lo = tot[1] + ex[2];
+    int r_hi = ex[0], r_lo = tot[0] + ex[1];
     auto rank = [&](uint32_t w, int c0) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -881,17 +868,16 @@ __device__ void finalize_and_select(const DevProblem& P, const DevPtrs& T, const
         q.k = samples_for(P, nsel);
         if (nsel == 0 && !full) q.cursor_next = cur;
         q.n_surv = 0;
-        *out = q;
+        *st = q;
     }
 }
 
-// Selection alone (after create).
 __global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs T, DevState* st)
 {
-    __shared__ int s_w[3][16];
+    __shared__ int s_w[2][16];
     __shared__ int s_sel[kSelLds];
     __shared__ DevState s_st;
-    finalize_and_select(P, T, st, s_st, false, s_w, s_sel, st);
+    select_one_block(P, T, st, s_st, s_w, s_sel);
 }
 
 // ------------------------------------------------------------------ insert
@@ -908,10 +894,14 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     const int tile = blk;
     const int s = tile * kTile + threadIdx.x;
     const int sc = min(s, P.s_max - 1);
+    // survivors before this tile: the earlier tiles (of its group, when the
+    // counts are grouped), four per thread first
+    const bool grp = grouped(P.n_tgroups);
+    const int g0 = grp ? tile / kGroup * kGroup : 0;
     int pre = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int j = threadIdx.x + u * kBlock;
+    for (int u = 0; u < kGroup / kBlock; ++u) {
+        const int j = g0 + threadIdx.x + u * kBlock;
         const int v = T.tile_count[min(j, max(tile - 1, 0))];
         pre += j < tile ? v : 0;
     }
@@ -927,7 +917,9 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     if (full) return;  // kernel-uniform: nothing happens in a full tree
     const int S = n_sel * K;
     if (tile * kTile >= S) return;  // block-uniform
-    for (int j = threadIdx.x + 4 * kBlock; j < tile; j += kBlock) pre += T.tile_count[j];
+    for (int j = g0 + threadIdx.x + kGroup; j < tile; j += kBlock) pre += T.tile_count[j];
+    if (grp)  // the earlier groups
+        for (int j = threadIdx.x; j < tile / kGroup; j += kBlock) pre += *tgroup_at(T, P, (int)(st - T.st), j);
     const int f = s < S ? f0 : 0;
     // rank = survivors of the earlier tiles + those before this slot in its tile
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1078,24 +1070,15 @@ __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T
         atomicMin(&st->sol, ((unsigned long long)T.cost[i] << 32) | (unsigned long long)(uint32_t)i);
 }
 
-// Closes the iteration and selects the next iteration's nodes in one block
-// (regions in more blocks than the many-block kernel below handles).
-__global__ __launch_bounds__(kSelectThreads) void k_finalize_select_one(DevProblem P, DevPtrs T, const DevState* st,
-                                                                       DevState* st_next)
-{
-    __shared__ int s_w[3][16];
-    __shared__ int s_sel[kSelLds];
-    __shared__ DevState s_st;
-    finalize_and_select(P, T, st, s_st, true, s_w, s_sel, st_next);
-}
-
 // Closes the iteration and selects the next iteration's nodes with one block
 // per kBlock regions (the prune kernel's blocks, whose counts of active
 // regions on either side of the cursor give each block the ranks of its own
-// regions; ballots rank them within the block).  It reads this iteration's
-// state and writes the next one, so no block sees another's update; block 0
-// writes everything but the cursor past the last selected region, which the
-// thread holding that rank writes.
+// regions; ballots rank them within the block), the block offsets by the
+// two-level scan.  It reads this iteration's state and writes the next one,
+// so no block sees another's update; block 0 writes everything but the cursor
+// past the last selected region, which the thread holding that rank writes.
+// The group sums of the other parity, which the next iteration's prune adds
+// to, are cleared here.
 __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const DevPtrs& T, const DevState* st,
                                                      DevState* st_next, int blk, int nb)
 {
@@ -1107,28 +1090,55 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
     const int cc = min(c, P.n_cells - 1);
     const uint8_t act = T.act[cc];
     const uint32_t own = reinterpret_cast<const uint32_t*>(T.tbl)[2 * (size_t)cc];
-    int2 bc[kSelBlocksMax / kBlock];
+    // the block counts summed here: every block's (for the totals too) in one
+    // level, or those of this block's group before it when grouped
+    const bool grp = grouped(P.n_bgroups);
+    const int par = (int)(st - T.st);
+    const int g0 = grp ? b / kGroup * kGroup : 0, jend = grp ? b : nb;
+    int2 bc[kGroup / kBlock];
 #pragma unroll
-    for (int k = 0; k < kSelBlocksMax / kBlock; ++k)
-        bc[k] = T.bcount[min((int)threadIdx.x + k * kBlock, nb - 1)];
+    for (int k = 0; k < kGroup / kBlock; ++k)
+        bc[k] = T.bcount[min(g0 + (int)threadIdx.x + k * kBlock, max(jend - 1, 0))];
     const int was_full = st->full, n_sel = st->n_sel, n_surv0 = st->n_surv, cur = st->cursor_next;
     const int k_cur = st->k;
     const long long n_tree = st->n_tree;
     // active regions at / after the cursor and before it: in the blocks before
     // this one, and in all
     int v[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < kSelBlocksMax / kBlock; ++k) {
-        const int j = threadIdx.x + k * kBlock;
-        if (j < nb) {
-            v[2] += bc[k].x;
-            v[3] += bc[k].y;
+    auto add = [&](int j, int2 t) {
+        if (j < jend) {
+            if (!grp) {
+                v[2] += t.x;
+                v[3] += t.y;
+            }
             if (j < b) {
-                v[0] += bc[k].x;
-                v[1] += bc[k].y;
+                v[0] += t.x;
+                v[1] += t.y;
+            }
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < kGroup / kBlock; ++k) add(g0 + (int)threadIdx.x + k * kBlock, bc[k]);
+    for (int j = g0 + (int)threadIdx.x + kGroup; j < jend; j += kBlock) add(j, T.bcount[j]);
+    if (grp) {  // the group sums: all of them for the totals, the earlier ones for the offsets
+        const int g = b / kGroup, ng = (nb + kGroup - 1) / kGroup;
+        for (int j = threadIdx.x; j < ng; j += kBlock) {
+            const int2 t = *bgroup_at(T, P, par, j);
+            v[2] += t.x;
+            v[3] += t.y;
+            if (j < g) {
+                v[0] += t.x;
+                v[1] += t.y;
             }
         }
     }
+    // the other parity's group sums start the next iteration at zero
+    if (grouped(P.n_bgroups))
+        for (int j = b * kBlock + (int)threadIdx.x; j < P.n_bgroups; j += nb * kBlock)
+            *bgroup_at(T, P, par ^ 1, j) = make_int2(0, 0);
+    if (grouped(P.n_tgroups))
+        for (int j = b * kBlock + (int)threadIdx.x; j < P.n_tgroups; j += nb * kBlock)
+            *tgroup_at(T, P, par ^ 1, j) = 0;
     const bool a = c < P.n_cells && act != 0;
     const bool h = c >= cur;
     const unsigned long long mh = __ballot(a && h), ml = __ballot(a && !h);
@@ -1262,6 +1272,8 @@ __device__ __forceinline__ DevPtrs global_ptrs(const DevPtrs& src)
     T.glist = as_global(T.glist);
     T.st = as_global(T.st);
     T.bcount = as_global(T.bcount);
+    T.bgroup = as_global(T.bgroup);
+    T.tgroup = as_global(T.tgroup);
     T.stats = as_global(T.stats);
     T.d_parent = as_global(T.d_parent);
     T.d_u = as_global(T.d_u);
@@ -1372,6 +1384,8 @@ struct Sizes {
     long long cap;
     int n_cells, s_max, n_tiles, n_boxes;
     int n_cells_cap;      // regions the arrays hold: n_cells * refine_max^3
+    int n_bgroups;        // groups of kGroup region blocks (of the n_cells_cap regions)
+    int n_tgroups;        // groups of kGroup tiles
     int n_act;            // activity bytes, padded to whole words
     int gb_n[3];          // box grid cells per axis
     int gb_entries;       // total list entries of the box grid
@@ -1406,6 +1420,8 @@ void for_each_array(const Sizes& z, F&& f)
     f("glist", sizeof(uint16_t) * (size_t)(z.gb_entries > 0 ? z.gb_entries : 1));
     f("st", 2 * sizeof(DevState));  // double-buffered by iteration parity
     f("bcount", sizeof(int2) * (size_t)((z.n_cells_cap + kBlock - 1) / kBlock));
+    f("bgroup", sizeof(int) * kGroupPad * 2 * (size_t)z.n_bgroups);
+    f("tgroup", sizeof(int) * kGroupPad * 2 * (size_t)z.n_tgroups);
     f("stats", sizeof(kpx_iter_stats) * kStatsCap);
     f("d_parent", sizeof(int) * S);
     f("d_u", sizeof(float) * z.m * S);
@@ -1597,6 +1613,8 @@ int validate(const kpx_problem* p, const kpx_params* q, Sizes* z, std::string* w
         z->n_cells_cap = (int)nc_cap;
         z->s_max = (int)S;
         z->n_tiles = (int)((S + kTile - 1) / kTile);
+        z->n_bgroups = (int)(((nc_cap + kBlock - 1) / kBlock + kGroup - 1) / kGroup);
+        z->n_tgroups = (z->n_tiles + kGroup - 1) / kGroup;
         z->n_boxes = p->n_boxes;
         z->n_act = (int)((nc_cap + 4095) & ~4095ll);
         BoxGrid g;
@@ -1706,6 +1724,8 @@ DevProblem make_dev_problem(const kpx_problem* p, const kpx_params* q, const Siz
     P.seed_hi = (uint32_t)(q->seed >> 32);
     P.query = q->query_id;
     P.n_tiles = z.n_tiles;
+    P.n_bgroups = z.n_bgroups;
+    P.n_tgroups = z.n_tgroups;
     return P;
 }
 
@@ -1781,7 +1801,7 @@ void carve(kpx_handle* h)
     size_t o = 0;
     DevPtrs& T = h->T;
     std::memset(&T, 0, sizeof(T));
-    void* ptrs[40];
+    void* ptrs[48];
     int k = 0;
     for_each_array(h->z, [&](const char*, size_t bytes) {
         ptrs[k++] = b + o;
@@ -1812,6 +1832,8 @@ void carve(kpx_handle* h)
     T.glist = (uint16_t*)ptrs[k++];
     T.st = (DevState*)ptrs[k++];
     T.bcount = (int2*)ptrs[k++];
+    T.bgroup = (int2*)ptrs[k++];
+    T.tgroup = (int*)ptrs[k++];
     T.stats = (kpx_iter_stats*)ptrs[k++];
     T.d_parent = (int*)ptrs[k++];
     T.d_u = (float*)ptrs[k++];
@@ -2204,6 +2226,11 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
         hipMemcpyAsync(h->T.glist, grid.list.data(), sizeof(uint16_t) * grid.list.size(),
                        hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return cleanup(KPX_ERR_DEVICE);
+    // the group sums of both parities start at zero (each close clears the
+    // other parity's for the next iteration)
+    if (hipMemsetAsync(h->T.bgroup, 0, sizeof(int) * kGroupPad * 2 * (size_t)z.n_bgroups, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->T.tgroup, 0, sizeof(int) * kGroupPad * 2 * (size_t)z.n_tgroups, h->stream) != hipSuccess)
+        return cleanup(KPX_ERR_DEVICE);
     float* xi = h->T.x_init;
     if (hipMemcpyAsync(xi, prob->x_init, sizeof(float) * KPX_MAX_STATE, hipMemcpyHostToDevice,
                        h->stream) != hipSuccess)
@@ -2241,12 +2268,8 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
                        polish_lds_bytes(h->P.n_boxes), h->stream>>>(h->P, T, cur_state(h), h->polish_c,
                                                                      h->polish_steps, h->polish_lr);
         if ((rc = timed_launch(h, 3, [&] {
-                 if (h->n_prune_blocks <= kSelBlocksMax)
-                     k_finalize_select<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
-                         h->P, T, cur_state(h), next_state(h), h->n_prune_blocks);
-                 else
-                     k_finalize_select_one<<<1, kSelectThreads, 0, h->stream>>>(h->P, T, cur_state(h),
-                                                                                next_state(h));
+                 k_finalize_select<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
+                     h->P, T, cur_state(h), next_state(h), h->n_prune_blocks);
              })) != KPX_OK)
             return rc;
         h->cur ^= 1;  // the state the close of this iteration wrote is current
@@ -2664,7 +2687,7 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
     for (int q = 0; q < n; ++q) {
         const kpx_handle* h = handles[q];
         if (!h || h->stream != handles[0]->stream || h->cur != handles[0]->cur || h->dump_on ||
-            h->n_prune_blocks > kSelBlocksMax || h->polish_steps > 0)
+            h->polish_steps > 0)
             return KPX_ERR_ARG;
         for (int r = 0; r < q; ++r)
             if (handles[r] == h) return KPX_ERR_ARG;

@@ -92,6 +92,7 @@ struct DevProblem {
     long long cap;
     uint32_t seed_lo, seed_hi, query;
     int n_tiles;                   // survivor-count tiles covering s_max slots
+    int n_bgroups, n_tgroups;      // group sums per parity: region blocks, tiles (two-level scans)
     int sort_shift;                // step-count sort: bin = (n - steps_min) >> sort_shift
 };
 

@@ -59,6 +59,30 @@ def test_batch_matches_each_query_alone(kpx):
         p.close()
 
 
+def test_batch_with_many_region_blocks_matches_alone(kpx):
+    """A query of 70^3 regions (more than 1024 region blocks) and one of more
+    than 1024 tiles, batched with a small one, graph-replayed: each tree is
+    the one the query grows alone."""
+    ws = [W.make_workload("di6", 6, n_select=2000, samples=0, tree_cap=1 << 20, grid=(70, 70, 70)),
+          W.make_workload("di6", 7, n_select=300_000, samples=0, tree_cap=1 << 20),
+          W.make_workload("quad12", 2, n_select=64, samples=8, tree_cap=1 << 16, grid=(8, 8, 8))]
+    alone = []
+    for w in ws:
+        p = kpx.Planner(w.problem, w.params)
+        p.iterate(8)
+        alone.append(p.snapshot())
+        p.close()
+    ps = [kpx.Planner(w.problem, w.params) for w in ws]
+    b = kpx.Batch(ps, graph=True)
+    b.iterate(8)
+    b.sync()
+    for q, (p, a) in enumerate(zip(ps, alone)):
+        _same(p.snapshot(), a, f"query {q}")
+    b.close()
+    for p in ps:
+        p.close()
+
+
 def test_batch_graph_replays_match_plain_launches(kpx):
     ws = _small_batch(8, 5, n_select_max=200)
     plain = [kpx.Planner(w.problem, w.params) for w in ws]

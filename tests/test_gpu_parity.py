@@ -157,6 +157,37 @@ def test_lockstep_uncapped_form(kpx, ora, case):
     pl.close()
 
 
+def test_lockstep_long_one_level_scans(kpx, ora):
+    """More than 1024 tiles (300,000 slots) and more than 1024 region blocks
+    (70^3 = 343,000 regions), summed in one level: each block's offset runs
+    over several thousand counts."""
+    w = W.make_workload("di6", 6, n_select=300_000, samples=0, tree_cap=1 << 21, grid=(70, 70, 70))
+    assert w.params.n_cells > 1024 * 256 and w.params.n_slots > 1024 * 256
+    P = ora.Problem(w.problem, w.params)
+    pl = _planner(kpx, w)
+    rep = parity.lockstep(ora, P, pl, 6)
+    print(rep)
+    assert rep["iterations"] == 6 and rep["slots"] > 6 * 1024 * 256
+    assert pl.counters()["n_tree"] > 100_000
+    pl.close()
+
+
+def test_lockstep_grouped_scans(kpx, ora):
+    """More than 8192 tiles (2.2 million slots, 9 groups of 1024) and more than
+    8192 region blocks (130^3 = 2,197,000 regions, 9 groups): survivor ranks
+    and selection offsets come from the group sums plus the counts within a
+    group."""
+    w = W.make_workload("di6", 6, n_select=2_200_000, samples=0, tree_cap=1 << 22, grid=(130, 130, 130))
+    assert w.params.n_slots > 8192 * 256 and w.params.n_cells > 8192 * 256
+    P = ora.Problem(w.problem, w.params)
+    pl = _planner(kpx, w)
+    rep = parity.lockstep(ora, P, pl, 2)
+    print(rep)
+    assert rep["iterations"] == 2 and rep["slots"] > 4_000_000
+    assert pl.counters()["n_tree"] > 10_000
+    pl.close()
+
+
 @pytest.mark.parametrize("name,iters", [("quad12", 200), ("dubins6", 300)])
 def test_full_size_solution_verifies(kpx, ora, name, iters):
     """A full-size plan of the quadrotor and Dubins workloads, re-integrated
