@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="quad12",
                     choices=["di6", "quad12", "dubins6", "di6_paper", "quad12_paper", "dubins6_paper",
+                             "di6_paper_small", "quad12_paper_small", "dubins6_paper_small",
                              "batch256", "diff65536"])
     ap.add_argument("--queries", type=int, default=256, help="queries of the batch256 workload")
     ap.add_argument("--no-sequential", action="store_true",

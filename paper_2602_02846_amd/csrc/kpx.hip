@@ -329,7 +329,8 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     const int S = st->n_sel * K;
     if (st->full || S == 0) return;  // kernel-uniform
     int chunk = max(kChunkMin, (S + nblk - 1) / nblk);
-    chunk = min(chunk, min(kChunkMax, (kParMax - 1) * K));
+    // at most kParMax parents per chunk (K may be up to the buffer size: 64-bit)
+    chunk = (int)min((long long)chunk, min((long long)kChunkMax, (long long)(kParMax - 1) * K));
     if (blk * chunk >= S) return;  // block-uniform
     if (blk == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
     const long long n_tree = st->n_tree;

@@ -42,9 +42,23 @@ def check_tree_invariants(kpx, snap, n_slots_max, n_cells):
 
 
 @pytest.mark.parametrize("name,warm", [("quad12", 12), ("dubins6", 12), ("di6", 40),
-                                       ("quad12_paper", 6), ("dubins6_paper", 6), ("di6_paper", 10)])
+                                       ("quad12_paper", 6), ("dubins6_paper", 6), ("di6_paper", 10),
+                                       ("quad12_paper_small", 2)])
 def test_full_size_sampled_slots(kpx, ora, name, warm):
-    w = W.make_workload(name, 0)
+    sampled_slots_check(kpx, ora, W.make_workload(name, 0), warm)
+
+
+def test_sampled_slots_root_with_nine_million_samples(kpx, ora):
+    """The uncapped form's first iterations give one node 9 million samples:
+    a chunk's parent bound (255 parents times the samples per node) no longer
+    fits 32 bits.  The root's expansion and the next iteration's."""
+    w = W.make_workload("quad12", 0, n_select=9_000_000, samples=0, tree_cap=1 << 24)
+    sampled_slots_check(kpx, ora, w, 0)
+    sampled_slots_check(kpx, ora, w, 1)
+
+
+def sampled_slots_check(kpx, ora, w, warm):
+    name = w.name
     P = ora.Problem(w.problem, w.params)
     pl = kpx.Planner(w.problem, w.params)
     pl.iterate(warm)

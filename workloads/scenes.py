@@ -390,8 +390,27 @@ def _paper(name):
     return make
 
 
+# The paper's small-delta sizes (App. B): t_e = 10^8 slots and nodes with about
+# 10^7 regions for every system (215^3; 250 x 250 x 160; 108^3 x 8 velocity-sign
+# classes).  About 21 GB of device memory per query.
+PAPER_SMALL_SIZES = {
+    "di6": dict(n_select=100_000_000, samples=0, tree_cap=100_000_000, grid=(215, 215, 215)),
+    "dubins6": dict(n_select=100_000_000, samples=0, tree_cap=100_000_000, grid=(250, 250, 160)),
+    "quad12": dict(n_select=100_000_000, samples=0, tree_cap=100_000_000, grid=(108, 108, 108)),
+}
+
+
+def _paper_small(name):
+    def make(seed: int = 0, **overrides) -> Workload:
+        w = WORKLOADS[name](seed, **dict(PAPER_SMALL_SIZES[name], **overrides))
+        w.name = name + "_paper_small"
+        return w
+    return make
+
+
 WORKLOADS = {"di6": di6_workload, "quad12": quad12_workload, "dubins6": dubins6_workload}
 WORKLOADS.update({n + "_paper": _paper(n) for n in ("di6", "quad12", "dubins6")})
+WORKLOADS.update({n + "_paper_small": _paper_small(n) for n in ("di6", "quad12", "dubins6")})
 
 
 def make_workload(name: str, seed: int = 0, **overrides) -> Workload:
