@@ -302,7 +302,8 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
     extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | grid lists
-    __shared__ float s_u[M][kChunkMax];
+    constexpr int SD = (D + 3) & ~3;     // a staged parent state: whole 16-byte words
+    __shared__ float4 s_u[kChunkMax];    // a slot's control (one 16-byte read per refill)
     __shared__ unsigned short s_n[kChunkMax];
     __shared__ uint32_t s_order[kChunkMax];  // slot in chunk | parent row << 16
     __shared__ short s_fi[kChunkMax];
@@ -316,8 +317,9 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     __shared__ float s_os[2][D];
     const int gbp = (P.gb_cells + 1) & ~1;  // grid cells, padded to whole 16-byte words
     float4* sbox = dyn_lds;
+    // parent states, one row of SD floats per parent, already in integration units
     float* spx = reinterpret_cast<float*>(dyn_lds + 2 * P.n_boxes);
-    int2* sgc = reinterpret_cast<int2*>(spx + D * kParMax);
+    int2* sgc = reinterpret_cast<int2*>(spx + SD * kParMax);
     uint16_t* sgl = reinterpret_cast<uint16_t*>(sgc + gbp);
 
     // the obstacle data does not depend on the device state: its loads go
@@ -381,21 +383,27 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                 float u[M];
                 int n;
                 sample<DYN>(P, it, (uint32_t)(base + li), u, n);
-#pragma unroll
-                for (int k = 0; k < M; ++k) s_u[k][li] = u[k];
+                float u3 = 0.f;
+                if constexpr (M > 3) u3 = u[3];
+                s_u[li] = make_float4(u[0], u[1], u[2], u3);
                 s_n[li] = (unsigned short)n;
                 bins[r] = (kSortBins - 1) - min(kSortBins - 1, (n - P.steps_min) >> P.sort_shift);
                 if (one_each) s_order[li] = (uint32_t)li | (uint32_t)((base + li) / K - r0) << 16;
                 else atomicAdd(&s_bin[bins[r]], 1);
             }
         }
+        // staged parent component c of row j: x_c in integration units
+        auto stage_x = [&](int idx, float v) {
+            const int c = idx / npar, j = idx % npar;
+            spx[j * SD + c] = v * (rev_state(DYN, c) ? kInv2Pi : 1.f);
+        };
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
             const int idx = threadIdx.x + r * kPropBlock;
-            if (idx < nstage) spx[(idx / npar) * kParMax + idx % npar] = pv[r];
+            if (idx < nstage) stage_x(idx, pv[r]);
         }
         for (int idx = threadIdx.x + kStage * kPropBlock; idx < nstage; idx += kPropBlock)
-            spx[(idx / npar) * kParMax + idx % npar] = T.x[(long long)(idx / npar) * P.cap + T.sel[r0 + idx % npar]];
+            stage_x(idx, T.x[(long long)(idx / npar) * P.cap + T.sel[r0 + idx % npar]]);
         if ((int)threadIdx.x < npar) {
             s_pid[threadIdx.x] = my_pid;
             s_pcost[threadIdx.x] = my_pcost;
@@ -424,6 +432,18 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
 
         // 2. integrate, each lane refilling from the queue
         float x[D], u[M];
+        // a parent's staged state into x: 16-byte LDS reads
+        auto load_parent = [&](int j) {
+            const float4* r = reinterpret_cast<const float4*>(spx + j * SD);
+#pragma unroll
+            for (int w = 0; w < SD / 4; ++w) {
+                const float4 v = r[w];
+                const float a[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (4 * w + e < D) x[4 * w + e] = a[e];
+            }
+        };
         float len = 0.f;
         int li = -1, n = 0, k = 0;
         int pjl = 0;                        // the lane's parent row
@@ -452,10 +472,11 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                         li = (int)(o & 0xFFFFu);
                         const int pj = (int)(o >> 16);
                         n = s_n[li];
+                        const float4 uv = s_u[li];
+                        const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
 #pragma unroll
-                        for (int c = 0; c < M; ++c) u[c] = s_u[c][li] * (rev_control(DYN, c) ? kInv2Pi : 1.f);
-#pragma unroll
-                        for (int c = 0; c < D; ++c) x[c] = spx[c * kParMax + pj] * (rev_state(DYN, c) ? kInv2Pi : 1.f);
+                        for (int c = 0; c < M; ++c) u[c] = ua[c] * (rev_control(DYN, c) ? kInv2Pi : 1.f);
+                        load_parent(pj);
                         k = 0;
                         len = 0.f;
                         gcur = -1;
@@ -528,9 +549,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                         ctv = __hip_atomic_load(&T.tbl[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         pend = true;
                         chk = true;
-#pragma unroll
-                        for (int q = 0; q < D; ++q)
-                            x[q] = spx[q * kParMax + pjl] * (rev_state(DYN, q) ? kInv2Pi : 1.f);
+                        load_parent(pjl);
                         k = 0;
                         len = 0.f;
                         gcur = -1;
@@ -597,7 +616,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             if (T.d_parent) {
                 T.d_parent[s] = s_pid[pj];
 #pragma unroll
-                for (int q = 0; q < M; ++q) T.d_u[(long long)q * P.s_max + s] = s_u[q][lj];
+                for (int q = 0; q < M; ++q) {
+                    const float4 uv = s_u[lj];
+                    T.d_u[(long long)q * P.s_max + s] = q == 0 ? uv.x : q == 1 ? uv.y : q == 2 ? uv.z : uv.w;
+                }
                 T.d_n[s] = nn;
                 T.d_fi[s] = fi;
             }
@@ -652,7 +674,7 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
                 // status, count and the first ancestor list in one round trip
                 uint8_t s = T.status[o];
                 const int ic0 = T.icount[o];
-                int4 A = T.anc[2 * o], B = T.anc[2 * o + 1];
+                int4 A = T.anc[2 * (size_t)o], B = T.anc[2 * (size_t)o + 1];
                 if (s == kInactive) {  // Alg. 3: a dormant node counts up and wakes past I_max
                     const int ic = ic0 + 1;
                     T.icount[o] = (uint8_t)ic;
@@ -673,8 +695,8 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
                         const int nq = ids[7];
                         int4 NA = make_int4(-1, -1, -1, -1), NB = NA;
                         if (nq >= 0) {
-                            NA = T.anc[2 * nq];
-                            NB = T.anc[2 * nq + 1];
+                            NA = T.anc[2 * (size_t)nq];
+                            NB = T.anc[2 * (size_t)nq + 1];
                         }
 #pragma unroll
                         for (int j = 0; j < 8; ++j) beaten |= d[j] != 0;
@@ -948,7 +970,7 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
         float xv[D];
 #pragma unroll
         for (int q = 0; q < D; ++q) xv[q] = T.cx[(long long)q * P.s_max + s];
-        const int4 pa = T.anc[2 * par], pb = T.anc[2 * par + 1];
+        const int4 pa = T.anc[2 * (size_t)par], pb = T.anc[2 * (size_t)par + 1];
         float u[M];
         int n;
         sample<DYN>(P, it, (uint32_t)s, u, n);
@@ -1874,7 +1896,7 @@ size_t propagate_lds_bytes(const Sizes& z, int d)
 {
     // every region padded to whole 16-byte words (the kernel stages them as such)
     const size_t gbp = ((size_t)z.gb_n[0] * z.gb_n[1] * z.gb_n[2] + 1) & ~(size_t)1;
-    return sizeof(float4) * 2 * (size_t)z.n_boxes + sizeof(float) * (size_t)d * kParMax +
+    return sizeof(float4) * 2 * (size_t)z.n_boxes + sizeof(float) * (size_t)((d + 3) & ~3) * kParMax +
            sizeof(int2) * gbp + 16 * (((size_t)z.gb_entries + 7) / 8);
 }
 
