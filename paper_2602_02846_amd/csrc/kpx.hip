@@ -741,14 +741,13 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
     const int s = tile * kTile + threadIdx.x;
     const int sc = min(s, P.s_max - 1);
     const uint8_t fl = T.cflag[sc];
-    const unsigned long long key = T.ckey[sc];
-    const int cell = T.ccell[sc];
     const int full = st->full;
     const int S = st->n_sel * st->k;
     if (full || tile * kTile >= S) return;  // block-uniform
     int f = 0;
     if (s < S) {
-        if (fl & 1) f = key == T.tbl[cell];
+        // only a valid slot's key and region are read
+        if (fl & 1) f = T.ckey[s] == T.tbl[T.ccell[s]];
         T.csurv[s] = (uint8_t)f;
     }
     const int wt = wave_sum(f);
@@ -929,11 +928,7 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
         pre += j < tile ? v : 0;
     }
     const uint8_t f0 = T.csurv[sc];
-    const unsigned long long key = T.ckey[sc];
-    const int c = T.ccell[sc];
-    const uint8_t flag = T.cflag[sc];
     const int K = P.K > 0 ? P.K : st->k;
-    const int par = T.sel[sc / K];
     const int full = st->full, n_sel = st->n_sel;
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
@@ -944,6 +939,17 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     if (grp)  // the earlier groups
         for (int j = threadIdx.x; j < tile / kGroup; j += kBlock) pre += *tgroup_at(T, P, (int)(st - T.st), j);
     const int f = s < S ? f0 : 0;
+    // a survivor's candidate record and parent, in flight while the ranks are
+    // scanned (the other slots' records are not read)
+    unsigned long long key = 0;
+    int c = 0, par = 0;
+    uint8_t flag = 0;
+    if (f) {
+        key = T.ckey[s];
+        c = T.ccell[s];
+        flag = T.cflag[s];
+        par = T.sel[s / K];
+    }
     // rank = survivors of the earlier tiles + those before this slot in its tile
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int inc = f;
