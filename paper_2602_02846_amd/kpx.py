@@ -271,8 +271,9 @@ class Planner:
             self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
             ws_ptr = self.workspace.data_ptr()
         h = _vp()
-        rc = lib().kpx_create(C.byref(self._ps), C.byref(self._qs), _vp(stream.cuda_stream),
-                              ws_ptr, ws_bytes, C.byref(h))
+        with torch.cuda.device(self.device):  # kpx_create sizes its launches for the current device
+            rc = lib().kpx_create(C.byref(self._ps), C.byref(self._qs), _vp(stream.cuda_stream),
+                                  ws_ptr, ws_bytes, C.byref(h))
         if rc != OK:
             raise KPXError(rc)
         self.h = h
