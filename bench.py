@@ -93,6 +93,9 @@ def parse():
     ap.add_argument("--cost-first", action="store_true",
                     help="propagate in the exact cost-first form (obstacle tests only for edges "
                          "that can still be their region's minimum)")
+    ap.add_argument("--tree-growth", type=int, default=0,
+                    help="also run the workload this many iterations and time every kernel in "
+                         "windows as the tree grows (prune and insert against tree size)")
     ap.add_argument("--refine-at", type=int, default=0,
                     help="solution runs: halve the region cells per axis after this many iterations")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -198,6 +201,7 @@ def main():
 
     planner.close()
     sols = solution_medians(K, W, a, a.polish, a.refine_at) if a.solution_seeds > 0 else None
+    growth = tree_growth(K, W, a) if a.tree_growth > 0 else None
     sols_plain = (solution_medians(K, W, a, 0) if a.solution_seeds > 0 and (a.polish or a.refine_at)
                   else None)
 
@@ -228,7 +232,44 @@ def main():
         "solutions_plain": sols_plain,
         "cpu_baseline": cpu,
     }
+    if growth is not None:
+        out["tree_growth"] = growth
     print(json.dumps(out))
+
+
+def tree_growth(K, W, a, window=50):
+    """Per-kernel HIP-event times over windows of `window` iterations at
+    geometrically spaced points of a run of a.tree_growth iterations, with the
+    tree size and live regions at each window: prune works per region and per
+    slot, so its time should follow the region count, not the tree."""
+    w = W.make_workload(a.workload, a.seed)
+    p = K.Planner(w.problem, w.params)
+    if a.cost_first:
+        p.set_cost_first(True)
+    out, done, start = [], 0, window
+    while done < a.tree_growth:
+        p.iterate(max(0, start - done))
+        done = start
+        c0 = p.counters()
+        if c0["full"]:
+            break
+        p.set_timing(True)
+        p.iterate(window)
+        ms, launches = p.read_timing()
+        p.set_timing(False)
+        c1 = p.counters()
+        snap = p.snapshot()
+        live = int((snap["cell_table"] != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+        st = p.stats(int(c0["iteration"]), int(c1["iteration"] - c0["iteration"]))
+        out.append({"iteration": int(c0["iteration"]), "n_tree": int(c1["n_tree"]),
+                    "live_regions": live, "survivors_per_iteration": float(st["n_survivors"].mean()) if st.size else 0.0,
+                    "us": {n: round(ms[i] / launches[i] * 1e3, 2) for i, n in enumerate(
+                        ["propagate", "prune_flags", "insert", "finalize_select"]) if launches[i]}})
+        done += window
+        start = max(done, 2 * start)
+        print(f"[bench] tree growth: iteration {done}, n_tree {c1['n_tree']}", file=sys.stderr, flush=True)
+    p.close()
+    return {"window_iterations": window, "capacity": int(w.params.tree_cap), "windows": out}
 
 
 BUDGETS_MS = (5.0, 10.0, 20.0, 40.0)
