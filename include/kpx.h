@@ -239,7 +239,10 @@ int kpx_sync(kpx_handle* h);
 /* Waits and copies the device counters to *out (host). */
 int kpx_counters_read(kpx_handle* h, kpx_counters* out);
 
-/* Waits, then returns the best goal node's trajectory (Alg. 4):
+/* Waits, then returns the best goal node's trajectory (Alg. 4).  A root that
+ * lies in the goal set (planning radius: goal radius minus the margin) is the
+ * solution from the start: cost 0, no edge, first_solution_iteration 0.
+ * Layout:
  * states (n_edges + 1) x KPX_MAX_STATE row-major starting at x_init,
  * controls n_edges x KPX_MAX_CONTROL, steps n_edges (host buffers, may be NULL).
  * If capacity_edges < n_edges only *info is filled and KPX_ERR_BUFFER is returned. */

@@ -480,6 +480,14 @@ int ora_init(const ora_problem* P, ora_tree* T)
     T->sol_cost = INFINITY;
     T->sol_id = -1;
     T->first_sol_iter = -1;
+    /* Reading: a root that already lies in the goal set is a solution of cost
+     * 0 (the empty trajectory), found before the first iteration.  Alg. 4
+     * otherwise tests only the nodes it inserts. */
+    if (ora_goal_test(P, x0, (double)P->goal_radius - (double)P->margin, NULL, NULL)) {
+        T->sol_cost = 0.0;
+        T->sol_id = 0;
+        T->first_sol_iter = 0;
+    }
     T->full = 0;
     T->last_n_sel = T->last_n_valid = T->last_n_surv = 0;
     return ORA_OK;
@@ -917,7 +925,8 @@ int ora_verify(const ora_problem* P, int32_t n_edges, const float* controls, con
         s += dlt * dlt;
     }
     rep->goal_distance = sqrt(s);
-    rep->reaches_goal = n_edges > 0 && rep->goal_distance <= (double)P->goal_radius;
+    /* an empty plan reaches the goal only when the start lies in it */
+    rep->reaches_goal = rep->goal_distance <= (double)P->goal_radius;
     if (P->cost == ORA_COST_TIME) {
         rep->cost = total_steps;
         rep->cost_ok = reported_cost == total_steps;

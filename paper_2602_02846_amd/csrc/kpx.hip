@@ -228,8 +228,10 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, DevState* st, const float* 
     T.act[c] = 1;
     st->n_tree = 1;
     st->it = 0;
-    st->first_sol_it = -1;
-    st->sol = kEmpty;
+    // a root in the goal set is already a solution: the empty trajectory, cost 0
+    const bool root_goal = in_goal(P, x);
+    st->first_sol_it = root_goal ? 0 : -1;
+    st->sol = root_goal ? 0ull : kEmpty;
     st->substeps_acc = 0;
     st->last_substeps = 0;
     st->n_valid_acc = 0;

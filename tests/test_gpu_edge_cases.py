@@ -52,6 +52,27 @@ def test_degenerate_and_ragged_sizes_lockstep(kpx, ora, n_select, k):
     pl.close()
 
 
+@pytest.mark.parametrize("name", ["di6", "quad12"])
+def test_root_in_the_goal_is_a_solution(kpx, ora, name):
+    """A start inside the goal set is a solution of cost 0 with no edge, from
+    before the first iteration; no inserted node can beat it."""
+    w = W.make_workload(name, 2, n_select=64, samples=4, tree_cap=1 << 14)
+    w.problem.x_init = w.problem.x_init.copy()
+    w.problem.x_init[:3] = np.asarray(w.problem.goal_center, np.float32)
+    P = ora.Problem(w.problem, w.params)
+    pl = kpx.Planner(w.problem, w.params)
+    c = pl.counters()
+    assert c["solution_key"] == 0 and c["first_solution_iteration"] == 0
+    rep = parity.lockstep(ora, P, pl, 4)
+    assert rep["iterations"] == 4
+    sol = pl.solution()
+    assert sol["found"] and sol["tree_index"] == 0 and sol["n_edges"] == 0 and sol["cost"] == 0.0
+    assert sol["first_solution_iteration"] == 0
+    rep = ora.verify(P, np.zeros((0, 4), np.float32), np.zeros(0, np.int32), sol["states"], 0.0)
+    assert rep["ok"] and rep["reaches_goal"]
+    pl.close()
+
+
 def test_unreachable_goal_has_no_solution(kpx):
     w = W.make_workload("di6", 3)
     c = w.problem.goal_center

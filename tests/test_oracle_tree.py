@@ -460,3 +460,27 @@ def test_refinement_that_outgrows_the_capacity_stops_the_tree(ora):
     assert tr.c.full == 1
     assert tr.step() == ora.FULL
     assert tr.n_tree == n
+
+
+def test_root_in_the_goal_is_a_solution_of_cost_zero(ora):
+    """A start inside the goal set is the empty trajectory of cost 0, found
+    before the first iteration, and no later node beats it (every edge costs
+    more than 0)."""
+    for name in ("di6", "dubins6"):
+        w = W.make_workload(name, 1, **dict(W.scenes.small_overrides(name), samples=64))
+        w.problem.x_init = w.problem.x_init.copy()
+        w.problem.x_init[:3] = np.asarray(w.problem.goal_center, np.float32)
+        P = ora.Problem(w.problem, w.params)
+        T = ora.Tree(P)
+        assert T.init() == ora.OK
+        assert (T.c.sol_id, T.c.sol_cost, T.c.first_sol_iter) == (0, 0.0, 0)
+        for _ in range(6):
+            T.step()
+        assert (T.c.sol_id, T.c.sol_cost, T.c.first_sol_iter) == (0, 0.0, 0)
+        # (the airplane, heading into the corner, only returns to the start region)
+        assert T.n_tree > 1 or name == "dubins6"
+        # just outside the planning goal radius there is no such solution
+        w.problem.x_init[0] += np.float32(w.problem.goal_radius - w.problem.margin + 1e-3)
+        T2 = ora.Tree(ora.Problem(w.problem, w.params))
+        if T2.init() == ora.OK:
+            assert T2.c.sol_id == -1 and T2.c.first_sol_iter == -1

@@ -60,3 +60,17 @@ def test_rejects_bound_violation(ora, solved):
     big[:] = 1.0  # full acceleration on every edge exceeds |v| <= 1
     rep = ora.verify(P, big, steps * 0 + 30, None, 0.0)
     assert not rep["within_bounds"] or not rep["collision_free"]
+
+
+def test_empty_plan_only_from_inside_the_goal(ora):
+    """No edge: accepted exactly when the start lies in the goal ball."""
+    w = W.make_workload("di6", 2)
+    P = ora.Problem(w.problem, w.params)
+    none_u, none_n = np.zeros((0, 4), np.float32), np.zeros(0, np.int32)
+    rep = ora.verify(P, none_u, none_n, w.problem.x_init[:6].reshape(1, 6), 0.0)
+    assert not rep["ok"] and not rep["reaches_goal"]
+    w.problem.x_init = w.problem.x_init.copy()
+    w.problem.x_init[:3] = np.asarray(w.problem.goal_center, np.float32)
+    P = ora.Problem(w.problem, w.params)
+    rep = ora.verify(P, none_u, none_n, w.problem.x_init[:6].reshape(1, 6), 0.0)
+    assert rep["ok"] and rep["reaches_goal"] and rep["cost"] == 0.0
