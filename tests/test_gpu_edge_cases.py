@@ -73,6 +73,26 @@ def test_root_in_the_goal_is_a_solution(kpx, ora, name):
     pl.close()
 
 
+@pytest.mark.parametrize("steps", [(1, 1), (7, 7), (1, 2)])
+def test_fixed_and_one_step_durations(kpx, ora, steps):
+    """Edges of one RK4 step, and fixed step counts (a single sort bin), in
+    lockstep with the oracle; the cost-first form grows the same tree."""
+    w = W.make_workload("quad12", 5, n_select=90, samples=9, tree_cap=1 << 15, grid=(8, 8, 8), steps=steps)
+    P = ora.Problem(w.problem, w.params)
+    pl = kpx.Planner(w.problem, w.params)
+    cf = kpx.Planner(w.problem, w.params)
+    cf.set_cost_first(True)
+    rep = parity.lockstep(ora, P, pl, 10)
+    assert rep["iterations"] == 10 and rep["valid"] > 0
+    cf.iterate(10)
+    a, b = pl.snapshot(), cf.snapshot()
+    for k in ("state", "control", "steps", "parent", "cost", "cell", "status", "cell_table"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    assert a["counters"]["n_tree"] > 1
+    pl.close()
+    cf.close()
+
+
 def test_unreachable_goal_has_no_solution(kpx):
     w = W.make_workload("di6", 3)
     c = w.problem.goal_center
