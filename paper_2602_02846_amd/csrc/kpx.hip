@@ -310,7 +310,8 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     __shared__ uint32_t s_order[kChunkMax];  // slot in chunk | parent row << 16
     __shared__ short s_fi[kChunkMax];
     __shared__ float s_len[COST == kPATH ? kChunkMax : 1];
-    __shared__ float s_xe[6][kChunkMax];  // end position and velocity of valid slots
+    __shared__ float s_pe[3][kChunkMax];  // end position of valid slots
+    __shared__ uint8_t s_vs[kChunkMax];   // ... and the signs of their velocity (bit a: v_a >= 0)
     __shared__ int s_pid[kParMax];        // the chunk's parents: tree index
     __shared__ uint32_t s_pcost[kParMax]; //                     cost field
     constexpr int VI = DYN == kQUAD12 ? 6 : 3;  // first velocity component
@@ -376,9 +377,11 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         }
         const uint32_t my_pcost = (int)threadIdx.x < npar ? T.cost[my_pid] : 0u;
         const bool one_each = cnt <= (int)blockDim.x;  // one slot per thread: no sort needed
+        const int nr = (cnt + kPropBlock - 1) / kPropBlock;  // slot rounds of this chunk
         int bins[kPerThread];
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
+            if (r >= nr) break;  // block-uniform
             const int li = threadIdx.x + r * kPropBlock;
             bins[r] = -1;
             if (li < cnt) {
@@ -424,11 +427,13 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             }
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < kPerThread; ++r)
+            for (int r = 0; r < kPerThread; ++r) {
+                if (r >= nr) break;
                 if (bins[r] >= 0)
                     s_order[atomicAdd(&s_bin[bins[r]], 1)] =
                         (uint32_t)(threadIdx.x + r * kPropBlock) |
                         (uint32_t)((base + (int)threadIdx.x + r * kPropBlock) / K - r0) << 16;
+            }
             __syncthreads();
         }
 
@@ -563,10 +568,8 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                     if (ok) {
                         if constexpr (COST == kPATH) s_len[li] = len;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            s_xe[a][li] = x[a];
-                            s_xe[3 + a][li] = x[VI + a];
-                        }
+                        for (int a = 0; a < 3; ++a) s_pe[a][li] = x[a];
+                        s_vs[li] = (uint8_t)((x[VI] >= 0.f) | (x[VI + 1] >= 0.f) << 1 | (x[VI + 2] >= 0.f) << 2);
 #pragma unroll
                         for (int c = 0; c < D; ++c)
                             T.cx[(long long)c * P.s_max + base + li] = x[c] * (rev_state(DYN, c) ? k2Pi : 1.f);
@@ -583,6 +586,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         unsigned long long keys[kPerThread], olds[kPerThread];
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
+            if (r >= nr) break;  // block-uniform
             const int lj = threadIdx.x + r * kPropBlock;
             keys[r] = kEmpty;
             olds[r] = kEmpty;
@@ -594,8 +598,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             if constexpr (!CF) my_steps += fi ? fi : nn;
             if (fi == 0) {
                 ++my_valid;
-                const float pe[3] = {s_xe[0][lj], s_xe[1][lj], s_xe[2][lj]};
-                const float ve[3] = {s_xe[3][lj], s_xe[4][lj], s_xe[5][lj]};
+                const float pe[3] = {s_pe[0][lj], s_pe[1][lj], s_pe[2][lj]};
+                // the velocity enters the region only through its signs
+                const int vs = s_vs[lj];
+                const float ve[3] = {vs & 1 ? 1.f : -1.f, vs & 2 ? 1.f : -1.f, vs & 4 ? 1.f : -1.f};
                 const int c = cell_of(P, pe, ve);
                 uint32_t cf;
                 if constexpr (COST == kTIME) {
@@ -628,6 +634,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         }
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
+            if (r >= nr) break;
             const unsigned long long key = keys[r], old = olds[r];
             if (key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
                 // this lane took the region from a tree node: it is beaten (V_T)
