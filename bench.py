@@ -275,6 +275,15 @@ def tree_growth(K, W, a, window=50):
 BUDGETS_MS = (5.0, 10.0, 20.0, 40.0)
 
 
+def key_cost(key, cost_kind, dt):
+    """Cost of a solution key: the high word is the total RK4 step count
+    (TIME cost, times dt) or the float32 bits of the path length."""
+    field = int(key) >> 32
+    if cost_kind == "TIME":
+        return field * dt
+    return float(np.array([field], np.uint32).view(np.float32)[0])
+
+
 def solution_medians(K, W, a, polish=0, refine_at=0):
     """Median device-timed time to first solution and median solution cost
     over seeds 0 .. solution_seeds - 1 of the workload, each run for
@@ -324,7 +333,7 @@ def solution_medians(K, W, a, polish=0, refine_at=0):
         for b in BUDGETS_MS:
             keys = st["solution_key"][t_ms <= b]
             best = int(keys.min()) if keys.size else (1 << 64) - 1
-            at_budget[b].append(np.inf if best == (1 << 64) - 1 else (best >> 32) * dt)
+            at_budget[b].append(np.inf if best == (1 << 64) - 1 else key_cost(best, w.problem.cost, dt))
         p.close()
     return {"queries": a.solution_seeds, "iterations": a.solution_iters, "polish_steps": polish,
             "refine_at": refine_at,
