@@ -52,7 +52,7 @@ constexpr int kChunkMax = 1024;           // expansion slots per propagate chunk
 constexpr int kChunkMin = 64;
 constexpr int kParMax = 256;              // parent states staged per chunk (at most)
 constexpr int kPropBlock = 256;           // propagate: one wave per SIMD, one block per CU
-constexpr int kPerThread = kChunkMax / kPropBlock;
+constexpr int kPropBlockWide = 512;       // ... or two, for cheap models at large sizes
 constexpr int kStatsCap = 1 << 16;
 constexpr int kMaxPath = 1 << 16;
 
@@ -298,11 +298,12 @@ __device__ __forceinline__ void stage_lds(const int4* s0, int4* d0, int n0, cons
 // table value is loaded when the first pass ends and compared after the next
 // trip, so that its latency hides under one RK4 step.
 constexpr short kSkipped = -1;
-template <int DYN, int COST, bool CF = false>
+template <int DYN, int COST, bool CF = false, int NT = kPropBlock>
 __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtrs& T, DevState* st, int blk,
                                                int nblk)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
+    constexpr int PT = kChunkMax / NT;   // slot rounds per thread in a full chunk
     extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | grid lists
     constexpr int SD = (D + 3) & ~3;     // a staged parent state: whole 16-byte words
     __shared__ float4 s_u[kChunkMax];    // a slot's control (one 16-byte read per refill)
@@ -366,23 +367,23 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         float pv[kStage];
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
-            const int idx = threadIdx.x + r * kPropBlock;
+            const int idx = threadIdx.x + r * NT;
             prow[r] = idx < nstage ? T.sel[r0 + idx % npar] : 0;
         }
         const int my_pid = (int)threadIdx.x < npar ? T.sel[r0 + threadIdx.x] : 0;
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
-            const int idx = threadIdx.x + r * kPropBlock;
+            const int idx = threadIdx.x + r * NT;
             pv[r] = idx < nstage ? T.x[(long long)(idx / npar) * P.cap + prow[r]] : 0.f;
         }
         const uint32_t my_pcost = (int)threadIdx.x < npar ? T.cost[my_pid] : 0u;
         const bool one_each = cnt <= (int)blockDim.x;  // one slot per thread: no sort needed
-        const int nr = (cnt + kPropBlock - 1) / kPropBlock;  // slot rounds of this chunk
-        int bins[kPerThread];
+        const int nr = (cnt + NT - 1) / NT;  // slot rounds of this chunk
+        int bins[PT];
 #pragma unroll
-        for (int r = 0; r < kPerThread; ++r) {
+        for (int r = 0; r < PT; ++r) {
             if (r >= nr) break;  // block-uniform
-            const int li = threadIdx.x + r * kPropBlock;
+            const int li = threadIdx.x + r * NT;
             bins[r] = -1;
             if (li < cnt) {
                 float u[M];
@@ -404,10 +405,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         };
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
-            const int idx = threadIdx.x + r * kPropBlock;
+            const int idx = threadIdx.x + r * NT;
             if (idx < nstage) stage_x(idx, pv[r]);
         }
-        for (int idx = threadIdx.x + kStage * kPropBlock; idx < nstage; idx += kPropBlock)
+        for (int idx = threadIdx.x + kStage * NT; idx < nstage; idx += NT)
             stage_x(idx, T.x[(long long)(idx / npar) * P.cap + T.sel[r0 + idx % npar]]);
         if ((int)threadIdx.x < npar) {
             s_pid[threadIdx.x] = my_pid;
@@ -427,12 +428,12 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             }
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < kPerThread; ++r) {
+            for (int r = 0; r < PT; ++r) {
                 if (r >= nr) break;
                 if (bins[r] >= 0)
                     s_order[atomicAdd(&s_bin[bins[r]], 1)] =
-                        (uint32_t)(threadIdx.x + r * kPropBlock) |
-                        (uint32_t)((base + (int)threadIdx.x + r * kPropBlock) / K - r0) << 16;
+                        (uint32_t)(threadIdx.x + r * NT) |
+                        (uint32_t)((base + (int)threadIdx.x + r * NT) / K - r0) << 16;
             }
             __syncthreads();
         }
@@ -583,11 +584,11 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         // 3. region map, cost, region minimum, candidate records.  Every
         // atomic of a thread is issued before the first of their results is
         // looked at, so that their round trips overlap.
-        unsigned long long keys[kPerThread], olds[kPerThread];
+        unsigned long long keys[PT], olds[PT];
 #pragma unroll
-        for (int r = 0; r < kPerThread; ++r) {
+        for (int r = 0; r < PT; ++r) {
             if (r >= nr) break;  // block-uniform
-            const int lj = threadIdx.x + r * kPropBlock;
+            const int lj = threadIdx.x + r * NT;
             keys[r] = kEmpty;
             olds[r] = kEmpty;
             if (lj >= cnt) continue;
@@ -633,7 +634,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             }
         }
 #pragma unroll
-        for (int r = 0; r < kPerThread; ++r) {
+        for (int r = 0; r < PT; ++r) {
             if (r >= nr) break;
             const unsigned long long key = keys[r], old = olds[r];
             if (key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
@@ -652,10 +653,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     }
 }
 
-template <int DYN, int COST, bool CF>
-__global__ __launch_bounds__(kPropBlock) void k_propagate(DevProblem P, DevPtrs T, DevState* st)
+template <int DYN, int COST, bool CF, int NT>
+__global__ __launch_bounds__(NT) void k_propagate(DevProblem P, DevPtrs T, DevState* st)
 {
-    propagate_body<DYN, COST, CF>(P, T, st, blockIdx.x, gridDim.x);
+    propagate_body<DYN, COST, CF, NT>(P, T, st, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ prune + survivor flags
@@ -1814,6 +1815,7 @@ struct kpx_handle {
     int polish_steps = 0;                     // edge polish of inserted nodes (0: off)
     float polish_lr = 0.f;
     bool cost_first = false;                  // propagate in the cost-first form
+    int prop_threads = kPropBlock;            // propagate block size (kPropBlock or kPropBlockWide)
     kpxd::DiffConst polish_c{};
     std::string err;
 };
@@ -1919,10 +1921,15 @@ template <int DYN, int COST>
 void launch_propagate(kpx_handle* h, const DevPtrs& T)
 {
     const size_t lds = propagate_lds_bytes(h->z, Dims<DYN>::D);
-    if (h->cost_first)
-        k_propagate<DYN, COST, true><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
+    const bool wide = h->prop_threads == kPropBlockWide;
+    if (h->cost_first && wide)
+        k_propagate<DYN, COST, true, kPropBlockWide><<<h->P.n_cu, kPropBlockWide, lds, h->stream>>>(h->P, T, cur_state(h));
+    else if (h->cost_first)
+        k_propagate<DYN, COST, true, kPropBlock><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
+    else if (wide)
+        k_propagate<DYN, COST, false, kPropBlockWide><<<h->P.n_cu, kPropBlockWide, lds, h->stream>>>(h->P, T, cur_state(h));
     else
-        k_propagate<DYN, COST, false><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
+        k_propagate<DYN, COST, false, kPropBlock><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
 }
 
 // Allows `dynamic` bytes of dynamic LDS for a propagate kernel, after checking
@@ -1941,20 +1948,23 @@ int allow_lds(const void* kernel, size_t dynamic, int lds_max)
 // The propagate kernel for a (model, cost) pair: batched, or single-query in
 // the plain or the cost-first form.
 template <int DYN, int COST>
-const void* propagate_kernel_t(bool batched, bool cf)
+const void* propagate_kernel_t(bool batched, bool cf, bool wide)
 {
     if (batched) return (const void*)kb_propagate<DYN, COST>;
-    return cf ? (const void*)k_propagate<DYN, COST, true> : (const void*)k_propagate<DYN, COST, false>;
+    if (wide)
+        return cf ? (const void*)k_propagate<DYN, COST, true, kPropBlockWide>
+                  : (const void*)k_propagate<DYN, COST, false, kPropBlockWide>;
+    return cf ? (const void*)k_propagate<DYN, COST, true, kPropBlock> : (const void*)k_propagate<DYN, COST, false, kPropBlock>;
 }
-const void* propagate_kernel(int dyn, int cost, bool batched, bool cf = false)
+const void* propagate_kernel(int dyn, int cost, bool batched, bool cf = false, bool wide = false)
 {
     switch (dyn * 2 + cost) {
-    case 0: return propagate_kernel_t<kDI6, kTIME>(batched, cf);
-    case 1: return propagate_kernel_t<kDI6, kPATH>(batched, cf);
-    case 2: return propagate_kernel_t<kQUAD12, kTIME>(batched, cf);
-    case 3: return propagate_kernel_t<kQUAD12, kPATH>(batched, cf);
-    case 4: return propagate_kernel_t<kDUBINS6, kTIME>(batched, cf);
-    default: return propagate_kernel_t<kDUBINS6, kPATH>(batched, cf);
+    case 0: return propagate_kernel_t<kDI6, kTIME>(batched, cf, wide);
+    case 1: return propagate_kernel_t<kDI6, kPATH>(batched, cf, wide);
+    case 2: return propagate_kernel_t<kQUAD12, kTIME>(batched, cf, wide);
+    case 3: return propagate_kernel_t<kQUAD12, kPATH>(batched, cf, wide);
+    case 4: return propagate_kernel_t<kDUBINS6, kTIME>(batched, cf, wide);
+    default: return propagate_kernel_t<kDUBINS6, kPATH>(batched, cf, wide);
     }
 }
 
@@ -2213,10 +2223,18 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
             return KPX_ERR_DEVICE;
         }
         h->P.n_cu = std::max(1, n_cu);
+        // The cheap models' RK4 step is short beside the LDS latency of a
+        // refill or a box lookup, so with two slots or more per lane they run
+        // two waves per SIMD, which hide each other's waits.  The quadrotor's
+        // step keeps one wave per SIMD busy, and small queries are bound by
+        // their longest edge, which a second wave would only slow.
+        h->prop_threads = (h->P.dyn != kQUAD12 && (long long)z.s_max >= 2LL * kPropBlock * h->P.n_cu)
+                              ? kPropBlockWide : kPropBlock;
         int rc = KPX_OK;
         for (bool cf : {false, true})  // both forms, so that kpx_set_cost_first needs no device call
             if (rc == KPX_OK)
-                rc = allow_lds(propagate_kernel(h->P.dyn, h->P.cost, false, cf), propagate_lds_bytes(z, z.d), lds_max);
+                rc = allow_lds(propagate_kernel(h->P.dyn, h->P.cost, false, cf, h->prop_threads == kPropBlockWide),
+                               propagate_lds_bytes(z, z.d), lds_max);
         if (rc != KPX_OK) {
             delete h;
             return rc;
