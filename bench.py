@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="bound on the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--solution-seeds", type=int, default=10,
+    ap.add_argument("--solution-seeds", type=int, default=100,
                     help="queries (seeds) for the median time to first solution and cost")
     ap.add_argument("--solution-iters", type=int, default=200,
                     help="iteration budget of each of those queries")
