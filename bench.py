@@ -356,19 +356,21 @@ def bench_batch(a):
 
     import paper_2602_02846_amd as K
     import workloads as W
-    from paper_2602_02846_amd.autotune import autotune_samples, first_solution_ms, with_samples
+    from paper_2602_02846_amd.autotune import autotune, first_solution_ms, with_samples
 
     K.lib()
     torch.cuda.set_device(0)
     ws = W.batch_workloads(a.seed, a.queries)
-    chosen, scores = autotune_samples(ws)
-    ws = [with_samples(w, chosen[w.problem.dynamics]) for w in ws]
-    print(f"[bench] batch of {len(ws)} queries; samples per node {chosen} "
+    chosen, scores = autotune(ws)
+    ws = [with_samples(w, chosen[w.problem.dynamics][0]) for w in ws]
+    print(f"[bench] batch of {len(ws)} queries; samples per node and propagate threads {chosen} "
           f"(autotuner medians, ms: {scores})", file=sys.stderr, flush=True)
     n_iter = a.warmup + a.steps
 
     planners = [K.Planner(w.problem, w.params) for w in ws]
     batch = K.Batch(planners, graph=True)
+    for model, (_, nt) in chosen.items():
+        batch.set_threads(model, nt)
     torch.cuda.synchronize()
     tb0 = time.perf_counter()
     batch.iterate(a.warmup)
@@ -424,7 +426,11 @@ def bench_batch(a):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batch{len(ws)}: {len(ws) // 2} DI6 + {len(ws) - len(ws) // 2} QUAD12 "
                                "queries, 4..256 boxes, caps 2^10..2^18, graph-replayed batch",
-                   "seed": a.seed, "samples_per_node": chosen, "edges_timed": edges,
+                   "seed": a.seed, "samples_per_node": {m: kt[0] for m, kt in chosen.items()},
+                   "propagate_threads": {m: kt[1] for m, kt in chosen.items()},
+                   "autotune_ms": {m: {f"K{k}/{nt}": round(v, 3) for (k, nt), v in sc.items()}
+                                   for m, sc in scores.items()},
+                   "edges_timed": edges,
                    "substeps_timed": substeps},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,

@@ -375,6 +375,14 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out);
  * KPX_ERR_ARG for other values. */
 int kpx_batch_set_graph(kpx_batch* b, int32_t enable);
 
+/* Propagate threads per block for the batch's queries of one robot model
+ * (KPX_DI6 / KPX_QUAD12 / KPX_DUBINS6): 256 (one wave per SIMD, the default)
+ * or 512 (two), the per-query thread count the samples-per-node autotuner
+ * also tries.  Results do not depend on it.  Captured graphs are dropped and
+ * captured again on the next iterate.  KPX_ERR_ARG for another thread count;
+ * a model the batch does not hold is left alone. */
+int kpx_batch_set_threads(kpx_batch* b, int32_t dynamics, int32_t threads);
+
 /* Enqueues n_iters iterations of every query, ordered after the work already
  * on the handles' stream and before any later work on it; returns at once.
  * A query whose tree is full stops changing, as with kpx_iterate; each

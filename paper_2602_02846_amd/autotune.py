@@ -1,6 +1,8 @@
-"""Samples-per-node autotuner for batches of queries.
+"""Samples-per-node and threads-per-block autotuner for batches of queries.
 
-For each robot model of a batch, every candidate K (samples per node) is tried
+For each robot model of a batch, every candidate K (samples per node), with
+every candidate propagate block size (256 or 512 threads: one or two waves per
+SIMD, the lanes that serve a node's samples), is tried
 on a sample of that model's queries, run together as a batch for a fixed
 number of iterations; the K whose queries reach a first solution soonest (the
 median over the sample of the device-timed span from the first iteration to
@@ -44,14 +46,24 @@ def with_samples(w, k: int):
 
 def autotune_samples(workloads, candidates=(8, 16, 32), iterations: int = 40, sample: int = 16):
     """Returns {model: K} for the models present in `workloads`, and the
-    per-candidate scores {model: {K: median ms}}."""
+    per-candidate scores {model: {K: median ms}} (256 threads per block)."""
+    chosen, scores = autotune(workloads, candidates, (256,), iterations, sample)
+    return ({m: kt[0] for m, kt in chosen.items()},
+            {m: {kt[0]: v for kt, v in sc.items()} for m, sc in scores.items()})
+
+
+def autotune(workloads, candidates=(8, 16, 32), threads=(256, 512), iterations: int = 40,
+             sample: int = 16):
+    """Returns {model: (K, threads)} for the models present in `workloads`,
+    and the per-candidate scores {model: {(K, threads): median ms}}."""
     chosen, scores = {}, {}
     for model in sorted({w.problem.dynamics for w in workloads}):
         ws = [w for w in workloads if w.problem.dynamics == model][:sample]
         scores[model] = {}
-        for k in candidates:
+        for k, nt in [(k, nt) for k in candidates for nt in threads]:
             planners = [Planner(p.problem, p.params) for p in (with_samples(w, k) for w in ws)]
             batch = Batch(planners, graph=False)
+            batch.set_threads(model, nt)
             batch.iterate(iterations)
             batch.sync()
             ts = []
@@ -61,7 +73,7 @@ def autotune_samples(workloads, candidates=(8, 16, 32), iterations: int = 40, sa
             # unsolved queries count as the whole run: the span of the longest solved one, doubled
             finite = [t for t in ts if np.isfinite(t)]
             cap = 2.0 * max(finite) if finite else 1e9
-            scores[model][k] = float(np.median([min(t, cap) for t in ts]))
+            scores[model][(k, nt)] = float(np.median([min(t, cap) for t in ts]))
             batch.close()
             for p in planners:
                 p.close()

@@ -1327,14 +1327,14 @@ __device__ __forceinline__ DevPtrs global_ptrs(const DevPtrs& src)
     return T;
 }
 
-template <int DYN, int COST>
-__global__ __launch_bounds__(kPropBlock) void kb_propagate(const DevProblem* __restrict__ Ps,
-                                                         const DevPtrs* __restrict__ Ts,
-                                                         const int4* __restrict__ map, int par)
+template <int DYN, int COST, int NT>
+__global__ __launch_bounds__(NT) void kb_propagate(const DevProblem* __restrict__ Ps,
+                                                 const DevPtrs* __restrict__ Ts,
+                                                 const int4* __restrict__ map, int par)
 {
     const int4 m = map[blockIdx.x];
     const DevPtrs T = global_ptrs(Ts[m.x]);
-    propagate_body<DYN, COST>(Ps[m.x], T, T.st + par, m.y, m.z);
+    propagate_body<DYN, COST, false, NT>(Ps[m.x], T, T.st + par, m.y, m.z);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_prune_flags(const DevProblem* __restrict__ Ps,
@@ -1950,7 +1950,7 @@ int allow_lds(const void* kernel, size_t dynamic, int lds_max)
 template <int DYN, int COST>
 const void* propagate_kernel_t(bool batched, bool cf, bool wide)
 {
-    if (batched) return (const void*)kb_propagate<DYN, COST>;
+    if (batched) return wide ? (const void*)kb_propagate<DYN, COST, kPropBlockWide> : (const void*)kb_propagate<DYN, COST, kPropBlock>;
     if (wide)
         return cf ? (const void*)k_propagate<DYN, COST, true, kPropBlockWide>
                   : (const void*)k_propagate<DYN, COST, false, kPropBlockWide>;
@@ -2047,6 +2047,7 @@ struct kpx_batch {
     DevPtrs* d_T = nullptr;
     struct Group {
         int dyn = 0, cost = 0;
+        int nt = kPropBlock;        // propagate threads per block (kpx_batch_set_threads)
         int4* prop = nullptr;
         int n_prop = 0;
         size_t lds = 0;
@@ -2082,7 +2083,10 @@ int bfail(kpx_batch* b, int code, const std::string& msg)
 template <int DYN, int COST>
 void kb_propagate_launch(const kpx_batch* b, const kpx_batch::Group& g, int par, hipStream_t s)
 {
-    kb_propagate<DYN, COST><<<g.n_prop, kPropBlock, g.lds, s>>>(b->d_P, b->d_T, g.prop, par);
+    if (g.nt == kPropBlockWide)
+        kb_propagate<DYN, COST, kPropBlockWide><<<g.n_prop, kPropBlockWide, g.lds, s>>>(b->d_P, b->d_T, g.prop, par);
+    else
+        kb_propagate<DYN, COST, kPropBlock><<<g.n_prop, kPropBlock, g.lds, s>>>(b->d_P, b->d_T, g.prop, par);
 }
 
 // Stream of group gi: the batch stream for the first, a side stream otherwise.
@@ -2855,6 +2859,29 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
         return KPX_ERR_DEVICE;
     }
     *out = b;
+    return KPX_OK;
+}
+
+int kpx_batch_set_threads(kpx_batch* b, int32_t dynamics, int32_t threads)
+{
+    if (!b || (threads != kPropBlock && threads != kPropBlockWide)) return KPX_ERR_ARG;
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return bfail(b, KPX_ERR_DEVICE, "device query failed");
+    for (auto& g : b->groups) {
+        if (g.dyn != dynamics) continue;
+        const int rc = allow_lds(propagate_kernel(g.dyn, g.cost, true, false, threads == kPropBlockWide), g.lds, lds_max);
+        if (rc != KPX_OK) return bfail(b, rc, "propagate does not fit the LDS at this block size");
+        g.nt = threads;
+    }
+    // captured iterations hold the old launches
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto& e : b->exec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
     return KPX_OK;
 }
 

@@ -145,6 +145,7 @@ def lib():
         L.kpx_last_error.restype = C.c_char_p
         L.kpx_batch_create.argtypes = [C.POINTER(_vp), i32, C.POINTER(_vp)]
         L.kpx_batch_set_graph.argtypes = [_vp, i32]
+        L.kpx_batch_set_threads.argtypes = [_vp, i32, i32]
         L.kpx_batch_iterate.argtypes = [_vp, i32]
         L.kpx_batch_destroy.argtypes = [_vp]
         L.kpx_batch_last_error.argtypes = [_vp]
@@ -155,7 +156,7 @@ def lib():
                      "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy",
                      "kpx_batch_create", "kpx_batch_set_graph", "kpx_batch_iterate",
                      "kpx_batch_destroy", "kpx_set_polish", "kpx_refine", "kpx_set_timing_every",
-                     "kpx_set_cost_first"):
+                     "kpx_set_cost_first", "kpx_batch_set_threads"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -438,6 +439,10 @@ class Batch:
             msg = lib().kpx_batch_last_error(self.b).decode() if getattr(self, "b", None) else ""
             raise KPXError(rc, msg)
         return rc
+
+    def set_threads(self, dynamics: str, threads: int):
+        """Propagate threads per block (256 or 512) for the queries of one model."""
+        self._check(lib().kpx_batch_set_threads(self.b, DYNAMICS[dynamics], int(threads)))
 
     def set_graph(self, enable: bool = True):
         self._check(lib().kpx_batch_set_graph(self.b, 1 if enable else 0))

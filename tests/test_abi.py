@@ -110,6 +110,7 @@ def test_null_arguments(kpx):
     assert L.kpx_set_polish(None, None) == -1
     assert L.kpx_set_timing_every(None, 1) == -1
     assert L.kpx_set_cost_first(None, 1) == -1
+    assert L.kpx_batch_set_threads(None, 0, 256) == -1
 
 
 def test_diff_invalid_arguments_are_rejected(kpx):

@@ -137,6 +137,44 @@ def test_autotuner_scores_every_candidate(kpx):
         assert w.params.samples_per_node != 8 or w2.params.n_select == w.params.n_select
 
 
+def test_batch_threads_per_block_keep_the_trees(kpx):
+    """Two waves per SIMD for one model's propagate (and back) leave every
+    tree as each query grows it alone; graphs are captured again."""
+    ws = _small_batch(6, 9)
+    alone = []
+    for w in ws:
+        p = kpx.Planner(w.problem, w.params)
+        p.iterate(16)
+        alone.append(p.snapshot())
+        p.close()
+    ps = [kpx.Planner(w.problem, w.params) for w in ws]
+    b = kpx.Batch(ps, graph=True)
+    b.set_threads("DI6", 512)
+    b.iterate(6)
+    b.set_threads("QUAD12", 512)
+    b.iterate(6)
+    b.set_threads("DI6", 256)
+    b.iterate(4)
+    b.sync()
+    for q, (p, a) in enumerate(zip(ps, alone)):
+        _same(p.snapshot(), a, f"query {q}")
+    with pytest.raises(kpx.KPXError):
+        b.set_threads("DI6", 384)
+    b.close()
+    for p in ps:
+        p.close()
+
+
+def test_autotuner_tries_threads_per_block(kpx):
+    from paper_2602_02846_amd.autotune import autotune
+
+    ws = _small_batch(6, 4)
+    chosen, scores = autotune(ws, candidates=(8,), threads=(256, 512), iterations=10, sample=2)
+    for model, (k, nt) in chosen.items():
+        assert set(scores[model]) == {(8, 256), (8, 512)}
+        assert scores[model][(k, nt)] == min(scores[model].values())
+
+
 def test_batch_of_uncapped_queries_matches_each_alone(kpx):
     """Queries in the uncapped form (every active node, lambda per iteration
     from the device state) batched with capped ones."""
