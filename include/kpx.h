@@ -97,7 +97,8 @@ typedef struct kpx_problem {
 /*
  * Algorithm parameters (Alg. 1 inputs, App. A sizing).
  *   dt, steps_min..steps_max  one expansion integrates n RK4 steps of size dt,
- *                             n uniform in [steps_min, steps_max] (duration in (0, T_prop])
+ *                             n uniform in [steps_min, steps_max] (duration in (0, T_prop]);
+ *                             1 <= steps_min <= steps_max <= 32767
  *   grid, vel_sign_bins       region decomposition R: grid[a] cells per
  *                             position axis over the workspace, times 8
  *                             velocity-sign classes when vel_sign_bins = 1
@@ -193,6 +194,13 @@ typedef struct kpx_dump_view {
     uint64_t* key;         /* (cost field << 32) | (n_tree + s); all ones when invalid */
     uint8_t* goal;
     uint8_t* survivor;
+    /* edge polish (kpx_set_polish): one entry per node the iteration inserted,
+     * in insertion order (kpx_counters.n_survivors entries; zeros with polish
+     * off) */
+    int32_t* polish_first_invalid; /* first invalid step of the polished edge, 0 when valid */
+    int32_t* polish_cell;          /* region of the polished edge's end state, -1 when invalid */
+    uint8_t* polish_goal;          /* 1 when that end state lies in the goal set */
+    uint8_t* polish_accepted;      /* 1 when the polished edge replaced the node's edge */
 } kpx_dump_view;
 
 /* One record per completed iteration (ring of kpx_stats_capacity entries). */
@@ -365,8 +373,10 @@ typedef struct kpx_batch kpx_batch;
 
 /* Groups n host-array handles (not copied; the caller keeps them alive and
  * destroys them after the batch).  They must be distinct, share one stream,
- * have run the same number of iterations modulo 2, and have candidate
- * recording and edge polish off.  KPX_ERR_ARG otherwise;
+ * have run the same number of iterations modulo 2, and have edge polish off.
+ * A handle that records its expansions (kpx_set_dump) when the batch is made
+ * keeps recording in the batch, and kpx_read_dump reads them after each
+ * batched iteration.  KPX_ERR_ARG otherwise;
  * KPX_ERR_OOM / KPX_ERR_DEVICE on allocation or runtime failure. */
 int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out);
 
@@ -387,7 +397,8 @@ int kpx_batch_set_threads(kpx_batch* b, int32_t dynamics, int32_t threads);
  * on the handles' stream and before any later work on it; returns at once.
  * A query whose tree is full stops changing, as with kpx_iterate; each
  * handle's kpx_sync reports it.  KPX_ERR_STATE if a handle was iterated on
- * its own since the batch was made (an odd number of times). */
+ * its own since the batch was made (an odd number of times), turned edge
+ * polish on, or switched its recording on or off. */
 int kpx_batch_iterate(kpx_batch* b, int32_t n_iters);
 
 /* Waits for the batch's work and releases what the batch allocated (not the

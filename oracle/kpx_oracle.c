@@ -536,35 +536,54 @@ int64_t ora_select(const ora_problem* P, const ora_tree* T, int64_t* sel, int64_
     return n_sel;
 }
 
-/* Alg. 3 PruneNodes, one node after another, in the printed order.
- * "x is its region's best" is read as: the region's (cost, id) minimum is x
- * itself (ties by id, see key_less).  Terminal nodes are visited too; they
- * can never be their region's best again, so they stay terminal. */
+/* Whether node i holds its region's minimum: the region's (cost, id) entry
+ * names i itself (ties by id, see key_less). */
+static int region_best(const ora_tree* T, int64_t i)
+{
+    return T->tbl_id[T->cell[i]] == i;
+}
+
+/* Whether some proper ancestor of node i does not hold its region's minimum.
+ * It depends on the table and the parent links only. */
+static int ancestor_beaten(const ora_tree* T, int64_t i)
+{
+    for (int64_t p = T->parent[i]; p >= 0; p = T->parent[p])
+        if (!region_best(T, p)) return 1;
+    return 0;
+}
+
+/* PruneNodes (Alg. 3) over the node sets of Sec. IV-A, node by node.  With
+ * best = region_best(i), the dormancy count c = icount(i) and I_max:
+ *
+ *   status    best  count                   ancestor beaten  ->  status, count
+ *   any       no    -                       -                ->  TERMINAL
+ *   INACTIVE  yes   c + 1 > I_max           -                ->  ACTIVE, c + 1
+ *   INACTIVE  yes   c + 1 <= I_max          -                ->  INACTIVE, c + 1
+ *   ACTIVE    yes   c > I_max (woken once)  -                ->  ACTIVE
+ *   ACTIVE    yes   c <= I_max              yes              ->  INACTIVE
+ *   ACTIVE    yes   c <= I_max              no               ->  ACTIVE
+ *
+ * A dormant node that holds its region counts iterations and wakes past
+ * I_max; a woken node is never made dormant again; a node that lost its region
+ * leaves the tree's live sets for good.  Terminal nodes fall in the first row,
+ * since a key that was beaten never becomes a region's minimum again. */
 void ora_prune(const ora_problem* P, ora_tree* T)
 {
     for (int64_t i = 0; i < T->n_tree; ++i) {
-        const int best = T->tbl_id[T->cell[i]] == i;
-        /* Alg. 3: a dormant region-best node counts up and wakes past I_max */
-        if (best && T->status[i] == ORA_INACTIVE) {
-            T->icount[i] += 1;
-            if (T->icount[i] > P->i_max) {
-                T->status[i] = ORA_ACTIVE;
-                continue;
-            }
-        }
-        /* Alg. 3: a woken region-best node is left alone */
-        if (T->icount[i] > P->i_max && best) continue;
-        /* Alg. 3: beaten in its region -> terminal */
-        if (!best) {
+        if (!region_best(T, i)) {
             T->status[i] = ORA_TERMINAL;
             continue;
         }
-        /* Alg. 3: an ancestor beaten in its own region -> inactive */
-        for (int64_t p = T->parent[i]; p >= 0; p = T->parent[p]) {
-            if (T->tbl_id[T->cell[p]] != p) {
-                T->status[i] = ORA_INACTIVE;
-                break;
-            }
+        switch (T->status[i]) {
+        case ORA_INACTIVE:
+            T->icount[i] += 1;
+            if (T->icount[i] > P->i_max) T->status[i] = ORA_ACTIVE;
+            break;
+        case ORA_ACTIVE:
+            if (T->icount[i] <= P->i_max && ancestor_beaten(T, i)) T->status[i] = ORA_INACTIVE;
+            break;
+        default:
+            break;
         }
     }
 }
@@ -583,10 +602,13 @@ static int near_tie(double a, double b, double rel)
  * node's edge when the planner's own propagation finds it valid, it ends in
  * the node's region, and a goal node stays in the goal; a node that enters
  * the goal competes for the solution.  Its cost (TIME: the step count) does
- * not change.  Where a decision of the polished edge is flagged within band,
- * the hint (the other side's accept decision) is adopted. */
-static void polish_node(const ora_problem* P, ora_tree* T, int64_t i, int was_goal, const float* grown,
-                        const uint8_t* hint)
+ * not change.  The other side's decisions of the polished edge are passed per
+ * test: its first invalid step (negative: none given), the region and the goal
+ * bit of its end state; each is adopted only where the oracle's own decision
+ * of that same test lies within band, as for any propagated edge.  Returns 1
+ * when the polished edge replaced the node's edge. */
+static int polish_node(const ora_problem* P, ora_tree* T, int64_t i, int was_goal, const float* grown,
+                       int32_t hint_fi, const int64_t* hint_cell, const uint8_t* hint_goal)
 {
     orad_problem D;
     memset(&D, 0, sizeof(D));
@@ -621,28 +643,19 @@ static void polish_node(const ora_problem* P, ora_tree* T, int64_t i, int was_go
     float uf[ORA_MAX_CONTROL];
     for (int c = 0; c < 4; ++c) uf[c] = (float)u[c];
     ora_edge e;
-    ora_propagate_edge(P, x0, uf, n, -1, &e);
-    uint32_t fl = e.flags;
-    double xe[ORA_MAX_STATE + 1];
-    if (e.first_invalid == 0) {
-        memcpy(xe, e.xn, sizeof(double) * ORA_MAX_STATE);
-    } else {  /* the end state all the same, for an adopted decision */
-        double ud[ORA_MAX_CONTROL];
-        for (int c = 0; c < ORA_MAX_CONTROL; ++c) ud[c] = (double)uf[c];
-        ora_integrate(P, x0, ud, n, (double)P->dt, xe);
-    }
-    const int64_t cell = ora_cell_of(P, xe, NULL, &fl);
-    const int goal_now = ora_goal_test(P, xe, (double)P->goal_radius - (double)P->margin, NULL, &fl);
-    int accept = e.first_invalid == 0 && cell == T->cell[i] && (!was_goal || goal_now);
-    if (fl && hint) accept = *hint != 0;
-    if (!accept) return;
-    for (int k = 0; k < ORA_MAX_STATE; ++k) T->x[i * ORA_MAX_STATE + k] = xe[k];
+    ora_propagate_edge(P, x0, uf, n, hint_fi, &e);
+    if (e.first_invalid != 0) return 0;
+    const int64_t cell = ora_cell_of(P, e.xn, hint_cell, NULL);
+    const int goal_now = ora_goal_test(P, e.xn, (double)P->goal_radius - (double)P->margin, hint_goal, NULL);
+    if (cell != T->cell[i] || (was_goal && !goal_now)) return 0;
+    for (int k = 0; k < ORA_MAX_STATE; ++k) T->x[i * ORA_MAX_STATE + k] = e.xn[k];
     for (int c = 0; c < 4; ++c) T->u[i * ORA_MAX_CONTROL + c] = uf[c];
     if (!was_goal && goal_now && key_less(T->cost[i], i, T->sol_cost, T->sol_id)) {
         if (T->sol_id < 0) T->first_sol_iter = T->iter;
         T->sol_cost = T->cost[i];
         T->sol_id = i;
     }
+    return 1;
 }
 
 /* One iteration of Alg. 1: Propagate, PruneNodes, UpdateTree.
@@ -799,8 +812,13 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
                 grown[6 * b + a] = P->boxes[6 * b + a] - P->margin;
                 grown[6 * b + 3 + a] = P->boxes[6 * b + 3 + a] + P->margin;
             }
-        for (int64_t t = 0; t < n_surv; ++t)
-            polish_node(P, T, n_tree + t, C->goal[I[t]], grown, (H && H->polished) ? &H->polished[t] : NULL);
+        for (int64_t t = 0; t < n_surv; ++t) {
+            const int32_t hfi = (H && H->polish_first_invalid) ? H->polish_first_invalid[t] : -1;
+            const int64_t* hc = (H && H->polish_cell) ? &H->polish_cell[t] : NULL;
+            const uint8_t* hg = (H && H->polish_goal) ? &H->polish_goal[t] : NULL;
+            const int acc = polish_node(P, T, n_tree + t, C->goal[I[t]], grown, hfi, hc, hg);
+            if (C->polished) C->polished[t] = (uint8_t)acc;
+        }
         free(grown);
     }
     T->n_tree = n_tree + n_surv;

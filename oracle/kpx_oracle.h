@@ -115,6 +115,8 @@ typedef struct {
     uint8_t* goal;
     uint8_t* survivor;
     int64_t* new_index;     /* tree index when a survivor, else -1 */
+    uint8_t* polished;      /* per node inserted, in insertion order: 1 when edge
+                             * polish replaced its edge (NULL: not recorded) */
     int64_t substeps_total;
     int64_t k;              /* samples per selected node in this iteration */
 } ora_cands;
@@ -127,7 +129,13 @@ typedef struct {
     const int64_t* cell;
     const uint8_t* goal;
     const uint8_t* survivor;
-    const uint8_t* polished;   /* per node inserted this iteration, in insertion order */
+    /* edge polish, per node inserted this iteration (insertion order): the
+     * first invalid step of the polished edge (0 when valid) and the region and
+     * goal decisions at its end state; each is adopted only where the oracle's
+     * own decision of that test is flagged within band */
+    const int32_t* polish_first_invalid;
+    const int64_t* polish_cell;
+    const uint8_t* polish_goal;
 } ora_hints;
 
 typedef struct {

@@ -70,14 +70,14 @@ class CandsC(C.Structure):
         ("cap_slots", C.c_int64), ("n_slots", C.c_int64), ("parent", _i64p), ("u", _f32p),
         ("n", _i32p), ("xn", _f64p), ("valid", _u8p), ("first_invalid", _i32p),
         ("substeps", _i32p), ("flags", _u32p), ("cell", _i64p), ("cost", _f64p), ("goal", _u8p),
-        ("survivor", _u8p), ("new_index", _i64p), ("substeps_total", C.c_int64),
-        ("k", C.c_int64),
+        ("survivor", _u8p), ("new_index", _i64p), ("polished", _u8p),
+        ("substeps_total", C.c_int64), ("k", C.c_int64),
     ]
 
 
 class HintsC(C.Structure):
     _fields_ = [("first_invalid", _i32p), ("cell", _i64p), ("goal", _u8p), ("survivor", _u8p),
-                ("polished", _u8p)]
+                ("polish_first_invalid", _i32p), ("polish_cell", _i64p), ("polish_goal", _u8p)]
 
 
 class EdgeC(C.Structure):
@@ -311,12 +311,13 @@ class Cands:
         self.goal = np.zeros(n, np.uint8)
         self.survivor = np.zeros(n, np.uint8)
         self.new_index = np.zeros(n, np.int64)
+        self.polished = np.zeros(n, np.uint8)
         s = CandsC()
         s.cap_slots = int(cap_slots)
         for name, ct in (("parent", _i64p), ("u", _f32p), ("n", _i32p), ("xn", _f64p),
                          ("valid", _u8p), ("first_invalid", _i32p), ("substeps", _i32p),
                          ("flags", _u32p), ("cell", _i64p), ("cost", _f64p), ("goal", _u8p),
-                         ("survivor", _u8p), ("new_index", _i64p)):
+                         ("survivor", _u8p), ("new_index", _i64p), ("polished", _u8p)):
             setattr(s, name, _ptr(getattr(self, name), ct))
         self.c = s
 
@@ -337,7 +338,7 @@ class Cands:
         k = self.n_slots
         return {name: getattr(self, name)[:k].copy() for name in (
             "parent", "u", "n", "xn", "valid", "first_invalid", "substeps", "flags", "cell",
-            "cost", "goal", "survivor", "new_index")}
+            "cost", "goal", "survivor", "new_index", "polished")}
 
 
 class Tree:
@@ -384,7 +385,8 @@ class Tree:
             hc = HintsC()
             for name, dt, ct in (("first_invalid", np.int32, _i32p), ("cell", np.int64, _i64p),
                                  ("goal", np.uint8, _u8p), ("survivor", np.uint8, _u8p),
-                                 ("polished", np.uint8, _u8p)):
+                                 ("polish_first_invalid", np.int32, _i32p),
+                                 ("polish_cell", np.int64, _i64p), ("polish_goal", np.uint8, _u8p)):
                 if hints.get(name) is not None:
                     a = np.ascontiguousarray(hints[name], dtype=dt)
                     keep.append(a)

@@ -169,18 +169,20 @@ def new_report():
 
 
 def polished_nodes(pre, post, dump):
-    """Nodes the GPU inserted in this iteration whose control is not the
-    sampled one (edge polish), as a mask over the post-iteration tree, and
-    the per-inserted-node hint the oracle adopts for flagged decisions."""
+    """The GPU's edge-polish decisions of this iteration: a mask over the
+    post-iteration tree of the nodes whose polished edge it accepted, and the
+    per-inserted-node hints (first invalid step, end region, goal bit of the
+    polished edge) that the oracle may adopt where its own decision of that
+    same test is flagged within band."""
     n0, n1 = int(pre["counters"]["n_tree"]), int(post["counters"]["n_tree"])
-    slots = np.flatnonzero(dump["survivor"])
-    assert len(slots) == n1 - n0
-    sampled = dump["control"][:, slots]
-    got = post["control"][:, n0:n1]
-    hint = np.any(got != sampled, axis=0).astype(np.uint8)
+    acc = dump["polish_accepted"].astype(bool)
+    assert acc.size == n1 - n0, (acc.size, n1 - n0)
     mask = np.zeros(n1, bool)
-    mask[n0:n1] = hint.astype(bool)
-    return mask, hint
+    mask[n0:n1] = acc
+    hints = {"polish_first_invalid": dump["polish_first_invalid"].astype(np.int32),
+             "polish_cell": dump["polish_cell"].astype(np.int64),
+             "polish_goal": dump["polish_goal"].astype(np.uint8)}
+    return mask, hints
 
 
 def lockstep(O, P, planner, iterations, report=None):
@@ -197,13 +199,17 @@ def lockstep(O, P, planner, iterations, report=None):
         post = planner.snapshot()
         tr = oracle_tree_from_snapshot(O, P, pre)
         report["n_tree_before"] = tr.n_tree
-        mask, hint = polished_nodes(pre, post, dump)
+        mask, polish_hints = polished_nodes(pre, post, dump)
         hints = hints_from_dump(dump)
-        hints["polished"] = hint
+        hints.update(polish_hints)
         rc = tr.step(hints)
         assert rc == O.OK
         compare_candidates(P, tr, dump, report)
+        if P.c.polish_steps > 0:
+            # the accept decision of every polished edge, exactly
+            n_ins = int(post["counters"]["n_tree"]) - report["n_tree_before"]
+            np.testing.assert_array_equal(dump["polish_accepted"], tr.cands.polished[:n_ins])
         compare_trees(P, tr, post, report, polished=mask)
-        report["polished"] += int(hint.sum())
+        report["polished"] += int(mask.sum())
         report["iterations"] += 1
     return report

@@ -110,6 +110,9 @@ struct DevPtrs {
     float* d_u;
     int* d_n;
     int* d_fi;
+    int* d_pfi;          // dump of the edge polish, per node inserted: first invalid step,
+    int* d_pcell;        //   region of the polished end state,
+    uint8_t* d_pflag;    //   bit 0 accepted, bit 1 end state in the goal
     int* path;           // solution extraction
     float* path_x;
     float* path_u;
@@ -121,6 +124,13 @@ struct DevPtrs {
 // ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -347,7 +357,8 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     }
     const Hot<DYN> H = make_hot<DYN>(P);
     const int lane = threadIdx.x & 63;
-    int my_valid = 0, my_steps = 0;
+    int my_valid = 0;
+    unsigned long long my_steps = 0;  // substeps of this lane's slots (64-bit: up to 2^28 slots of 32767 steps)
 
     for (int base = blk * chunk; base < S; base += nblk * chunk) {
         const int cnt = min(chunk, S - base);
@@ -646,7 +657,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         }
     }
     const int wv = wave_sum(my_valid);
-    const int ws = wave_sum(my_steps);
+    const unsigned long long ws = wave_sum64(my_steps);
     if (lane == 0) {
         if (wv) atomicAdd(&st->n_valid_acc, wv);
         if (ws) atomicAdd(&st->substeps_acc, (unsigned long long)ws);
@@ -1090,17 +1101,25 @@ __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T
 #pragma unroll
     for (int c = 0; c < 4; ++c) ur[c] = u[c] * (rev_control(kQUAD12, c) ? kInv2Pi : 1.f);
     bool ok = true;
-    for (int k = 0; k < n && ok; ++k) {
+    int fi = 0;
+    for (int k = 1; k <= n && ok; ++k) {
         rk4<kQUAD12, kTIME>(H, x, ur, len);
         ok = in_bounds<kQUAD12>(H, x, P.os_lo, P.os_hi);
         for (int b = 0; b < nb; ++b) ok = ok && !in_box(sbox + 2 * b, x[0], x[1], x[2]);
+        if (!ok) fi = k;
     }
-    if (!ok) return;
     float xe[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) xe[c] = x[c] * (rev_state(kQUAD12, c) ? k2Pi : 1.f);
-    const bool goal_now = in_goal(P, xe);
-    if (cell_of(P, xe, xe + 6) != T.cell[i] || (was_goal && !goal_now)) return;
+    const bool goal_now = ok && in_goal(P, xe);
+    const int cell = ok ? cell_of(P, xe, xe + 6) : -1;
+    const bool accept = ok && cell == T.cell[i] && (!was_goal || goal_now);
+    if (T.d_pfi) {  // the decisions, for the oracle's replay
+        T.d_pfi[t] = fi;
+        T.d_pcell[t] = cell;
+        T.d_pflag[t] = (uint8_t)((accept ? 1 : 0) | (goal_now ? 2 : 0));
+    }
+    if (!accept) return;
 #pragma unroll
     for (int q = 0; q < 12; ++q) T.x[(long long)q * P.cap + i] = xe[q];
 #pragma unroll
@@ -1318,6 +1337,9 @@ __device__ __forceinline__ DevPtrs global_ptrs(const DevPtrs& src)
     T.d_u = as_global(T.d_u);
     T.d_n = as_global(T.d_n);
     T.d_fi = as_global(T.d_fi);
+    T.d_pfi = as_global(T.d_pfi);
+    T.d_pcell = as_global(T.d_pcell);
+    T.d_pflag = as_global(T.d_pflag);
     T.path = as_global(T.path);
     T.path_x = as_global(T.path_x);
     T.path_u = as_global(T.path_u);
@@ -1466,6 +1488,11 @@ void for_each_array(const Sizes& z, F&& f)
     f("d_u", sizeof(float) * z.m * S);
     f("d_n", sizeof(int) * S);
     f("d_fi", sizeof(int) * S);
+    // nodes inserted by one iteration: at most min(regions, slots)
+    const size_t SU = std::min(S, (size_t)z.n_cells_cap);
+    f("d_pfi", sizeof(int) * SU);
+    f("d_pcell", sizeof(int) * SU);
+    f("d_pflag", SU);
     f("path", sizeof(int) * kMaxPath);
     f("path_x", sizeof(float) * KPX_MAX_STATE * kMaxPath);
     f("path_u", sizeof(float) * KPX_MAX_CONTROL * kMaxPath);
@@ -1621,7 +1648,8 @@ int validate(const kpx_problem* p, const kpx_params* q, Sizes* z, std::string* w
         for (int k = 0; k < 5; ++k)
             if (!finite(p->dyn_params[k]) || !(p->dyn_params[k] > 0.f)) return bad("quadrotor parameters");
     if (!finite(q->dt) || !(q->dt > 0.f)) return bad("dt");
-    if (q->steps_min < 1 || q->steps_max < q->steps_min || q->steps_max > 65535) return bad("steps range");
+    // step counts and first invalid steps travel as 16-bit signed values
+    if (q->steps_min < 1 || q->steps_max < q->steps_min || q->steps_max > 32767) return bad("steps range");
     long long nc = 1;
     for (int a = 0; a < 3; ++a) {
         if (q->grid[a] < 1 || q->grid[a] > (1 << 20)) return bad("grid");
@@ -1879,6 +1907,9 @@ void carve(kpx_handle* h)
     T.d_u = (float*)ptrs[k++];
     T.d_n = (int*)ptrs[k++];
     T.d_fi = (int*)ptrs[k++];
+    T.d_pfi = (int*)ptrs[k++];
+    T.d_pcell = (int*)ptrs[k++];
+    T.d_pflag = (uint8_t*)ptrs[k++];
     T.path = (int*)ptrs[k++];
     T.path_x = (float*)ptrs[k++];
     T.path_u = (float*)ptrs[k++];
@@ -1905,6 +1936,9 @@ DevPtrs kernel_ptrs(const kpx_handle* h)
         T.d_u = nullptr;
         T.d_n = nullptr;
         T.d_fi = nullptr;
+        T.d_pfi = nullptr;
+        T.d_pcell = nullptr;
+        T.d_pflag = nullptr;
     }
     return T;
 }
@@ -2063,6 +2097,7 @@ struct kpx_batch {
     bool graph_on = false;
     hipGraphExec_t exec[2] = {nullptr, nullptr};  // two iterations from state parity 0 / 1
     std::vector<int> cells;         // each handle's region count when the batch was made
+    std::vector<char> dump;         // ... and whether it recorded its expansions (fixed since)
     // groups after the first run their propagate and insert on side streams
     // forked from and joined back to the batch stream, so that the models'
     // kernels overlap (each is bound by its longest edge, not by the machine)
@@ -2517,9 +2552,26 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* v, int64_t* n_slots)
         }
     std::vector<uint8_t> flag(S);
     if ((rc = get(flag.data(), h->T.cflag, S))) return rc;
+    // edge polish decisions, one per inserted node
+    const size_t NI = (size_t)std::max<int64_t>(0, c.n_survivors);
+    const bool pol = h->polish_steps > 0 && NI > 0;
+    std::vector<uint8_t> pflag(pol ? NI : 1, 0);
+    if (pol) {
+        if (v->polish_first_invalid && (rc = get(v->polish_first_invalid, h->T.d_pfi, sizeof(int) * NI))) return rc;
+        if (v->polish_cell && (rc = get(v->polish_cell, h->T.d_pcell, sizeof(int) * NI))) return rc;
+        if ((rc = get(pflag.data(), h->T.d_pflag, NI))) return rc;
+    }
     KPX_HIP(h, hipStreamSynchronize(h->stream));
     if (v->goal)
         for (size_t s = 0; s < S; ++s) v->goal[s] = (flag[s] >> 1) & 1;
+    if (!pol) {
+        if (v->polish_first_invalid) std::memset(v->polish_first_invalid, 0, sizeof(int32_t) * NI);
+        if (v->polish_cell) std::memset(v->polish_cell, 0, sizeof(int32_t) * NI);
+    }
+    for (size_t t = 0; t < NI; ++t) {
+        if (v->polish_accepted) v->polish_accepted[t] = pol ? (pflag[t] & 1) : 0;
+        if (v->polish_goal) v->polish_goal[t] = pol ? ((pflag[t] >> 1) & 1) : 0;
+    }
     return KPX_OK;
 }
 
@@ -2746,8 +2798,7 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
     *out = nullptr;
     for (int q = 0; q < n; ++q) {
         const kpx_handle* h = handles[q];
-        if (!h || h->stream != handles[0]->stream || h->cur != handles[0]->cur || h->dump_on ||
-            h->polish_steps > 0)
+        if (!h || h->stream != handles[0]->stream || h->cur != handles[0]->cur || h->polish_steps > 0)
             return KPX_ERR_ARG;
         for (int r = 0; r < q; ++r)
             if (handles[r] == h) return KPX_ERR_ARG;
@@ -2755,7 +2806,10 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
     kpx_batch* b = new (std::nothrow) kpx_batch;
     if (!b) return KPX_ERR_OOM;
     b->hs.assign(handles, handles + n);
-    for (int q = 0; q < n; ++q) b->cells.push_back(handles[q]->z.n_cells);
+    for (int q = 0; q < n; ++q) {
+        b->cells.push_back(handles[q]->z.n_cells);
+        b->dump.push_back(handles[q]->dump_on ? 1 : 0);
+    }
     b->user = handles[0]->stream;
     b->cur = handles[0]->cur;
     int dev = 0, lds_max = 0;
@@ -2895,9 +2949,12 @@ int kpx_batch_set_graph(kpx_batch* b, int32_t enable)
 int kpx_batch_iterate(kpx_batch* b, int32_t n_iters)
 {
     if (!b || n_iters < 0) return KPX_ERR_ARG;
-    for (kpx_handle* h : b->hs)
-        if (h->cur != b->cur || h->dump_on || h->polish_steps > 0)
-            return bfail(b, KPX_ERR_STATE, "a handle left the batch's step or has edge polish on");
+    for (size_t q = 0; q < b->hs.size(); ++q) {
+        const kpx_handle* h = b->hs[q];
+        if (h->cur != b->cur || h->polish_steps > 0 || (h->dump_on ? 1 : 0) != b->dump[q])
+            return bfail(b, KPX_ERR_STATE,
+                         "a handle left the batch's step, has edge polish on or changed its recording");
+    }
     for (size_t q = 0; q < b->hs.size(); ++q)
         if (b->hs[q]->z.n_cells != b->cells[q]) return bfail(b, KPX_ERR_STATE, "a handle was refined");
     if (n_iters == 0) return KPX_OK;

@@ -82,7 +82,8 @@ class DumpViewC(C.Structure):
     _fields_ = [
         ("capacity", C.c_int64), ("parent", _vp), ("control", _vp), ("steps", _vp),
         ("state", _vp), ("first_invalid", _vp), ("cell", _vp), ("key", _vp), ("goal", _vp),
-        ("survivor", _vp),
+        ("survivor", _vp), ("polish_first_invalid", _vp), ("polish_cell", _vp),
+        ("polish_goal", _vp), ("polish_accepted", _vp),
     ]
 
 
@@ -363,6 +364,8 @@ class Planner:
             "first_invalid": np.zeros(cap, np.int32), "cell": np.zeros(cap, np.int32),
             "key": np.zeros(cap, np.uint64), "goal": np.zeros(cap, np.uint8),
             "survivor": np.zeros(cap, np.uint8),
+            "polish_first_invalid": np.zeros(cap, np.int32), "polish_cell": np.zeros(cap, np.int32),
+            "polish_goal": np.zeros(cap, np.uint8), "polish_accepted": np.zeros(cap, np.uint8),
         }
         v = DumpViewC()
         v.capacity = cap
@@ -375,6 +378,9 @@ class Planner:
         out["state"] = a["state"][: self.d, :k]
         out["control"] = a["control"][: self.m, :k]
         out["n_slots"] = k
+        n_ins = int(self.counters()["n_survivors"])
+        for name in ("polish_first_invalid", "polish_cell", "polish_goal", "polish_accepted"):
+            out[name] = a[name][:n_ins]
         return out
 
     def set_polish(self, steps: int = 3, lr: float = 0.01, w_ctrl: float = 0.1, w_obst: float = 1.0,

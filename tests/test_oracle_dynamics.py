@@ -107,6 +107,65 @@ def test_quad_isotropic_rates_are_linear_in_time(ora):
     np.testing.assert_allclose(z[9:12], x0[9:12] + 30 * 0.005 * tau / J, atol=1e-12)
 
 
+# The path length of the quadrotor, the speed |v| integrated as a 13th RK4
+# component (Assumption 1's additive cost; the model is cited in Sec. V).
+# Each pin below makes a wrong velocity index, a dropped or doubled component
+# or a rate read from another block of the state fail.
+
+def test_quad_path_length_free_fall_from_rest(ora):
+    # speed g t grows linearly from rest, which RK4 integrates exactly:
+    # length = g T^2 / 2, whatever the (constant) attitude
+    P, w = _quad(ora)
+    _, _, g = _consts(w)
+    x0 = np.zeros(12)
+    x0[:3] = (0.5, 0.5, 0.9)
+    x0[3:6] = (0.3, -0.2, 1.1)
+    n, h = 40, 0.005
+    z = ora.integrate(P, x0, [0, 0, 0, 0], n, h)
+    T = n * h
+    assert abs(z[12] - 0.5 * g * T * T) < 1e-14
+
+
+def test_quad_path_length_hover_at_constant_velocity(ora):
+    # level attitude and thrust m g: the velocity stays put, length = |v| T
+    P, w = _quad(ora)
+    m, _, g = _consts(w)
+    x0 = np.zeros(12)
+    x0[:3] = (0.2, 0.6, 0.4)
+    x0[5] = 0.7
+    x0[6:9] = (0.3, -0.4, 0.5)
+    n, h = 50, 0.005
+    z = ora.integrate(P, x0, [m * g, 0, 0, 0], n, h)
+    T = n * h
+    assert abs(z[12] - math.sqrt(0.5) * T) < 1e-14
+    np.testing.assert_allclose(z[6:9], x0[6:9], atol=1e-15)
+
+
+def test_quad_path_length_ballistic_closed_form(ora):
+    # thrust off, initial velocity (vx, vy, vz): the horizontal speed c stays
+    # constant and the vertical one is vz - g t, so with F(s) =
+    # (s sqrt(c^2 + s^2) + c^2 asinh(s / c)) / 2 the length is
+    # (F(vz) - F(vz - g T)) / g.  RK4 converges to it at fourth order.
+    P, w = _quad(ora)
+    _, _, g = _consts(w)
+    x0 = np.zeros(12)
+    x0[:3] = (0.3, 0.3, 0.5)
+    x0[3:6] = (0.1, 0.2, -0.4)
+    x0[6:9] = (0.4, -0.3, 0.9)
+    c = 0.5
+
+    def F(s):
+        return 0.5 * (s * math.sqrt(c * c + s * s) + c * c * math.asinh(s / c))
+
+    T = 0.2
+    exact = (F(0.9) - F(0.9 - g * T)) / g
+    errs = []
+    for n in (10, 20, 40):
+        errs.append(abs(ora.integrate(P, x0, [0, 0, 0, 0], n, T / n)[12] - exact))
+    assert errs[-1] < 1e-8, errs
+    assert 12.0 < errs[0] / errs[1] < 20.0 and 12.0 < errs[1] / errs[2] < 20.0, errs
+
+
 def _rot(phi, theta, psi):
     cx, sx = math.cos(phi), math.sin(phi)
     cy, sy = math.cos(theta), math.sin(theta)
