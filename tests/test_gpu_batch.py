@@ -106,9 +106,12 @@ def test_batch_rejects_bad_groupings(kpx):
     with pytest.raises(kpx.KPXError):
         kpx.Batch([ps[0], ps[0]])  # the same handle twice
     ps[1].set_dump(True)
+    b = kpx.Batch(ps)  # a recording handle keeps recording in the batch
+    b.iterate(1)
+    ps[1].set_dump(False)  # ... but may not switch it off while batched
     with pytest.raises(kpx.KPXError):
-        kpx.Batch(ps)  # candidate recording on
-    ps[1].set_dump(False)
+        b.iterate(1)
+    b.close()
     ps[2].iterate(1)  # out of step with the others
     with pytest.raises(kpx.KPXError):
         kpx.Batch(ps)
