@@ -317,6 +317,18 @@ int kpx_clock_rate_khz(kpx_handle* h, int64_t* out);
  * current device with its own short-lived buffers. */
 int kpx_philox(const uint32_t* counter_key, int64_t n, uint32_t* out);
 
+/* kpx_philox without any allocation, for callers that cannot allocate device
+ * memory (tight loops, code that forbids hipMalloc): the same records and
+ * results, staged through a buffer the library holds in static device memory
+ * (10 * KPX_PHILOX_STATIC_MAX words, 2.5 MiB, kept by each device it runs on
+ * until the process ends).  It runs on the current device and the default
+ * stream and waits for its copies.  Every call on a device shares that
+ * device's buffer: calls that overlap on one device (from several host
+ * threads) race.  KPX_ERR_ARG for n > KPX_PHILOX_STATIC_MAX, n < 0 or NULL
+ * buffers; KPX_ERR_DEVICE when a runtime call fails. */
+#define KPX_PHILOX_STATIC_MAX 65536
+int kpx_philox_static(const uint32_t* counter_key, int64_t n, uint32_t* out);
+
 /* Releases what the library allocated (not a caller workspace).  NULL is ok. */
 int kpx_destroy(kpx_handle* h);
 

@@ -25,6 +25,6 @@ differentiable quadrotor edge rollout.
 
 from .kpx import (  # noqa: F401
     ACTIVE, INACTIVE, TERMINAL, Batch, KPXError, Planner, lib, philox, workspace_bytes,
-    status_string, OK, FULL,
+    status_string, OK, FULL, ERR_ARG, PHILOX_STATIC_MAX, philox_static,
 )
 from .diff import Rollout, edge_loss  # noqa: F401,E402

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -2756,6 +2757,47 @@ int kpx_philox(const uint32_t* counter_key, int64_t n, uint32_t* out)
     (void)hipFree(din);
     (void)hipFree(dout);
     return rc;
+}
+
+// Staging for kpx_philox_static: KPX_PHILOX_STATIC_MAX input records of 6
+// words, then as many output records of 4.  Each device holds its own copy
+// for the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr long long kPhiloxStaticWords = 10LL * KPX_PHILOX_STATIC_MAX;
+static __device__ __align__(256) uint32_t scratch[kPhiloxStaticWords];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint32_t* g_scratch_ptr[kMaxDevices];  // per device; null until looked up
+
+// The device address of `scratch` on the current device (looked up once per
+// device), or null on failure.
+static uint32_t* scratch_on_current_device()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+int kpx_philox_static(const uint32_t* counter_key, int64_t n, uint32_t* out)
+{
+    if (n < 0 || n > KPX_PHILOX_STATIC_MAX || (n > 0 && (!counter_key || !out))) return KPX_ERR_ARG;
+    if (n == 0) return KPX_OK;
+    uint32_t* din = scratch_on_current_device();
+    if (!din) return KPX_ERR_DEVICE;
+    uint32_t* dout = din + 6LL * KPX_PHILOX_STATIC_MAX;
+    if (hipMemcpy(din, counter_key, sizeof(uint32_t) * 6 * n, hipMemcpyHostToDevice) != hipSuccess)
+        return KPX_ERR_DEVICE;
+    k_philox_eval<<<(unsigned)((n + 255) / 256), 256>>>(din, n, dout);
+    if (hipGetLastError() != hipSuccess) return KPX_ERR_DEVICE;
+    if (hipMemcpy(out, dout, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost) != hipSuccess) return KPX_ERR_DEVICE;
+    return KPX_OK;
 }
 
 int kpx_destroy(kpx_handle* h)

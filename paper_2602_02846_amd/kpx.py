@@ -139,6 +139,7 @@ def lib():
         L.kpx_read_stats.argtypes = [_vp, i64, i64, C.POINTER(IterStatsC)]
         L.kpx_clock_rate_khz.argtypes = [_vp, C.POINTER(i64)]
         L.kpx_philox.argtypes = [_vp, i64, _vp]
+        L.kpx_philox_static.argtypes = [_vp, i64, _vp]
         L.kpx_destroy.argtypes = [_vp]
         L.kpx_status_string.argtypes = [C.c_int]
         L.kpx_status_string.restype = C.c_char_p
@@ -154,7 +155,7 @@ def lib():
         for name in ("kpx_workspace_bytes", "kpx_create", "kpx_iterate", "kpx_sync",
                      "kpx_counters_read", "kpx_solution", "kpx_snapshot", "kpx_set_dump",
                      "kpx_read_dump", "kpx_set_timing", "kpx_read_timing", "kpx_stats_capacity",
-                     "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_destroy",
+                     "kpx_read_stats", "kpx_clock_rate_khz", "kpx_philox", "kpx_philox_static", "kpx_destroy",
                      "kpx_batch_create", "kpx_batch_set_graph", "kpx_batch_iterate",
                      "kpx_batch_destroy", "kpx_set_polish", "kpx_refine", "kpx_set_timing_every",
                      "kpx_set_cost_first", "kpx_batch_set_threads"):
@@ -241,6 +242,21 @@ def philox(counter_key: np.ndarray) -> np.ndarray:
     rc = lib().kpx_philox(ck.ctypes.data, ck.shape[0], out.ctypes.data)
     if rc != OK:
         raise KPXError(rc)
+    return out
+
+
+PHILOX_STATIC_MAX = 65536  # KPX_PHILOX_STATIC_MAX
+
+
+def philox_static(counter_key: np.ndarray) -> np.ndarray:
+    """philox() through kpx_philox_static: no device allocation, at most
+    PHILOX_STATIC_MAX rows per call."""
+    ck = np.ascontiguousarray(counter_key, dtype=np.uint32).reshape(-1, 6)
+    out = np.zeros((ck.shape[0], 4), dtype=np.uint32)
+    rc = lib().kpx_philox_static(ck.ctypes.data, ck.shape[0], out.ctypes.data)
+    if rc != OK:
+        raise KPXError(rc, f"kpx_philox_static: {ck.shape[0]} rows (at most {PHILOX_STATIC_MAX})"
+                       if rc == ERR_ARG else "")
     return out
 
 
