@@ -1,18 +1,30 @@
-"""Benchmark: propagated edges/s of the Kino-PAX+ iteration on one MI355X.
+"""Benchmark: propagated edges/s of Kino-PAX+ queries on one MI355X.
 
-A step is one planner iteration (select -> propagate -> prune -> insert) of one
-query on the 12D quadrotor workload (4096 nodes x 32 samples per iteration,
-64-box wall with two slots, 16^3 x 2^3 regions, tree capacity 2^21).  Inputs
-live in HBM before timing starts; every count stays on the device.
+A step is one query: a planner run of --iters iterations (select ->
+propagate -> prune -> insert, 200 by default) from the root, on the seeded
+scene of that query.  --steps queries (seeds 0 .. steps-1) are timed after
+--warmup untimed ones; each query's tree and scene are resident in HBM before
+its run starts, and every count stays on the device.
 
-Prints one JSON line.  `roofline` covers the dominant kernel (propagate, bound
-by float32 ALU work); `cpu_baseline` is the float64 oracle replaying the same
-workload on the host from the GPU tree at the start of the timed region.
+value = the median over the timed queries of that query's propagated edges
+(every expansion integrated, valid or not: the sum over its iterations of
+selected nodes x samples per node) divided by its device-timed span (the
+device wall clock from the first iteration's start to the last one's end).
+The default workload is the 12D quadrotor (4096 nodes x 32 samples per
+iteration, 64-box wall with two slots, 16^3 x 2^3 regions, tree capacity 2^21).
+
+`roofline` covers the dominant kernel (propagate, bound by float32 ALU work),
+from HIP events around the kernels of every `--timing-every`-th iteration of
+the timed queries; `steady_state` repeats the measurement over a window of
+iterations in which the selection is full; `cpu_baseline` is the float64
+oracle running the first query from its root on every host core (and on one).
+Prints one JSON line.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,43 +48,118 @@ FLOPS_PER_SUBSTEP = {
     ("QUAD12", "TIME"): 324, ("QUAD12", "PATH_LENGTH"): 324 + 13 + 4 * 6,
     ("DUBINS6", "TIME"): 110, ("DUBINS6", "PATH_LENGTH"): 110 + 13,
 }
-PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 FLOP/clk)
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 FLOP/clk, packed)
+PEAK_FP32_UNPACKED = 78.6     # ... without packed FP32 (this build issues none)
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2602_02846_amd/csrc/kpx.hip", "paper_2602_02846_amd/csrc/kpx_device.hpp")
+KERNELS = ("propagate", "prune_flags", "insert", "finalize_select")
+DIMS = {"DI6": (6, 3), "QUAD12": (12, 4), "DUBINS6": (6, 3)}
+BUDGETS_MS = (5.0, 10.0, 20.0, 40.0)
 
 
-def measured_traffic(workload):
-    """HBM bytes per propagate launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a plain copy), or
-    None when there is none or the kernel sources changed since it was taken."""
-    import hashlib
+def kernel_bytes(prob, prm, st):
+    """Algorithmic bytes per launch of each iteration kernel, per iteration of
+    the stats records `st` (what the step must read and write, not what this
+    implementation happens to move):
+      prune_flags  every region: table key 8 + activity byte 1; every region a
+                   tree node still owns: status and I_count read and written 4;
+                   every slot: flag 1 + survivor byte 1; every valid slot: its
+                   key 8, region 4 and the region's table entry 8
+      insert       every slot: survivor byte 1; per 256-slot tile: count 4;
+                   every survivor: end state 4d, key 8, region 4, parent 4
+                   read; state 4d, control 4m, steps 2, parent 4, cost 4,
+                   region 4, status 1, I_count 1, table entry 8 written
+      finalize     every region: activity 1 + owner 4; every selected node
+                   of the next iteration: its index 4"""
+    d, m = DIMS[prob.dynamics]
+    cells = float(prm.n_cells)
+    S = st["n_select"].astype(np.float64) * st["samples_per_node"]
+    nv = st["n_valid"].astype(np.float64)
+    ns = st["n_survivors"].astype(np.float64)
+    nl = st["n_live"].astype(np.float64)
+    nsel_next = np.append(st["n_select"][1:], st["n_select"][-1:]).astype(np.float64)
+    prune = cells * 9 + nl * 4 + S * 2 + nv * 20
+    insert = S + np.ceil(S / 256) * 4 + ns * (4 * d + 16 + 4 * d + 4 * m + 28)
+    final = cells * 5 + nsel_next * 4
+    return {"prune_flags": prune, "insert": insert, "finalize_select": final}
 
-    path = os.path.join(ROOT, "profiles", f"propagate_{workload}_traffic.txt")
-    if not os.path.exists(path):
-        return None
+
+def source_sha():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def bench_args_key(a):
+    """The arguments that decide which kernels run (a counter profile of the
+    same command covers the same launches)."""
+    return (f"--workload {a.workload} --steps {a.steps} --warmup {a.warmup} --iters {a.iters}"
+            + (f" --polish {a.polish}" if a.polish else "") + (" --cost-first" if a.cost_first else "")
+            + (f" --refine-at {a.refine_at}" if a.refine_at else ""))
+
+
+def profile_fields(a, kind):
+    """key: value lines of the committed profile summary profiles/<workload>_<kind>.txt,
+    or None unless it was taken on the current kernel sources with the same
+    bench arguments."""
+    path = os.path.join(ROOT, "profiles", f"{a.workload}_{kind}.txt")
+    if not os.path.exists(path):
+        return None
     fields = {}
     with open(path) as fh:
         for line in fh:
             k, sep, v = line.partition(":")
             if sep:
                 fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256") != h.hexdigest():
+    if fields.get("kernel_source_sha256") != source_sha() or fields.get("bench_args") != bench_args_key(a):
         return None
-    try:
-        return int(fields["propagate_hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+    return fields
+
+
+def measured_trace(a):
+    """Average kernel-trace duration (us) per launch of each iteration kernel
+    over the timed queries, from the committed rocprofv3 summary of the same
+    command, or None."""
+    f = profile_fields(a, "kernel_trace")
+    if f is None:
         return None
+    out = {}
+    for k in KERNELS:
+        try:
+            out[k] = float(f[f"{k}_trace_us_per_launch"])
+        except (KeyError, ValueError):
+            pass
+    return out or None
+
+
+def measured_traffic(a):
+    """HBM bytes per launch of each iteration kernel from the committed
+    rocprofv3 counter summary of the same bench command (FETCH_SIZE and
+    WRITE_SIZE, calibrated against a plain copy), or None when there is none,
+    the kernel sources changed since it was taken or it profiled other
+    arguments."""
+    fields = profile_fields(a, "traffic")
+    if fields is None:
+        return None
+    out = {}
+    for k in KERNELS:
+        try:
+            out[k] = int(fields[f"{k}_hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            pass
+    return out or None
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=150)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100,
+                    help="timed queries: seeds 0 .. steps-1, each a run of --iters iterations")
+    ap.add_argument("--warmup", type=int, default=3,
+                    help="untimed queries before them (seeds 0 .. warmup-1 on planners of their own)")
+    ap.add_argument("--iters", type=int, default=200, help="iterations of every query")
     ap.add_argument("--workload", default="quad12",
                     choices=["di6", "quad12", "dubins6", "di6_paper", "quad12_paper", "dubins6_paper",
                              "di6_paper_small", "quad12_paper_small", "dubins6_paper_small",
@@ -80,29 +167,27 @@ def parse():
     ap.add_argument("--queries", type=int, default=256, help="queries of the batch256 workload")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batch256: skip the sequential per-query comparison")
-    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=0, help="batch256 and diff65536: scene seed")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
-                    help="bound on the oracle CPU-baseline sample")
+                    help="bound on the oracle CPU-baseline sample on every host core")
+    ap.add_argument("--cpu-seconds-single", type=float, default=8.0,
+                    help="bound on the oracle sample on one core")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--solution-seeds", type=int, default=100,
-                    help="queries (seeds) for the median time to first solution and cost")
-    ap.add_argument("--solution-iters", type=int, default=200,
-                    help="iteration budget of each of those queries")
     ap.add_argument("--polish", type=int, default=0,
                     help="edge polish steps of every inserted node (quadrotor, TIME cost); 0 = plain")
     ap.add_argument("--cost-first", action="store_true",
                     help="propagate in the exact cost-first form (obstacle tests only for edges "
                          "that can still be their region's minimum)")
     ap.add_argument("--tree-growth", type=int, default=0,
-                    help="also run the workload this many iterations and time every kernel in "
+                    help="also run the first query this many iterations and time every kernel in "
                          "windows as the tree grows (prune and insert against tree size)")
     ap.add_argument("--refine-at", type=int, default=0,
-                    help="solution runs: halve the region cells per axis after this many iterations")
+                    help="halve the region cells per axis after this many iterations of each query")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--timing-every", type=int, default=8,
-                    help="bracket the kernels with HIP events in every n-th timed iteration")
-    ap.add_argument("--time-all", action="store_true",
-                    help="HIP events around all four kernels (default: propagate only)")
+                    help="bracket the kernels with HIP events in every n-th iteration of each query")
+    ap.add_argument("--steady-window", type=int, default=20,
+                    help="iterations of the steady-state window (0: none)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
     return ap.parse_args()
@@ -112,12 +197,11 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {a.gpus} is not supported "
-              "(the planner query runs on a single device)", file=sys.stderr)
+              "(a planner query runs on a single device; this build uses no second GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
 
     import paper_2602_02846_amd as K
-    import workloads as W
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -135,84 +219,235 @@ def main():
         return bench_batch(a)
     if a.workload == "diff65536":
         return bench_diff(a)
-    w = W.make_workload(a.workload, a.seed)
-    prob, prm = w.problem, w.params
+    return bench_queries(a)
 
-    planner = K.Planner(prob, prm, device="cuda:0")
-    if a.polish:
-        planner.set_polish(a.polish)
+
+def key_cost(key, cost_kind, dt):
+    """Cost of a solution key: the high word is the total RK4 step count
+    (TIME cost, times dt) or the float32 bits of the path length."""
+    field = int(key) >> 32
+    if cost_kind == "TIME":
+        return field * dt
+    return float(np.array([field], np.uint32).view(np.float32)[0])
+
+
+def make_planner(K, W, a, seed, polish):
+    w = W.make_workload(a.workload, seed)
+    if a.refine_at:
+        w.params.refine_max = 2
+    p = K.Planner(w.problem, w.params)
+    if polish:
+        p.set_polish(polish)
     if a.cost_first:
-        planner.set_cost_first(True)
-    print(f"[bench] {a.workload}: {prm.n_select} x {prm.samples_per_node} slots, "
-          f"{prm.n_cells} regions, cap {prm.tree_cap}; warmup {a.warmup}", file=sys.stderr,
+        p.set_cost_first(True)
+    return w, p
+
+
+def run_query(p, a):
+    """Enqueues one query's run (with the optional mid-run refinement)."""
+    if 0 < a.refine_at < a.iters:
+        p.iterate(a.refine_at)
+        p.refine(2)
+        p.iterate(a.iters - a.refine_at)
+    else:
+        p.iterate(a.iters)
+
+
+def run_queries(K, W, a, polish, timing):
+    """Runs the timed queries one after another (each created, with its scene
+    uploaded, before its timed run) and gathers per-query device-timed rates,
+    solutions, cost at budgets and the sampled per-kernel times."""
+    import torch
+
+    from paper_2602_02846_amd.autotune import first_solution_ms
+
+    for s in range(a.warmup):
+        _, p = make_planner(K, W, a, s, polish)
+        run_query(p, a)
+        p.sync()
+        p.close()
+    rates, spans, edges_all, iters_all, wall, full = [], [], 0, 0, 0.0, 0
+    t_first, costs = [], []
+    at_budget = {b: [] for b in BUDGETS_MS}
+    ksum = {k: 0.0 for k in KERNELS}
+    klaunch = {k: 0 for k in KERNELS}
+    flops = 0.0
+    kbytes = {k: 0.0 for k in KERNELS[1:]}
+    w = None
+    for seed in range(a.steps):
+        w, p = make_planner(K, W, a, seed, polish)
+        if timing:
+            p.set_timing(True, every=a.timing_every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_query(p, a)
+        p.sync()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        c = p.counters()
+        done = int(c["iteration"])
+        full += int(c["full"])
+        st = p.stats(0, done)
+        rate_hz = p.clock_rate_khz() * 1e3
+        e = int((st["n_select"].astype(np.int64) * st["samples_per_node"]).sum())
+        span = (int(st["t_end"][-1]) - int(st["t_begin"][0])) / rate_hz
+        rates.append(e / span)
+        spans.append(span)
+        edges_all += e
+        iters_all += done
+        t = first_solution_ms(p, a.iters)
+        if t is not None:
+            t_first.append(t)
+            costs.append(p.solution()["cost"])
+        t_ms = (st["t_end"].astype(np.float64) - float(st["t_begin"][0])) / rate_hz * 1e3
+        for b in BUDGETS_MS:
+            keys = st["solution_key"][t_ms <= b]
+            best = int(keys.min()) if keys.size else (1 << 64) - 1
+            at_budget[b].append(np.inf if best == (1 << 64) - 1 else key_cost(best, w.problem.cost, w.params.dt))
+        if timing:
+            ms, launches = p.read_timing()
+            # the bracketed launches are those of iterations 0, E, 2E, ... that ran
+            idx = np.arange(0, done, a.timing_every)
+            n_t = min(len(idx), launches[0])
+            if n_t == launches[0] and all(n == launches[0] for n in launches):
+                idx = idx[:n_t]
+                for i, k in enumerate(KERNELS):
+                    ksum[k] += ms[i]
+                    klaunch[k] += launches[i]
+                flops += FLOPS_PER_SUBSTEP[(w.problem.dynamics, w.problem.cost)] * float(st["substeps"][idx].sum())
+                kb = kernel_bytes(w.problem, w.params, st)
+                for k in kbytes:
+                    kbytes[k] += float(kb[k][idx].sum())
+        p.close()
+        if seed % 10 == 9:
+            print(f"[bench] {seed + 1} queries timed", file=sys.stderr, flush=True)
+    sols = {
+        "queries": a.steps, "iterations": a.iters, "polish_steps": polish, "refine_at": a.refine_at,
+        "solved": len(t_first),
+        "time_to_first_solution_ms_median": round(float(np.median(t_first)), 3) if t_first else None,
+        "cost_median": round(float(np.median(costs)), 4) if costs else None,
+        "cost_at_budget_median": {f"{b:g}ms": (None if not np.isfinite(np.median(v)) else
+                                               round(float(np.median(v)), 4)) for b, v in at_budget.items()},
+        "solved_at_budget": {f"{b:g}ms": int(np.isfinite(v).sum()) for b, v in at_budget.items()},
+        "cost_unit": "s" if w.problem.cost == "TIME" else "length",
+    }
+    return {"rates": rates, "spans": spans, "edges": edges_all, "iterations": iters_all, "wall": wall,
+            "full": full, "solutions": sols, "ksum": ksum, "klaunch": klaunch, "flops": flops,
+            "kbytes": kbytes, "w": w}
+
+
+def roofline_of(flops, ms, launches, traffic=None):
+    if not launches or ms <= 0:
+        return None
+    achieved = flops / (ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+            "frac_of_unpacked_peak": round(achieved / PEAK_FP32_UNPACKED, 4),
+            "launches": launches, "flops_per_launch": round(flops / launches, 1)}
+
+
+def kernels_summary(ksum, klaunch, kbytes, traffic, trace=None):
+    """Per iteration kernel: HIP-event microseconds per launch (which include
+    the dispatch around the kernel, a few us), the kernel-trace time of the
+    committed profile of the same command when there is one, and for prune,
+    insert and finalize their algorithmic bytes per launch and the rate at
+    either time."""
+    out = {}
+    for k in KERNELS:
+        if not klaunch[k]:
+            continue
+        us = ksum[k] / klaunch[k] * 1e3
+        e = {"us": round(us, 3)}
+        if trace and k in trace:
+            e["trace_us"] = round(trace[k], 3)
+        if k in kbytes:
+            b = kbytes[k] / klaunch[k]
+            e["algorithmic_bytes_per_launch"] = round(b)
+            e["algorithmic_gbs"] = round(b / us / 1e3, 2)
+            e["frac_of_hbm"] = round(b / us / 1e3 / PEAK_HBM_GBS, 4)
+            if trace and k in trace:
+                e["algorithmic_gbs_trace"] = round(b / trace[k] / 1e3, 2)
+                e["frac_of_hbm_trace"] = round(b / trace[k] / 1e3 / PEAK_HBM_GBS, 4)
+        if traffic and k in traffic:
+            e["counter_bytes_per_launch"] = traffic[k]
+            if k in kbytes:
+                e["counter_over_algorithmic"] = round(traffic[k] / (kbytes[k] / klaunch[k]), 2)
+        out[k] = e
+    return out
+
+
+def steady_state(K, W, a, polish):
+    """The first query once its selection is full: per-kernel HIP-event times
+    and the propagate roofline over a window of iterations."""
+    w, p = make_planner(K, W, a, 0, polish)
+    target = w.params.n_select if w.params.samples_per_node else None
+    done = 0
+    while done < 400:
+        p.iterate(5)
+        done += 5
+        c = p.counters()
+        if c["full"] or target is None or int(c["n_select"]) >= target:
+            break
+    c0 = p.counters()
+    if c0["full"] or (target is not None and int(c0["n_select"]) < target):
+        p.close()
+        return None
+    p.set_timing(True, every=1)
+    p.iterate(a.steady_window)
+    p.sync()
+    c1 = p.counters()
+    n = int(c1["iteration"] - c0["iteration"])
+    ms, launches = p.read_timing()
+    st = p.stats(int(c0["iteration"]), n)
+    p.close()
+    if n != a.steady_window or launches[0] != n:
+        return None
+    e = int((st["n_select"].astype(np.int64) * st["samples_per_node"]).sum())
+    fl = FLOPS_PER_SUBSTEP[(w.problem.dynamics, w.problem.cost)] * float(st["substeps"].sum())
+    kb = kernel_bytes(w.problem, w.params, st)
+    return {"first_iteration": int(c0["iteration"]), "iterations": n,
+            "edges_per_iteration": e // n, "substeps_per_iteration": int(st["substeps"].sum()) // n,
+            "note": "HIP events around every kernel of every iteration of the window",
+            "kernels": kernels_summary(dict(zip(KERNELS, ms)), dict(zip(KERNELS, launches)),
+                                       {k: float(v.sum()) for k, v in kb.items()}, None),
+            "roofline": roofline_of(fl, ms[0], launches[0])}
+
+
+def bench_queries(a):
+    import paper_2602_02846_amd as K
+    import workloads as W
+
+    w0 = W.make_workload(a.workload, 0)
+    prob, prm = w0.problem, w0.params
+    print(f"[bench] {a.workload}: {prm.n_select} x {prm.samples_per_node} slots, {prm.n_cells} regions, "
+          f"cap {prm.tree_cap}; {a.warmup} + {a.steps} queries of {a.iters} iterations", file=sys.stderr,
           flush=True)
-    planner.iterate(a.warmup)
-    planner.sync()
-    snap_start = planner.snapshot() if not a.no_cpu_baseline else None
-    c0 = planner.counters()
-    if not a.no_timing:
-        # HIP events around propagate (the roofline kernel), or all four
-        # kernels, in every timing_every-th iteration of the timed region
-        planner.set_timing(15 if a.time_all else 1, every=a.timing_every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    planner.iterate(a.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rc = planner.sync()
-    c1 = planner.counters()
-    done = int(c1["iteration"] - c0["iteration"])
-    st = planner.stats(int(c0["iteration"]), done) if done > 0 else None
-    edges = int((st["n_select"].astype(np.int64) * st["samples_per_node"]).sum()) if done else 0
-    substeps = int(st["substeps"].sum()) if done else 0
-    elapsed = t1 - t0
-    value = edges / elapsed if elapsed > 0 else 0.0
-    print(f"[bench] timed {done} iterations in {elapsed * 1e3:.2f} ms, {edges} edges, "
-          f"status {rc}", file=sys.stderr, flush=True)
-
-    roofline = None
-    kernel_ms = None
-    if not a.no_timing:
-        ms, launches = planner.read_timing()
-        kernel_ms = {name: (ms[i] / launches[i] if launches[i] else None)
-                     for i, name in enumerate(["propagate", "prune_flags", "insert",
-                                               "finalize_select"]) if launches[i]}
-        if launches[0] and done:
-            # the FLOPs of the launches the events bracketed (every
-            # timing_every-th timed iteration, from the first), over their time
-            sampled = st["substeps"][:: max(1, a.timing_every)][: launches[0]]
-            fl = FLOPS_PER_SUBSTEP[(prob.dynamics, prob.cost)] * float(sampled.sum()) / launches[0]
-            avg_s = ms[0] / launches[0] / 1e3
-            achieved = fl / avg_s / 1e12
-            roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                        # the counters were taken on the plain form's kernel
-                        "traffic": None if a.cost_first else measured_traffic(a.workload)}
-
-    # time to first solution and cost, from device timestamps of this query
-    it_done = int(c1["iteration"])
-    all_st = planner.stats(max(0, it_done - 65536), min(it_done, 65536))
-    rate = planner.clock_rate_khz() * 1e3
-    first_it = int(c1["first_solution_iteration"])
-    sol = planner.solution()
-    t_first = None
-    if first_it >= 0 and all_st.size and all_st["iteration"][0] == 0:
-        t_first = float((int(all_st["t_end"][first_it]) - int(all_st["t_begin"][0])) / rate * 1e3)
-
-    planner.close()
-    sols = solution_medians(K, W, a, a.polish, a.refine_at) if a.solution_seeds > 0 else None
+    timing = not a.no_timing
+    R = run_queries(K, W, a, a.polish, timing)
+    value = float(np.median(R["rates"]))
+    traffic = measured_traffic(a)
+    roof = roofline_of(R["flops"], R["ksum"]["propagate"], R["klaunch"]["propagate"],
+                       traffic.get("propagate") if traffic and not a.cost_first else None) if timing else None
+    trace = measured_trace(a)
+    kern = kernels_summary(R["ksum"], R["klaunch"], R["kbytes"], traffic, trace) if timing else None
+    steady = steady_state(K, W, a, a.polish) if timing and a.steady_window > 0 else None
+    print(f"[bench] {a.steps} queries: median {value:.4g} edges/s; whole job {R['edges']} edges in "
+          f"{R['wall'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     growth = tree_growth(K, W, a) if a.tree_growth > 0 else None
-    sols_plain = (solution_medians(K, W, a, 0) if a.solution_seeds > 0 and (a.polish or a.refine_at)
-                  else None)
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(w, snap_start, a.cpu_seconds)
+    plain = None
+    if a.polish or a.refine_at:
+        class _A:  # the same queries with the plain planner
+            pass
+        b = _A()
+        b.__dict__.update(vars(a))
+        b.refine_at = 0
+        plain = run_queries(K, W, b, 0, False)["solutions"]
+    cpu = None if a.no_cpu_baseline else cpu_baseline(w0, a)
 
     out = {
         "metric": "propagated edges/s", "value": round(value, 1), "unit": "edges/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": round(elapsed * 1e3 / max(done, 1), 4), "higher_is_better": True,
+        "ms_per_step": round(float(np.median(R["spans"])) * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{a.workload}: {prob.dynamics} {prob.n_boxes} boxes, "
                    + (f"{prm.n_select}x{prm.samples_per_node} expansions/iteration, "
@@ -220,16 +455,20 @@ def main():
                       f"every active node sharing {prm.n_select} expansion slots per iteration, ")
                    + f"{prm.n_cells} regions, cap {prm.tree_cap}"
                    + (f", edge polish {a.polish} steps per inserted node" if a.polish else "")
-                   + (", cost-first propagate" if a.cost_first else ""),
-                   "seed": a.seed, "iterations_timed": done, "edges_timed": edges,
-                   "substeps_timed": substeps, "cost": prob.cost},
-        "roofline": roofline,
-        "kernel_ms": kernel_ms,
-        "time_to_first_solution_ms": t_first,
-        "first_solution_iteration": first_it,
-        "solution_cost": sol["cost"] if sol["found"] else None,
-        "solutions": sols,
-        "solutions_plain": sols_plain,
+                   + (", cost-first propagate" if a.cost_first else "")
+                   + (f", regions refined after {a.refine_at} iterations" if a.refine_at else ""),
+                   "step": f"one query: {a.iters} iterations from the root (seed = query index)",
+                   "value": "median over queries of edges / device-timed span of the query",
+                   "iterations_timed": R["iterations"], "edges_timed": R["edges"],
+                   "queries_full": R["full"], "cost": prob.cost},
+        "whole_job_edges_per_s": round(R["edges"] / R["wall"], 1) if R["wall"] > 0 else None,
+        "whole_job_ms_per_iteration": round(R["wall"] * 1e3 / max(R["iterations"], 1), 5),
+        "roofline": roof,
+        "kernels": kern,
+        "timing_every": a.timing_every if timing else None,
+        "steady_state": steady,
+        "solutions": R["solutions"],
+        "solutions_plain": plain,
         "cpu_baseline": cpu,
     }
     if growth is not None:
@@ -242,7 +481,7 @@ def tree_growth(K, W, a, window=50):
     geometrically spaced points of a run of a.tree_growth iterations, with the
     tree size and live regions at each window: prune works per region and per
     slot, so its time should follow the region count, not the tree."""
-    w = W.make_workload(a.workload, a.seed)
+    w = W.make_workload(a.workload, 0)
     p = K.Planner(w.problem, w.params)
     if a.cost_first:
         p.set_cost_first(True)
@@ -258,94 +497,16 @@ def tree_growth(K, W, a, window=50):
         ms, launches = p.read_timing()
         p.set_timing(False)
         c1 = p.counters()
-        snap = p.snapshot()
-        live = int((snap["cell_table"] != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
         st = p.stats(int(c0["iteration"]), int(c1["iteration"] - c0["iteration"]))
         out.append({"iteration": int(c0["iteration"]), "n_tree": int(c1["n_tree"]),
-                    "live_regions": live, "survivors_per_iteration": float(st["n_survivors"].mean()) if st.size else 0.0,
-                    "us": {n: round(ms[i] / launches[i] * 1e3, 2) for i, n in enumerate(
-                        ["propagate", "prune_flags", "insert", "finalize_select"]) if launches[i]}})
+                    "live_regions": int(st["n_live"][-1] + st["n_survivors"][-1]) if st.size else 0,
+                    "survivors_per_iteration": float(st["n_survivors"].mean()) if st.size else 0.0,
+                    "us": {n: round(ms[i] / launches[i] * 1e3, 2) for i, n in enumerate(KERNELS) if launches[i]}})
         done += window
         start = max(done, 2 * start)
         print(f"[bench] tree growth: iteration {done}, n_tree {c1['n_tree']}", file=sys.stderr, flush=True)
     p.close()
     return {"window_iterations": window, "capacity": int(w.params.tree_cap), "windows": out}
-
-
-BUDGETS_MS = (5.0, 10.0, 20.0, 40.0)
-
-
-def key_cost(key, cost_kind, dt):
-    """Cost of a solution key: the high word is the total RK4 step count
-    (TIME cost, times dt) or the float32 bits of the path length."""
-    field = int(key) >> 32
-    if cost_kind == "TIME":
-        return field * dt
-    return float(np.array([field], np.uint32).view(np.float32)[0])
-
-
-def solution_medians(K, W, a, polish=0, refine_at=0):
-    """Median device-timed time to first solution and median solution cost
-    over seeds 0 .. solution_seeds - 1 of the workload, each run for
-    solution_iters iterations (or until its tree is full), with edge polish
-    of `polish` steps (0: the plain planner).  Also the cost of the best plan
-    known at fixed device-time budgets (median over all seeds, an unsolved
-    seed counting as infinite) and the number of seeds solved by then.  With
-    refine_at > 0 the region grid is halved per axis after that many
-    iterations (adaptive decomposition)."""
-    from paper_2602_02846_amd.autotune import first_solution_ms
-
-    times, costs, refine_ms = [], [], []
-    at_budget = {b: [] for b in BUDGETS_MS}
-    dt = None
-    for seed in range(a.solution_seeds):
-        w = W.make_workload(a.workload, seed)
-        dt = w.params.dt
-        if refine_at:
-            w.params.refine_max = 2
-        p = K.Planner(w.problem, w.params)
-        if polish:
-            p.set_polish(polish)
-        if a.cost_first:
-            p.set_cost_first(True)
-        if 0 < refine_at < a.solution_iters:
-            import torch
-
-            p.iterate(refine_at)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            p.refine(2)
-            e1.record()
-            p.iterate(a.solution_iters - refine_at)
-            torch.cuda.synchronize()
-            refine_ms.append(e0.elapsed_time(e1))
-        else:
-            p.iterate(a.solution_iters)
-        p.sync()
-        t = first_solution_ms(p, a.solution_iters)
-        if t is not None:
-            times.append(t)
-            costs.append(p.solution()["cost"])
-        c = p.counters()
-        st = p.stats(0, min(int(c["iteration"]), 65536))
-        rate = p.clock_rate_khz() * 1e3
-        t_ms = (st["t_end"].astype(np.float64) - float(st["t_begin"][0])) / rate * 1e3 if st.size else np.zeros(0)
-        for b in BUDGETS_MS:
-            keys = st["solution_key"][t_ms <= b]
-            best = int(keys.min()) if keys.size else (1 << 64) - 1
-            at_budget[b].append(np.inf if best == (1 << 64) - 1 else key_cost(best, w.problem.cost, dt))
-        p.close()
-    return {"queries": a.solution_seeds, "iterations": a.solution_iters, "polish_steps": polish,
-            "refine_at": refine_at,
-            "refine_ms_median": round(float(np.median(refine_ms)), 4) if refine_ms else None,
-            "solved": len(times),
-            "time_to_first_solution_ms_median": round(float(np.median(times)), 3) if times else None,
-            "cost_median": round(float(np.median(costs)), 4) if costs else None,
-            "cost_at_budget_median": {f"{b:g}ms": (None if not np.isfinite(np.median(v)) else
-                                                   round(float(np.median(v)), 4))
-                                      for b, v in at_budget.items()},
-            "solved_at_budget": {f"{b:g}ms": int(np.isfinite(v).sum()) for b, v in at_budget.items()},
-            "cost_unit": "s" if W.make_workload(a.workload, 0).problem.cost == "TIME" else "length"}
 
 
 def bench_batch(a):
@@ -586,27 +747,57 @@ def bench_diff(a):
     print(json.dumps(out))
 
 
-def cpu_baseline(w, snap, seconds):
-    """The float64 oracle (single thread, as written) stepping the same tree."""
-    from oracle import oracle as O
-    from oracle import parity
 
-    P = O.Problem(w.problem, w.params)
-    tr = parity.oracle_tree_from_snapshot(O, P, snap)
-    edges = 0
-    iters = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        rc = tr.step()
-        if rc != O.OK:
-            break
-        edges += tr.cands.n_slots
-        iters += 1
-    el = time.perf_counter() - t0
-    return {"value": round(edges / el, 1) if el > 0 else None, "unit": "edges/s", "cores": 1,
+
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(w, a):
+    """The float64 oracle running the first query (seed 0) from its root, as
+    the GPU does: on every host core (the OpenMP build of the same source,
+    expansions shared among threads), then on one, each for a bounded sample
+    of its iterations."""
+    from oracle import oracle as O
+
+    def sample(threaded, seconds):
+        P = O.Problem(w.problem, w.params)
+        tr = O.Tree(P)
+        assert tr.init() == O.OK
+        edges = iters = 0
+        t0 = time.perf_counter()
+        while iters < a.iters and time.perf_counter() - t0 < seconds:
+            if tr.step(threaded=threaded) != O.OK:
+                break
+            edges += tr.cands.n_slots
+            iters += 1
+        return edges, iters, time.perf_counter() - t0
+
+    threads = int(O.lib_threads().ora_threads())
+    e_all, i_all, t_all = sample(True, a.cpu_seconds)
+    e_one, i_one, t_one = sample(False, a.cpu_seconds_single)
+    host = host_cpu()
+    return {"value": round(e_all / t_all, 1) if t_all > 0 else None, "unit": "edges/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{iters} iterations of the same query from the GPU tree at the start of "
-                      f"the timed region ({edges} expansions, {el:.1f} s, float64, one thread)"}
+            "sample": f"iterations 0..{i_all - 1} of query 0 from its root ({e_all} expansions, "
+                      f"{t_all:.1f} s, float64, {threads} threads)",
+            "single_thread": {"value": round(e_one / t_one, 1) if t_one > 0 else None,
+                              "sample": f"iterations 0..{i_one - 1} of query 0 ({e_one} expansions, "
+                                        f"{t_one:.1f} s, one thread)"},
+            **host}
 
 
 if __name__ == "__main__":

@@ -215,6 +215,8 @@ typedef struct kpx_iter_stats {
     uint64_t solution_key;
     uint64_t t_begin;         /* device wall clock ticks (kpx_clock_rate_khz) */
     uint64_t t_end;
+    int64_t n_live;           /* regions a tree node still owned after propagate (the
+                               * owners prune examines) */
 } kpx_iter_stats;
 
 /* Bytes of device workspace kpx_create needs for this problem.  Pure host

@@ -15,6 +15,18 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 int ora_state_dim(int32_t dyn)
 {
@@ -685,8 +697,11 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
     C->k = K;
     C->substeps_total = 0;
 
-    /* Alg. 2: each of the K expansions of each selected node */
-    int64_t n_valid = 0;
+    /* Alg. 2: each of the K expansions of each selected node.  The
+     * expansions are independent; a build with OpenMP (the CPU timing
+     * baseline only) shares them among threads, with the same results. */
+    int64_t n_valid = 0, substeps_total = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n_valid, substeps_total)
     for (int64_t s = 0; s < n_slots; ++s) {
         const int64_t par = sel[s / K];
         float u[ORA_MAX_CONTROL];
@@ -699,7 +714,7 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
         const int32_t hint_fi = (H && H->first_invalid) ? H->first_invalid[s] : -1;
         ora_propagate_edge(P, &T->x[par * ORA_MAX_STATE], u, n, hint_fi, &e);
         C->substeps[s] = e.substeps;
-        C->substeps_total += e.substeps;
+        substeps_total += e.substeps;
         C->first_invalid[s] = e.first_invalid;
         C->flags[s] = e.flags;
         C->valid[s] = e.first_invalid == 0;
@@ -720,6 +735,7 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
                                             (H && H->goal) ? &H->goal[s] : NULL, &fl);
         C->flags[s] |= fl;
     }
+    C->substeps_total = substeps_total;
 
     /* Alg. 2: region minimum over this iteration's arrivals; the
      * arrival id of slot s is n_tree + s */

@@ -161,6 +161,9 @@ typedef struct {
 } ora_verify_report;
 
 int ora_state_dim(int32_t dynamics);
+/* Threads ora_step shares its expansions among: 1 for the plain build, the
+ * OpenMP thread count for the timing build (liboracle_omp.so). */
+int ora_threads(void);
 int ora_control_dim(int32_t dynamics);
 
 void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "kpx_oracle.c")
 SRC_DIFF = os.path.join(HERE, "kpx_oracle_diff.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")  # the same source with OpenMP (CPU timing only)
 
 MAX_STATE = 12
 MAX_CONTROL = 4
@@ -95,18 +96,35 @@ class VerifyC(C.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (strict IEEE float64, no fast-math)."""
+    """Compile the oracle with gcc (strict IEEE float64, no fast-math), and the
+    same source with OpenMP for the CPU-baseline timing."""
     deps = [SRC, SRC_DIFF, os.path.join(HERE, "kpx_oracle.h"), os.path.join(HERE, "kpx_oracle_diff.h")]
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(map(os.path.getmtime, deps)):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-                               "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, SRC, SRC_DIFF,
-                               "-lm"])
-        os.replace(tmp, LIB)
+    for out, extra in ((LIB, ["-Wno-unknown-pragmas"]), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < max(map(os.path.getmtime, deps)):
+            tmp = out + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                                   "-ffp-contract=off", "-Wall", "-Wextra", *extra, "-o", tmp, SRC,
+                                   SRC_DIFF, "-lm"])
+            os.replace(tmp, out)
     return LIB
 
 
 _lib = None
+_lib_omp = None
+
+
+def lib_threads():
+    """The OpenMP build, for timing the oracle on every host core (its step
+    gives the same results as the plain build's)."""
+    global _lib_omp
+    if _lib_omp is None:
+        build()
+        L = C.CDLL(LIB_OMP)
+        L.ora_step.argtypes = lib().ora_step.argtypes
+        L.ora_step.restype = C.c_int
+        L.ora_threads.restype = C.c_int
+        _lib_omp = L
+    return _lib_omp
 
 
 def lib():
@@ -378,7 +396,7 @@ class Tree:
     def n_tree(self) -> int:
         return int(self.c.n_tree)
 
-    def step(self, hints: Optional[dict] = None) -> int:
+    def step(self, hints: Optional[dict] = None, threaded: bool = False) -> int:
         h = None
         keep = []
         if hints is not None:
@@ -392,7 +410,8 @@ class Tree:
                     keep.append(a)
                     setattr(hc, name, _ptr(a, ct))
             h = C.byref(hc)
-        return lib().ora_step(self.P.ref, C.byref(self.c), C.byref(self.cands.c), h)
+        L = lib_threads() if threaded else lib()
+        return L.ora_step(self.P.ref, C.byref(self.c), C.byref(self.cands.c), h)
 
     def refine(self, P_new: Problem, factor: int, hint_cell=None) -> int:
         """Adaptive decomposition: P_new is the problem with the refined grid

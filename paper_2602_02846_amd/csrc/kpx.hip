@@ -65,6 +65,7 @@ struct DevState {
     unsigned long long substeps_acc;
     long long last_substeps;
     int n_valid_acc;
+    int n_live_acc;      // regions a tree node still owns after propagate (prune's count)
     int last_n_valid;
     int n_sel;
     int last_n_sel;
@@ -246,6 +247,7 @@ __global__ void k_init_root(DevProblem P, DevPtrs T, DevState* st, const float* 
     st->substeps_acc = 0;
     st->last_substeps = 0;
     st->n_valid_acc = 0;
+    st->n_live_acc = 0;
     st->last_n_valid = 0;
     st->n_sel = 0;
     st->last_n_sel = 0;
@@ -673,10 +675,10 @@ __global__ __launch_bounds__(NT) void k_propagate(DevProblem P, DevPtrs T, DevSt
 
 // ------------------------------------------------------------------ prune + survivor flags
 
-__device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevPtrs& T, const DevState* st,
+__device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevPtrs& T, DevState* st,
                                                  int blk, int n_prune_blocks)
 {
-    __shared__ int s_w[kBlock / 64], s_w2[kBlock / 64];
+    __shared__ int s_w[kBlock / 64], s_w2[kBlock / 64], s_w3[kBlock / 64];
     if (blk < n_prune_blocks) {
         // Alg. 3 for the owner of region c (every live node owns its region);
         // also records whether the region's node is active after this
@@ -688,11 +690,13 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
         const long long n_tree = st->n_tree;
         if (full) return;  // kernel-uniform
         uint8_t a = 0;
+        bool owned = false;  // a tree node owns the region
         if (c < P.n_cells && key != kEmpty) {
             const uint32_t o = (uint32_t)key;
             if ((long long)o >= n_tree) {
                 a = 1;  // an arrival of this iteration owns it; it is inserted active
             } else {
+                owned = true;
                 // status, count and the first ancestor list in one round trip
                 uint8_t s = T.status[o];
                 const int ic0 = T.icount[o];
@@ -737,19 +741,23 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
         }
         if (c < P.n_cells) T.act[c] = a;
         const int hi = __popcll(__ballot(a && c >= cur)), lo = __popcll(__ballot(a && c < cur));
+        const int ow = __popcll(__ballot(owned));
         if ((threadIdx.x & 63) == 0) {
             s_w[threadIdx.x >> 6] = hi;
             s_w2[threadIdx.x >> 6] = lo;
+            s_w3[threadIdx.x >> 6] = ow;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            int th = 0, tl = 0;
+            int th = 0, tl = 0, to = 0;
 #pragma unroll
             for (int w = 0; w < kBlock / 64; ++w) {
                 th += s_w[w];
                 tl += s_w2[w];
+                to += s_w3[w];
             }
             T.bcount[blk] = make_int2(th, tl);
+            if (to) atomicAdd(&st->n_live_acc, to);
             if (grouped(P.n_bgroups)) {
                 int2* g = bgroup_at(T, P, (int)(st - T.st), blk / kGroup);
                 if (th) atomicAdd(&g->x, th);
@@ -784,7 +792,7 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T, const DevState* st,
+__global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T, DevState* st,
                                                         int n_prune_blocks)
 {
     prune_flags_body(P, T, st, blockIdx.x, n_prune_blocks);
@@ -1247,6 +1255,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
             r->n_tree = nt;
             r->n_select = n_sel;
             r->n_valid = st->n_valid_acc;
+            r->n_live = st->n_live_acc;
             r->n_survivors = n_surv;
             r->samples_per_node = k_cur;
             r->substeps = (long long)st->substeps_acc;
@@ -1261,6 +1270,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
             o->last_n_surv = n_surv;
             o->last_substeps = (long long)st->substeps_acc;
             o->n_valid_acc = 0;
+            o->n_live_acc = 0;
             o->substeps_acc = 0;
             o->cursor = cur;
         } else {
@@ -1273,6 +1283,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
             o->last_n_surv = st->last_n_surv;
             o->last_substeps = st->last_substeps;
             o->n_valid_acc = st->n_valid_acc;
+            o->n_live_acc = st->n_live_acc;
             o->substeps_acc = st->substeps_acc;
             o->cursor = st->cursor;
         }

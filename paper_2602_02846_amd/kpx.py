@@ -92,7 +92,7 @@ class IterStatsC(C.Structure):
         ("iteration", C.c_int64), ("n_tree", C.c_int64), ("n_select", C.c_int32),
         ("n_valid", C.c_int32), ("n_survivors", C.c_int32), ("samples_per_node", C.c_int32),
         ("substeps", C.c_int64), ("solution_key", C.c_uint64), ("t_begin", C.c_uint64),
-        ("t_end", C.c_uint64),
+        ("t_end", C.c_uint64), ("n_live", C.c_int64),
     ]
 
 
@@ -100,7 +100,7 @@ STATS_DTYPE = np.dtype([
     ("iteration", np.int64), ("n_tree", np.int64), ("n_select", np.int32),
     ("n_valid", np.int32), ("n_survivors", np.int32), ("samples_per_node", np.int32),
     ("substeps", np.int64), ("solution_key", np.uint64), ("t_begin", np.uint64),
-    ("t_end", np.uint64)])
+    ("t_end", np.uint64), ("n_live", np.int64)])
 
 class PolishC(C.Structure):
     _fields_ = [("steps", C.c_int32), ("lr", C.c_float), ("w_ctrl", C.c_float), ("w_obst", C.c_float),

@@ -123,6 +123,14 @@ def test_stats_ring_and_timing(kpx):
     assert np.all(np.diff(st["n_tree"]) == st["n_survivors"][1:])
     assert np.all(st["t_end"] >= st["t_begin"])
     assert pl.clock_rate_khz() > 0
+    # the regions a tree node kept through propagate, plus those this
+    # iteration's survivors took, are the regions owned after it
+    for _ in range(3):
+        pl.iterate(1)
+        c = pl.counters()
+        r = pl.stats(int(c["iteration"]) - 1, 1)[0]
+        owned = int((pl.snapshot()["cell_table"] != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+        assert int(r["n_live"]) + int(r["n_survivors"]) == owned, (r, owned)
     pl.set_timing(1)  # propagate only
     pl.iterate(5)
     ms, launches = pl.read_timing()

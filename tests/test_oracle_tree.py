@@ -484,3 +484,24 @@ def test_root_in_the_goal_is_a_solution_of_cost_zero(ora):
         T2 = ora.Tree(ora.Problem(w.problem, w.params))
         if T2.init() == ora.OK:
             assert T2.c.sol_id == -1 and T2.c.first_sol_iter == -1
+
+
+@pytest.mark.parametrize("name", ["quad12", "dubins6"])
+def test_threaded_timing_build_steps_like_the_plain_oracle(ora, name):
+    """The OpenMP build that times the oracle on every host core shares the
+    expansions among threads; its trees equal the plain build's."""
+    w = W.make_workload(name, 1, n_select=64, samples=8, tree_cap=1 << 14)
+    P = ora.Problem(w.problem, w.params)
+    a, b = ora.Tree(P), ora.Tree(P)
+    assert a.init() == ora.OK and b.init() == ora.OK
+    for _ in range(12):
+        assert a.step() == ora.OK
+        assert b.step(threaded=True) == ora.OK
+        assert a.cands.substeps_total == b.cands.substeps_total
+    n = a.n_tree
+    assert n == b.n_tree and n > 100
+    for k in ("x", "u", "steps", "parent", "cost", "cell", "status", "icount", "tbl_cost", "tbl_id"):
+        np.testing.assert_array_equal(getattr(a, k)[:n] if k not in ("tbl_cost", "tbl_id") else getattr(a, k),
+                                      getattr(b, k)[:n] if k not in ("tbl_cost", "tbl_id") else getattr(b, k),
+                                      err_msg=k)
+    assert ora.lib_threads().ora_threads() >= 1
