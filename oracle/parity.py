@@ -185,6 +185,29 @@ def polished_nodes(pre, post, dump):
     return mask, hints
 
 
+def check_iteration(O, P, planner, pre, report):
+    """The planner has just run one iteration from the snapshot `pre` (with
+    its expansions recorded): the oracle replays that iteration from `pre`
+    and every decision is compared."""
+    dump = planner.read_dump()
+    post = planner.snapshot()
+    tr = oracle_tree_from_snapshot(O, P, pre)
+    report["n_tree_before"] = tr.n_tree
+    mask, polish_hints = polished_nodes(pre, post, dump)
+    hints = hints_from_dump(dump)
+    hints.update(polish_hints)
+    rc = tr.step(hints)
+    assert rc == O.OK
+    compare_candidates(P, tr, dump, report)
+    if P.c.polish_steps > 0:
+        # the accept decision of every polished edge, exactly
+        n_ins = int(post["counters"]["n_tree"]) - report["n_tree_before"]
+        np.testing.assert_array_equal(dump["polish_accepted"], tr.cands.polished[:n_ins])
+    compare_trees(P, tr, post, report, polished=mask)
+    report["polished"] += int(mask.sum())
+    report["iterations"] += 1
+
+
 def lockstep(O, P, planner, iterations, report=None):
     """Runs `iterations` GPU iterations, replaying each one in the oracle."""
     report = report or new_report()
@@ -195,21 +218,26 @@ def lockstep(O, P, planner, iterations, report=None):
         if pre["counters"]["full"]:
             break
         planner.iterate(1)
-        dump = planner.read_dump()
-        post = planner.snapshot()
-        tr = oracle_tree_from_snapshot(O, P, pre)
-        report["n_tree_before"] = tr.n_tree
-        mask, polish_hints = polished_nodes(pre, post, dump)
-        hints = hints_from_dump(dump)
-        hints.update(polish_hints)
-        rc = tr.step(hints)
-        assert rc == O.OK
-        compare_candidates(P, tr, dump, report)
-        if P.c.polish_steps > 0:
-            # the accept decision of every polished edge, exactly
-            n_ins = int(post["counters"]["n_tree"]) - report["n_tree_before"]
-            np.testing.assert_array_equal(dump["polish_accepted"], tr.cands.polished[:n_ins])
-        compare_trees(P, tr, post, report, polished=mask)
-        report["polished"] += int(mask.sum())
-        report["iterations"] += 1
+        check_iteration(O, P, planner, pre, report)
     return report
+
+
+def lockstep_batch(O, Ps, planners, batch, iterations):
+    """Runs `iterations` batched iterations of planners (made with recording
+    on before the batch was), replaying every query's iteration in the oracle.
+    A query whose tree is full must stay exactly as it was."""
+    reports = [dict(new_report(), polished=0, full_at=None) for _ in planners]
+    for _ in range(iterations):
+        pres = [p.snapshot() for p in planners]
+        batch.iterate(1)
+        for q, (P, p, pre, rep) in enumerate(zip(Ps, planners, pres, reports)):
+            if pre["counters"]["full"]:
+                post = p.snapshot()
+                assert post["counters"] == pre["counters"], q
+                for k in ("parent", "status", "cell_table"):
+                    np.testing.assert_array_equal(post[k], pre[k], err_msg=f"query {q}: {k}")
+                continue
+            check_iteration(O, P, p, pre, rep)
+            if p.counters()["full"] and rep["full_at"] is None:
+                rep["full_at"] = rep["iterations"]
+    return reports

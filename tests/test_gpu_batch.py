@@ -1,6 +1,6 @@
 """Batched queries through the C ABI: each query of a batch computes exactly
-what it computes alone (whose parity with the oracle the other GPU tests
-establish), with plain launches and with replayed HIP graphs."""
+what it computes alone, with plain launches and with replayed HIP graphs, and
+the oracle replays every iteration of a batch of queries at their own sizes."""
 
 import numpy as np
 import pytest
@@ -199,5 +199,33 @@ def test_batch_of_uncapped_queries_matches_each_alone(kpx):
     for q, (p, a) in enumerate(zip(ps, alone)):
         _same(p.snapshot(), a, f"query {q}")
     b.close()
+    for p in ps:
+        p.close()
+
+
+def test_batch_lockstep_with_the_oracle(kpx, ora):
+    """Seven queries of the batched workload at their own sizes (double
+    integrators and quadrotors with 94 to 250 boxes, capacities 2^13 to 2^18,
+    one of which fills up in the tenth iteration), graph-replayed as one
+    batch: every query's every iteration is replayed by the oracle."""
+    from oracle import parity
+
+    ws = W.batch_workloads(0, 40)
+    pick = [2, 3, 4, 14, 19, 21, 33]
+    chosen = [ws[q] for q in pick]
+    assert {w.problem.dynamics for w in chosen} == {"DI6", "QUAD12"}
+    assert all(w.problem.n_boxes >= 94 for w in chosen)
+    Ps = [ora.Problem(w.problem, w.params) for w in chosen]
+    ps = [kpx.Planner(w.problem, w.params) for w in chosen]
+    for p in ps:
+        p.set_dump(True)
+    b = kpx.Batch(ps, graph=True)
+    reps = parity.lockstep_batch(ora, Ps, ps, b, 14)
+    b.close()
+    for q, (w, rep) in zip(pick, zip(chosen, reps)):
+        print(q, w.problem.dynamics, w.problem.n_boxes, rep)
+        assert rep["iterations"] >= 10 and rep["valid"] > 0, (q, rep)
+    # the query that fills up does so mid-run, and stays as it was afterwards
+    assert reps[0]["full_at"] is not None and reps[0]["iterations"] < 14, reps[0]
     for p in ps:
         p.close()

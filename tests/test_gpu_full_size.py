@@ -110,3 +110,34 @@ def sampled_slots_check(kpx, ora, w, warm):
     np.testing.assert_array_equal((tbl[dump["cell"][surv]] & np.uint64(0xFFFFFFFF)).astype(np.int64),
                                   n0 + np.arange(len(surv)))
     pl.close()
+
+
+@pytest.mark.parametrize("name,warm", [("quad12", None), ("dubins6", 40), ("dubins6_paper", 12)])
+def test_full_size_lockstep_at_the_benchmark_shapes(kpx, ora, name, warm):
+    """Three iterations at a workload's own size, replayed slot by slot by the
+    oracle.  quad12: once its selection is full (4096 x 32 slots: 512 per
+    propagate chunk, two per lane, sorted by length and refilled from the
+    queue).  dubins6: after 40 iterations; its capped selection never exceeds
+    the ~2,000 regions with an active owner (of 16,384), so its lanes hold one
+    slot each.  dubins6_paper, the uncapped form with a 300,000-slot buffer:
+    1,024-slot chunks, four slots per lane, the Dubins sort and refill path."""
+    w = W.make_workload(name, 0)
+    P = ora.Problem(w.problem, w.params)
+    pl = kpx.Planner(w.problem, w.params)
+    if warm is None:
+        for _ in range(100):
+            pl.iterate(1)
+            if int(pl.counters()["n_select"]) == w.params.n_select:
+                break
+        pl.iterate(1)  # the next selection is full as well (the region count only grows)
+        assert int(pl.counters()["n_select"]) == w.params.n_select
+    else:
+        pl.iterate(warm)
+    rep = parity.lockstep(ora, P, pl, 3)
+    print(name, rep)
+    assert rep["iterations"] == 3
+    if warm is None:
+        assert rep["slots"] == 3 * w.params.n_slots, rep
+    if name == "dubins6_paper":
+        assert rep["slots"] > 3 * 4 * 256 * 256, rep  # more than four slots per lane on 256 CUs
+    pl.close()
