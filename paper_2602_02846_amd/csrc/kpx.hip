@@ -330,7 +330,6 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     __shared__ uint32_t s_pcost[kParMax]; //                     cost field
     constexpr int VI = DYN == kQUAD12 ? 6 : 3;  // first velocity component
     __shared__ int s_bin[kSortBins];
-    __shared__ int s_next;
     __shared__ float s_os[2][D];
     const int gbp = (P.gb_cells + 1) & ~1;  // grid cells, padded to whole 16-byte words
     float4* sbox = dyn_lds;
@@ -367,10 +366,9 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         const int cnt = min(chunk, S - base);
         const int r0 = base / K;
         const int npar = (base + cnt - 1) / K - r0 + 1;
-        // the sort bins and the queue head are free once the previous chunk
-        // has left its integration loop
+        // the sort bins are free once the previous chunk has left its
+        // integration loop
         if (threadIdx.x < kSortBins) s_bin[threadIdx.x] = 0;
-        if (threadIdx.x == 0) s_next = 0;
         __syncthreads();  // LDS of the previous chunk is free
         // 1. parents (tree index, cost, state) into LDS, samples, sort by step
         // count (longest first).  The parent loads are issued before the
@@ -391,7 +389,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             pv[r] = idx < nstage ? T.x[(long long)(idx / npar) * P.cap + prow[r]] : 0.f;
         }
         const uint32_t my_pcost = (int)threadIdx.x < npar ? T.cost[my_pid] : 0u;
-        const bool one_each = cnt <= (int)blockDim.x;  // one slot per thread: no sort needed
+        const bool one_each = cnt <= NT;  // one slot per thread: no sort needed
         const int nr = (cnt + NT - 1) / NT;  // slot rounds of this chunk
         int bins[PT];
 #pragma unroll
@@ -452,7 +450,12 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             __syncthreads();
         }
 
-        // 2. integrate, each lane refilling from the queue
+        // 2. integrate, each lane refilling from the queue.  Wave w of the
+        // block owns queue places w, w + NW, w + 2 NW, ... (the sorted order
+        // dealt out round-robin, so every wave gets long and short edges
+        // alike) and counts its own places, so a refill needs no atomic.
+        constexpr int NW = NT / 64;
+        const int wid = (int)threadIdx.x >> 6;
         float x[D], u[M];
         // a parent's staged state into x: 16-byte LDS reads
         auto load_parent = [&](int j) {
@@ -476,19 +479,17 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         // safe ball: no box is within sqrt(r2) of (rx, ry, rz), the last
         // position whose grid cell was looked up
         float rx = 0.f, ry = 0.f, rz = 0.f, r2 = -1.f;
-        bool exhausted = false;  // wave-uniform: the queue has no slot left
+        int wtaken = 0;  // wave-uniform: queue places of this wave taken so far
+        bool exhausted = wid >= cnt;  // wave-uniform: no place left for this wave
         while (true) {
             const bool want = li < 0 && !exhausted;
             const unsigned long long m = __ballot(want);
             if (m) {
-                const int leader = __ffsll((long long)m) - 1;
-                int first = 0;
-                if (lane == leader) first = atomicAdd(&s_next, __popcll(m));
-                first = __builtin_amdgcn_readlane(first, leader);
-                // one slot per thread: nothing is left to take after the first
-                if (one_each || first + __popcll(m) >= cnt) exhausted = true;
+                const int qi = wtaken + __popcll(m & __lanemask_lt());
+                wtaken += __popcll(m);
+                if (wtaken * NW + wid >= cnt) exhausted = true;
                 if (want) {
-                    const int q = first + __popcll(m & __lanemask_lt());
+                    const int q = qi * NW + wid;
                     if (q < cnt) {
                         const uint32_t o = s_order[q];
                         li = (int)(o & 0xFFFFu);
@@ -496,8 +497,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                         n = s_n[li];
                         const float4 uv = s_u[li];
                         const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
-#pragma unroll
-                        for (int c = 0; c < M; ++c) u[c] = ua[c] * (rev_control(DYN, c) ? kInv2Pi : 1.f);
+                        edge_controls<DYN>(H, ua, u);
                         load_parent(pj);
                         k = 0;
                         len = 0.f;
@@ -1107,8 +1107,7 @@ __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T
     float x[12], ur[4], len = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) x[c] = x0[c] * (rev_state(kQUAD12, c) ? kInv2Pi : 1.f);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) ur[c] = u[c] * (rev_control(kQUAD12, c) ? kInv2Pi : 1.f);
+    edge_controls<kQUAD12>(H, u, ur);
     bool ok = true;
     int fi = 0;
     for (int k = 1; k <= n && ok; ++k) {
@@ -2276,9 +2275,11 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
         h->P.n_cu = std::max(1, n_cu);
         // The cheap models' RK4 step is short beside the LDS latency of a
         // refill or a box lookup, so with two slots or more per lane they run
-        // two waves per SIMD, which hide each other's waits.  The quadrotor's
-        // step keeps one wave per SIMD busy, and small queries are bound by
-        // their longest edge, which a second wave would only slow.
+        // two waves per SIMD, which hide each other's waits.  The quadrotor
+        // keeps one wave per SIMD: a lone wave issues a dependent VALU
+        // instruction only every ~7.5 clocks, but a second wave on the SIMD
+        // delays the wave holding the longest edge, which bounds the kernel,
+        // whatever their priorities (25% slower measured).
         h->prop_threads = (h->P.dyn != kQUAD12 && (long long)z.s_max >= 2LL * kPropBlock * h->P.n_cu)
                               ? kPropBlockWide : kPropBlock;
         int rc = KPX_OK;

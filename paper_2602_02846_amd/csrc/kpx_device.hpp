@@ -152,7 +152,7 @@ struct Hot {
     float dt, h2, h6;
     float bs[D], bo[D];            // scaled bound test (see DevProblem)
     uint32_t os_mask;
-    float inv_mass, inv_j[3], gyro[3], grav;   // gyro in revolution units
+    float inv_mass, inv_j[3], gyro_j[3], grav;  // gyro_j: gyroscopic coefficient times 1/J, revolution units
     float gb_lo[3], gb_scale[3];
     int gb_n[3];
 };
@@ -181,18 +181,38 @@ __device__ __forceinline__ Hot<DYN> make_hot(const DevProblem& P)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         H.inv_j[a] = P.inv_j[a];
-        H.gyro[a] = P.gyro[a] * k2Pi;
+        H.gyro_j[a] = P.gyro[a] * k2Pi * P.inv_j[a];
         H.gb_lo[a] = P.gb_lo[a];
         H.gb_scale[a] = P.gb_scale[a];
         H.gb_n[a] = P.gb_n[a];
-        asm volatile("" : "+v"(H.inv_j[a]), "+v"(H.gyro[a]), "+v"(H.gb_lo[a]), "+v"(H.gb_scale[a]),
+        asm volatile("" : "+v"(H.inv_j[a]), "+v"(H.gyro_j[a]), "+v"(H.gb_lo[a]), "+v"(H.gb_scale[a]),
                      "+v"(H.gb_n[a]));
     }
     return H;
 }
 
 // ---------------------------------------------------------------------------
-// Dynamics f(x, u) and, for the path-length cost, the speed |p'|.
+// A control in the form the derivative takes it, fixed for the whole edge:
+// angular-rate controls in revolutions, and for the quadrotor the thrust
+// divided by the mass and each torque divided by its moment of inertia, so
+// that no substep repeats those products.
+// ---------------------------------------------------------------------------
+template <int DYN>
+__device__ __forceinline__ void edge_controls(const Hot<DYN>& H, const float* u_in, float* u)
+{
+    constexpr int M = Dims<DYN>::M;
+#pragma unroll
+    for (int c = 0; c < M; ++c) u[c] = u_in[c] * (rev_control(DYN, c) ? kInv2Pi : 1.f);
+    if constexpr (DYN == kQUAD12) {
+        u[0] *= H.inv_mass;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[1 + a] *= H.inv_j[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dynamics f(x, u) (u as edge_controls leaves it) and, for the path-length
+// cost, the speed |p'|.
 // ---------------------------------------------------------------------------
 template <int DYN, int COST>
 __device__ __forceinline__ void deriv(const Hot<DYN>& P, const float* x, const float* u,
@@ -209,19 +229,21 @@ __device__ __forceinline__ void deriv(const Hot<DYN>& P, const float* x, const f
         const float sps = __builtin_amdgcn_sinf(x[5]), cps = __builtin_amdgcn_cosf(x[5]);
         const float rc = __builtin_amdgcn_rcpf(cth);
         const float wp = x[9], wq = x[10], wr = x[11];
-        const float a = sph * wq + cph * wr;
+        // Euler-angle rates W(roll, pitch) w
+        const float b = __builtin_fmaf(sph, wq, cph * wr) * rc;
         xd[0] = x[6]; xd[1] = x[7]; xd[2] = x[8];
-        xd[3] = __builtin_fmaf(a * sth, rc, wp);
-        xd[4] = cph * wq - sph * wr;
-        xd[5] = a * rc;
-        const float acc = u[0] * P.inv_mass;
-        const float sc = sth * cph;
-        xd[6] = acc * __builtin_fmaf(cps, sc, sps * sph);
-        xd[7] = acc * __builtin_fmaf(sps, sc, -(cps * sph));
-        xd[8] = __builtin_fmaf(acc, cth * cph, -P.grav);
-        xd[9] = (u[1] - P.gyro[0] * wq * wr) * P.inv_j[0];
-        xd[10] = (u[2] - P.gyro[1] * wp * wr) * P.inv_j[1];
-        xd[11] = (u[3] - P.gyro[2] * wp * wq) * P.inv_j[2];
+        xd[3] = __builtin_fmaf(b, sth, wp);
+        xd[4] = __builtin_fmaf(cph, wq, -(sph * wr));
+        xd[5] = b;
+        // thrust along the body z axis, R_z(yaw) R_y(pitch) R_x(roll) e_3, minus gravity
+        const float t1 = u[0] * sph, t2 = u[0] * cph, t3 = t2 * sth;
+        xd[6] = __builtin_fmaf(cps, t3, sps * t1);
+        xd[7] = __builtin_fmaf(sps, t3, -(cps * t1));
+        xd[8] = __builtin_fmaf(t2, cth, -P.grav);
+        // J^-1 (tau - w x J w) with diagonal J
+        xd[9] = __builtin_fmaf(-(P.gyro_j[0] * wq), wr, u[1]);
+        xd[10] = __builtin_fmaf(-(P.gyro_j[1] * wp), wr, u[2]);
+        xd[11] = __builtin_fmaf(-(P.gyro_j[2] * wp), wq, u[3]);
         if constexpr (COST == kPATH) ld = __builtin_sqrtf(x[6] * x[6] + x[7] * x[7] + x[8] * x[8]);
     } else {
         // x[3], x[4] in revolutions
