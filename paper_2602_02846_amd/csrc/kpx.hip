@@ -8,11 +8,12 @@
 //                  cost, packed (cost | id) 64-bit atomicMin on the region
 //                  table (Alg. 2, Alg. 6); the lane that takes a region from
 //                  a tree node marks that node terminal (Alg. 3).
-//   2. prune+flags blocks [0, P): Alg. 3 for each region's owner (the live
-//                  nodes are exactly the region owners, so prune walks the
-//                  region table instead of the whole tree); blocks [P, P+Q):
-//                  survivor mask V_U = valid and still the region minimum
-//                  (the U-filter of App. A) with per-tile counts.
+//   2. prune+flags one thread per region: Alg. 3 for the region's owner (the
+//                  live nodes are exactly the region owners, so prune walks
+//                  the region table instead of the whole tree); a region an
+//                  arrival took marks that slot in the survivor mask V_U
+//                  (the U-filter of App. A: valid and still the region
+//                  minimum) and counts it in its tile.
 //   3. insert      App. A UpdateTree: rank = exclusive scan of the mask, the
 //                  survivor is appended at |T| + rank, its region is re-keyed
 //                  to the new tree index, goal nodes atomicMin the solution.
@@ -609,6 +610,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             const int s = base + lj;
             const int fi = s_fi[lj];
             const int nn = s_n[lj];
+            // the survivor byte and the chunk's tile counts start the
+            // iteration at zero (prune marks the survivors)
+            T.csurv[s] = 0;
+            if ((s & (kTile - 1)) == 0) T.tile_count[s / kTile] = 0;
             const int pj = s / K - r0;
             if constexpr (!CF) my_steps += fi ? fi : nn;
             if (fi == 0) {
@@ -679,11 +684,14 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
                                                  int blk, int n_prune_blocks)
 {
     __shared__ int s_w[kBlock / 64], s_w2[kBlock / 64], s_w3[kBlock / 64];
-    if (blk < n_prune_blocks) {
+    if (blk >= n_prune_blocks) return;
+    {
         // Alg. 3 for the owner of region c (every live node owns its region);
         // also records whether the region's node is active after this
         // iteration, and per block the active regions on either side of the
-        // selection cursor
+        // selection cursor.  A region an arrival took marks that slot the
+        // survivor (its key is the region's minimum) and counts it in its
+        // 256-slot tile, for the ranks insert gives the survivors.
         const int c = blk * kBlock + threadIdx.x;
         const unsigned long long key = T.tbl[min(c, P.n_cells - 1)];
         const int full = st->full, cur = st->cursor_next;
@@ -694,7 +702,13 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
         if (c < P.n_cells && key != kEmpty) {
             const uint32_t o = (uint32_t)key;
             if ((long long)o >= n_tree) {
-                a = 1;  // an arrival of this iteration owns it; it is inserted active
+                // an arrival of this iteration owns it: that slot is the
+                // region's survivor (V_U, the App. A U-filter), inserted active
+                a = 1;
+                const int sv = (int)((long long)o - n_tree);
+                T.csurv[sv] = 1;
+                atomicAdd(&T.tile_count[sv / kTile], 1);
+                if (grouped(P.n_tgroups)) atomicAdd(tgroup_at(T, P, (int)(st - T.st), sv / kTile / kGroup), 1);
             } else {
                 owned = true;
                 // status, count and the first ancestor list in one round trip
@@ -765,30 +779,6 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
             }
         }
         return;
-    }
-    // survivor mask V_U (App. A U-filter) and per-tile counts
-    const int tile = blk - n_prune_blocks;
-    const int s = tile * kTile + threadIdx.x;
-    const int sc = min(s, P.s_max - 1);
-    const uint8_t fl = T.cflag[sc];
-    const int full = st->full;
-    const int S = st->n_sel * st->k;
-    if (full || tile * kTile >= S) return;  // block-uniform
-    int f = 0;
-    if (s < S) {
-        // only a valid slot's key and region are read
-        if (fl & 1) f = T.ckey[s] == T.tbl[T.ccell[s]];
-        T.csurv[s] = (uint8_t)f;
-    }
-    const int wt = wave_sum(f);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = wt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int total = 0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) total += s_w[w];
-        T.tile_count[tile] = total;
-        if (grouped(P.n_tgroups) && total) atomicAdd(tgroup_at(T, P, (int)(st - T.st), tile / kGroup), total);
     }
 }
 
@@ -2366,7 +2356,7 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
         int rc;
         if ((rc = timed_launch(h, 0, [&] { propagate(h, T); })) != KPX_OK) return rc;
         if ((rc = timed_launch(h, 1, [&] {
-                 k_prune_flags<<<h->n_prune_blocks + h->z.n_tiles, kBlock, 0, h->stream>>>(
+                 k_prune_flags<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
                      h->P, T, cur_state(h), h->n_prune_blocks);
              })) != KPX_OK)
             return rc;
@@ -2898,7 +2888,7 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
         const int np = std::max(1, std::min(h->P.n_cu, (h->z.s_max + 2 * kPropBlock - 1) / (2 * kPropBlock)));
         for (int k = 0; k < np; ++k) prop[gi].push_back(make_int4(q, k, np, h->n_prune_blocks));
         for (int k = 0; k < h->z.n_tiles; ++k) ins[gi].push_back(make_int4(q, k, h->z.n_tiles, h->n_prune_blocks));
-        const int npf = h->n_prune_blocks + h->z.n_tiles;
+        const int npf = h->n_prune_blocks;
         for (int k = 0; k < npf; ++k) prune.push_back(make_int4(q, k, npf, h->n_prune_blocks));
         for (int k = 0; k < h->n_prune_blocks; ++k) fin.push_back(make_int4(q, k, h->n_prune_blocks, h->n_prune_blocks));
     }
