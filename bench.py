@@ -96,7 +96,9 @@ def bench_args_key(a):
     """The arguments that decide which kernels run (a counter profile of the
     same command covers the same launches)."""
     return (f"--workload {a.workload} --steps {a.steps} --warmup {a.warmup} --iters {a.iters}"
-            + (f" --polish {a.polish}" if a.polish else "") + (" --cost-first" if a.cost_first else "")
+            + (f" --cost {a.cost}" if a.cost else "")
+            + (f" --polish {a.polish}" if a.polish else "") + (" --polish-goal-only" if a.polish_goal_only else "")
+            + (" --cost-first" if a.cost_first else "")
             + (f" --refine-at {a.refine_at}" if a.refine_at else ""))
 
 
@@ -174,7 +176,13 @@ def parse():
                     help="bound on the oracle sample on one core")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--polish", type=int, default=0,
-                    help="edge polish steps of every inserted node (quadrotor, TIME cost); 0 = plain")
+                    help="edge polish steps of every inserted node (quadrotor); 0 = plain")
+    ap.add_argument("--polish-w-len", type=float, default=1.0,
+                    help="weight of the path length in the polish loss (path-length cost)")
+    ap.add_argument("--polish-goal-only", action="store_true",
+                    help="polish only the nodes inserted in the goal set")
+    ap.add_argument("--cost", choices=["TIME", "PATH_LENGTH"], default=None,
+                    help="the workload's cost instead of its own")
     ap.add_argument("--cost-first", action="store_true",
                     help="propagate in the exact cost-first form (obstacle tests only for edges "
                          "that can still be their region's minimum)")
@@ -231,13 +239,18 @@ def key_cost(key, cost_kind, dt):
     return float(np.array([field], np.uint32).view(np.float32)[0])
 
 
+def make_workload(W, a, seed):
+    return W.make_workload(a.workload, seed, **({"cost": a.cost} if a.cost else {}))
+
+
 def make_planner(K, W, a, seed, polish):
-    w = W.make_workload(a.workload, seed)
+    w = make_workload(W, a, seed)
     if a.refine_at:
         w.params.refine_max = 2
     p = K.Planner(w.problem, w.params)
     if polish:
-        p.set_polish(polish)
+        p.set_polish(polish, w_len=a.polish_w_len if w.problem.cost == "PATH_LENGTH" else 0.0,
+                     goal_only=a.polish_goal_only)
     if a.cost_first:
         p.set_cost_first(True)
     return w, p
@@ -417,7 +430,7 @@ def bench_queries(a):
     import paper_2602_02846_amd as K
     import workloads as W
 
-    w0 = W.make_workload(a.workload, 0)
+    w0 = make_workload(W, a, 0)
     prob, prm = w0.problem, w0.params
     print(f"[bench] {a.workload}: {prm.n_select} x {prm.samples_per_node} slots, {prm.n_cells} regions, "
           f"cap {prm.tree_cap}; {a.warmup} + {a.steps} queries of {a.iters} iterations", file=sys.stderr,
@@ -455,6 +468,8 @@ def bench_queries(a):
                       f"every active node sharing {prm.n_select} expansion slots per iteration, ")
                    + f"{prm.n_cells} regions, cap {prm.tree_cap}"
                    + (f", edge polish {a.polish} steps per inserted node" if a.polish else "")
+                   + (f" (path-length weight {a.polish_w_len})" if a.polish and prob.cost == "PATH_LENGTH" else "")
+                   + (" of the nodes inserted in the goal set" if a.polish and a.polish_goal_only else "")
                    + (", cost-first propagate" if a.cost_first else "")
                    + (f", regions refined after {a.refine_at} iterations" if a.refine_at else ""),
                    "step": f"one query: {a.iters} iterations from the root (seed = query index)",
@@ -481,7 +496,7 @@ def tree_growth(K, W, a, window=50):
     geometrically spaced points of a run of a.tree_growth iterations, with the
     tree size and live regions at each window: prune works per region and per
     slot, so its time should follow the region count, not the tree."""
-    w = W.make_workload(a.workload, 0)
+    w = make_workload(W, a, 0)
     p = K.Planner(w.problem, w.params)
     if a.cost_first:
         p.set_cost_first(True)

@@ -354,21 +354,28 @@ int kpx_refine(kpx_handle* h, int32_t factor);
  * it inserted: the node's control u takes `steps` projected gradient steps
  *   u <- clamp(u - lr grad L(u, u, u, u), control box)
  * on the loss of the differentiable edges below (all 4 segments tied to u,
- * the margin-grown boxes, the goal centre, the given weights).  The polished
- * edge, integrated and checked as propagate does, replaces the node's edge
- * when it is valid, ends in the node's region and keeps a goal node in the
- * goal; a node that enters the goal competes for the solution (Alg. 4).
- * Regions, costs (the step count) and statuses do not change. */
+ * the margin-grown boxes, the goal centre, the given weights; w_len weighs
+ * the edge's path length).  The polished edge, integrated and checked as
+ * propagate does, replaces the node's edge when it is valid, ends in the
+ * node's region and keeps a goal node in the goal, and, under
+ * KPX_COST_PATH_LENGTH, is shorter; a node that enters the goal competes for
+ * the solution (Alg. 4).  Under KPX_COST_TIME the node's cost (its step
+ * count) does not change; under KPX_COST_PATH_LENGTH the shorter edge lowers
+ * the node's cost and its region's key (the node keeps the region and has no
+ * descendants yet), and a goal node's solution key.  Statuses do not change. */
 typedef struct kpx_polish {
     int32_t steps;           /* 0 = off (also NULL); at most 16 */
     float lr;                /* >= 0 */
     float w_ctrl, w_obst, k_obst, d_safe, w_goal;
+    float w_len;             /* weight of the path length in the loss */
+    int32_t goal_only;       /* 1: polish only the nodes inserted in the goal set */
 } kpx_polish;
 
 /* Sets edge polish for later iterations.  KPX_ERR_ARG unless the handle is a
- * KPX_QUAD12 problem with KPX_COST_TIME and steps_max <= 64, or for steps
- * outside 0..16, lr < 0 or non-finite values; KPX_ERR_DEVICE if the kernel
- * cannot get its shared memory.  Handles with polish on cannot be batched. */
+ * KPX_QUAD12 problem with steps_max <= 64, or for steps outside 0..16,
+ * lr < 0, non-finite values or goal_only outside 0..1; KPX_ERR_DEVICE if
+ * the kernel cannot get its shared memory.  Handles with polish on cannot be
+ * batched. */
 int kpx_set_polish(kpx_handle* h, const kpx_polish* p);
 
 /* Static message for a status code. */
@@ -431,9 +438,11 @@ const char* kpx_batch_last_error(const kpx_batch* b);
  * step k using segment j with floor(j n / 4) <= k < floor((j + 1) n / 4).
  * The loss of an edge is
  *   n dt + w_ctrl |u|^2 + w_obst sum_{k=1..n} softplus(k_obst (d_safe - sd(p_k)))
- *        + w_goal |p_n - goal|^2
+ *        + w_goal |p_n - goal|^2 + w_len l
  * with sd(p) the signed distance of position p to the nearest box (negative
- * inside); the gradient is with respect to the edge's 16 controls.  It is
+ * inside) and l the length of the position path (the speed integrated by the
+ * same RK4 steps, as the planner's KPX_COST_PATH_LENGTH is); the gradient is
+ * with respect to the edge's 16 controls.  It is
  * computed by reverse mode through the RK4 steps, in float32.
  *
  * Device arrays are structure-of-arrays over the edges: x0 is 12 x E
@@ -450,6 +459,7 @@ typedef struct kpx_diff_problem {
     float u_lo[4], u_hi[4];   /* control box for kpx_diff_polish's projection */
     float x_lo[12], x_hi[12]; /* state bounds (may be +-INFINITY), for validity */
     float ws_lo[3], ws_hi[3]; /* workspace, for validity */
+    float w_len;              /* weight of the path length (finite) */
 } kpx_diff_problem;
 
 typedef struct kpx_diff kpx_diff;

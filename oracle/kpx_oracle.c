@@ -610,17 +610,23 @@ static int near_tie(double a, double b, double rel)
  * node's control u takes `polish_steps` projected gradient steps
  *   u <- clamp(u - lr grad L(u, u, u, u), U)
  * on the tied loss of kpx_oracle_diff.h (complex-step gradient) over the
- * margin-grown boxes, towards the goal centre.  The polished edge replaces the
- * node's edge when the planner's own propagation finds it valid, it ends in
- * the node's region, and a goal node stays in the goal; a node that enters
- * the goal competes for the solution.  Its cost (TIME: the step count) does
- * not change.  The other side's decisions of the polished edge are passed per
+ * margin-grown boxes, towards the goal centre, with the path length weighted
+ * by polish_w_len.  The polished edge replaces the node's edge when the
+ * planner's own propagation finds it valid, it ends in the node's region, a
+ * goal node stays in the goal, and, for the path-length cost, it is shorter;
+ * a node that enters the goal competes for the solution.  For the TIME cost
+ * the node's cost (the step count) does not change; for the path-length cost
+ * the shorter edge's cost (parent cost + length, Assumption 1) replaces it,
+ * and the region's cost with it (the node has no descendants yet and keeps its
+ * region).  The other side's decisions of the polished edge are passed per
  * test: its first invalid step (negative: none given), the region and the goal
- * bit of its end state; each is adopted only where the oracle's own decision
- * of that same test lies within band, as for any propagated edge.  Returns 1
- * when the polished edge replaced the node's edge. */
+ * bit of its end state, and its accept bit for the length comparison; each is
+ * adopted only where the oracle's own decision of that same test lies within
+ * band, as for any propagated edge.  Returns 1 when the polished edge replaced
+ * the node's edge. */
 static int polish_node(const ora_problem* P, ora_tree* T, int64_t i, int was_goal, const float* grown,
-                       int32_t hint_fi, const int64_t* hint_cell, const uint8_t* hint_goal)
+                       int32_t hint_fi, const int64_t* hint_cell, const uint8_t* hint_goal,
+                       const uint8_t* hint_acc)
 {
     orad_problem D;
     memset(&D, 0, sizeof(D));
@@ -638,6 +644,7 @@ static int polish_node(const ora_problem* P, ora_tree* T, int64_t i, int was_goa
     D.k_obst = P->polish_k_obst;
     D.d_safe = P->polish_d_safe;
     D.w_goal = P->polish_w_goal;
+    D.w_len = P->polish_w_len;
     const double* x0 = &T->x[T->parent[i] * ORA_MAX_STATE];
     const int32_t n = T->steps[i];
     double u[4];
@@ -660,9 +667,17 @@ static int polish_node(const ora_problem* P, ora_tree* T, int64_t i, int was_goa
     const int64_t cell = ora_cell_of(P, e.xn, hint_cell, NULL);
     const int goal_now = ora_goal_test(P, e.xn, (double)P->goal_radius - (double)P->margin, hint_goal, NULL);
     if (cell != T->cell[i] || (was_goal && !goal_now)) return 0;
+    if (P->cost == ORA_COST_PATH) {
+        const double c_new = T->cost[T->parent[i]] + e.length;
+        int shorter = c_new < T->cost[i];
+        if (hint_acc && near_tie(c_new, T->cost[i], P->band)) shorter = *hint_acc != 0;
+        if (!shorter) return 0;
+        T->cost[i] = c_new;
+        T->tbl_cost[T->cell[i]] = c_new;
+    }
     for (int k = 0; k < ORA_MAX_STATE; ++k) T->x[i * ORA_MAX_STATE + k] = e.xn[k];
     for (int c = 0; c < 4; ++c) T->u[i * ORA_MAX_CONTROL + c] = uf[c];
-    if (!was_goal && goal_now && key_less(T->cost[i], i, T->sol_cost, T->sol_id)) {
+    if (goal_now && key_less(T->cost[i], i, T->sol_cost, T->sol_id)) {
         if (T->sol_id < 0) T->first_sol_iter = T->iter;
         T->sol_cost = T->cost[i];
         T->sol_id = i;
@@ -821,7 +836,7 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
             T->sol_id = i;
         }
     }
-    if (P->polish_steps > 0 && P->dynamics == ORA_QUAD12 && P->cost == ORA_COST_TIME) {
+    if (P->polish_steps > 0 && P->dynamics == ORA_QUAD12) {
         float* grown = (float*)malloc(sizeof(float) * 6 * (size_t)(P->n_boxes > 0 ? P->n_boxes : 1));
         for (int32_t b = 0; b < P->n_boxes; ++b)
             for (int a = 0; a < 3; ++a) {
@@ -832,7 +847,11 @@ int ora_step(const ora_problem* P, ora_tree* T, ora_cands* C, const ora_hints* H
             const int32_t hfi = (H && H->polish_first_invalid) ? H->polish_first_invalid[t] : -1;
             const int64_t* hc = (H && H->polish_cell) ? &H->polish_cell[t] : NULL;
             const uint8_t* hg = (H && H->polish_goal) ? &H->polish_goal[t] : NULL;
-            const int acc = polish_node(P, T, n_tree + t, C->goal[I[t]], grown, hfi, hc, hg);
+            const uint8_t* ha = (H && H->polish_accepted) ? &H->polish_accepted[t] : NULL;
+            /* the goal-only form leaves every node outside the goal set as inserted */
+            const int acc = (P->polish_goal_only && !C->goal[I[t]])
+                                ? 0
+                                : polish_node(P, T, n_tree + t, C->goal[I[t]], grown, hfi, hc, hg, ha);
             if (C->polished) C->polished[t] = (uint8_t)acc;
         }
         free(grown);

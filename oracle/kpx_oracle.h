@@ -70,11 +70,13 @@ typedef struct {
     uint64_t seed;
     uint32_t query_id;
     double band;               /* flag band for decisions (1e-5) */
-    /* edge polish of every inserted node (QUAD12, TIME cost; steps 0 = off):
-     * projected gradient steps on the node's control of the tied loss of
+    /* edge polish of every inserted node (QUAD12; steps 0 = off): projected
+     * gradient steps on the node's control of the tied loss of
      * kpx_oracle_diff.h over the margin-grown boxes */
     int32_t polish_steps;
     double polish_lr, polish_w_ctrl, polish_w_obst, polish_k_obst, polish_d_safe, polish_w_goal;
+    double polish_w_len;
+    int32_t polish_goal_only;  /* 1: only the nodes inserted in the goal set */
 } ora_problem;
 
 typedef struct {
@@ -136,6 +138,9 @@ typedef struct {
     const int32_t* polish_first_invalid;
     const int64_t* polish_cell;
     const uint8_t* polish_goal;
+    /* ... and whether the polished edge replaced the node's edge, adopted only
+     * where the path-length comparison (shorter or not) lies within band */
+    const uint8_t* polish_accepted;
 } ora_hints;
 
 typedef struct {

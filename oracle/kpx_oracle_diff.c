@@ -46,18 +46,30 @@ static void deriv(const orad_problem* D, const cplx* z, const cplx* u, cplx* zd)
     zd[11] = (u[3] - (D->jy - D->jx) * wp * wq) / D->jz;
 }
 
-/* classical RK4 step of size h */
-static void rk4(const orad_problem* D, cplx* z, const cplx* u, double h)
+/* speed |v| of a state (the rate of the path length) */
+static cplx speed(const cplx* z)
 {
-    cplx k1[12], k2[12], k3[12], k4[12], t[12];
+    return csqrt(z[6] * z[6] + z[7] * z[7] + z[8] * z[8]);
+}
+
+/* classical RK4 step of size h; the path length *ell (when not NULL) is one
+ * more component of the step, with rate |v| */
+static void rk4(const orad_problem* D, cplx* z, const cplx* u, double h, cplx* ell)
+{
+    cplx k1[12], k2[12], k3[12], k4[12], t[12], s1, s2, s3, s4;
     deriv(D, z, u, k1);
+    s1 = speed(z);
     for (int i = 0; i < 12; ++i) t[i] = z[i] + 0.5 * h * k1[i];
     deriv(D, t, u, k2);
+    s2 = speed(t);
     for (int i = 0; i < 12; ++i) t[i] = z[i] + 0.5 * h * k2[i];
     deriv(D, t, u, k3);
+    s3 = speed(t);
     for (int i = 0; i < 12; ++i) t[i] = z[i] + h * k3[i];
     deriv(D, t, u, k4);
+    s4 = speed(t);
     for (int i = 0; i < 12; ++i) z[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    if (ell) *ell += h / 6.0 * (s1 + 2.0 * s2 + 2.0 * s3 + s4);
 }
 
 static cplx box_sd(const float* b, const cplx* p)
@@ -109,10 +121,10 @@ static cplx loss_c(const orad_problem* D, const double* x0, const cplx* u, int32
     for (int i = 0; i < 12; ++i) z[i] = x0[i];
     if (states)
         for (int i = 0; i < 12; ++i) states[i] = x0[i];
-    cplx L = n * D->dt;
+    cplx L = n * D->dt, ell = 0.0;
     for (int i = 0; i < 16; ++i) L += D->w_ctrl * u[i] * u[i];
     for (int32_t k = 0; k < n; ++k) {
-        rk4(D, z, u + 4 * orad_segment(k, n), D->dt);
+        rk4(D, z, u + 4 * orad_segment(k, n), D->dt, &ell);
         if (states)
             for (int i = 0; i < 12; ++i) states[(k + 1) * 12 + i] = creal(z[i]);
         if (D->n_boxes > 0 && D->w_obst != 0.0)
@@ -122,7 +134,7 @@ static cplx loss_c(const orad_problem* D, const double* x0, const cplx* u, int32
         const cplx e = z[a] - D->goal[a];
         L += D->w_goal * e * e;
     }
-    return L;
+    return L + D->w_len * ell;
 }
 
 double orad_loss(const orad_problem* D, const double* x0, const double* u, int32_t n, double* states)
@@ -161,7 +173,7 @@ int32_t orad_first_invalid(const orad_problem* D, const double* x0, const double
     for (int i = 0; i < 12; ++i) z[i] = x0[i];
     for (int i = 0; i < 16; ++i) uc[i] = u[i];
     for (int32_t k = 0; k < n; ++k) {
-        rk4(D, z, uc + 4 * orad_segment(k, n), D->dt);
+        rk4(D, z, uc + 4 * orad_segment(k, n), D->dt, NULL);
         double x[12];
         for (int i = 0; i < 12; ++i) x[i] = creal(z[i]);
         for (int i = 0; i < 12; ++i)

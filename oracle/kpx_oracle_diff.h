@@ -8,8 +8,10 @@
  * Its loss is
  *   n dt + w_ctrl * sum u^2
  *        + w_obst * sum_{k=1..n} softplus(k_obst * (d_safe - sd(p_k)))
- *        + w_goal * |p_n - goal|^2,
- * sd = signed distance of the position to the nearest box (negative inside).
+ *        + w_goal * |p_n - goal|^2 + w_len * l,
+ * sd = signed distance of the position to the nearest box (negative inside),
+ * l = length of the position path, the speed |v| integrated as one more
+ * component of the same RK4 steps (the planner's path-length cost).
  * The gradient with respect to the 16 controls is taken by the complex step,
  * Im L(u + i h e_j) / h, which has no cancellation error.
  */
@@ -25,6 +27,7 @@ typedef struct {
     int32_t n_boxes;
     double goal[3];
     double w_ctrl, w_obst, k_obst, d_safe, w_goal;
+    double w_len;        /* weight of the path length */
 } orad_problem;
 
 /* Control segment of step k of an n-step edge. */

@@ -51,7 +51,7 @@ class ProblemC(C.Structure):
         ("query_id", C.c_uint32), ("band", C.c_double),
         ("polish_steps", C.c_int32), ("polish_lr", C.c_double), ("polish_w_ctrl", C.c_double),
         ("polish_w_obst", C.c_double), ("polish_k_obst", C.c_double), ("polish_d_safe", C.c_double),
-        ("polish_w_goal", C.c_double),
+        ("polish_w_goal", C.c_double), ("polish_w_len", C.c_double), ("polish_goal_only", C.c_int32),
     ]
 
 
@@ -78,7 +78,8 @@ class CandsC(C.Structure):
 
 class HintsC(C.Structure):
     _fields_ = [("first_invalid", _i32p), ("cell", _i64p), ("goal", _u8p), ("survivor", _u8p),
-                ("polish_first_invalid", _i32p), ("polish_cell", _i64p), ("polish_goal", _u8p)]
+                ("polish_first_invalid", _i32p), ("polish_cell", _i64p), ("polish_goal", _u8p),
+                ("polish_accepted", _u8p)]
 
 
 class EdgeC(C.Structure):
@@ -205,6 +206,8 @@ class Problem:
             s.polish_k_obst = f(polish.get("k_obst", 50.0))
             s.polish_d_safe = f(polish.get("d_safe", 0.02))
             s.polish_w_goal = f(polish.get("w_goal", 1.0))
+            s.polish_w_len = f(polish.get("w_len", 0.0))
+            s.polish_goal_only = int(bool(polish.get("goal_only", False)))
         self.c = s
         self.d = {"DI6": 6, "QUAD12": 12, "DUBINS6": 6}[problem.dynamics]
         self.m = {"DI6": 3, "QUAD12": 4, "DUBINS6": 3}[problem.dynamics]
@@ -404,7 +407,8 @@ class Tree:
             for name, dt, ct in (("first_invalid", np.int32, _i32p), ("cell", np.int64, _i64p),
                                  ("goal", np.uint8, _u8p), ("survivor", np.uint8, _u8p),
                                  ("polish_first_invalid", np.int32, _i32p),
-                                 ("polish_cell", np.int64, _i64p), ("polish_goal", np.uint8, _u8p)):
+                                 ("polish_cell", np.int64, _i64p), ("polish_goal", np.uint8, _u8p),
+                                 ("polish_accepted", np.uint8, _u8p)):
                 if hints.get(name) is not None:
                     a = np.ascontiguousarray(hints[name], dtype=dt)
                     keep.append(a)
@@ -502,6 +506,7 @@ class OradProblemC(C.Structure):
         ("grav", C.c_double), ("dt", C.c_double), ("boxes", _f32p), ("n_boxes", C.c_int32),
         ("goal", C.c_double * 3), ("w_ctrl", C.c_double), ("w_obst", C.c_double),
         ("k_obst", C.c_double), ("d_safe", C.c_double), ("w_goal", C.c_double),
+        ("w_len", C.c_double),
     ]
 
 
@@ -534,7 +539,7 @@ class DiffProblem:
     values widened, as everywhere in the oracle)."""
 
     def __init__(self, problem, dt, goal=None, w_ctrl=0.1, w_obst=1.0, k_obst=50.0, d_safe=0.02,
-                 w_goal=1.0):
+                 w_goal=1.0, w_len=0.0):
         f = lambda v: float(np.float32(v))  # noqa: E731
         self.problem = problem
         self.boxes = np.ascontiguousarray(problem.boxes, dtype=np.float32).reshape(-1, 6)
@@ -548,6 +553,7 @@ class DiffProblem:
         s.goal = (C.c_double * 3)(*[f(v) for v in g[:3]])
         s.w_ctrl, s.w_obst, s.k_obst, s.d_safe, s.w_goal = (f(w_ctrl), f(w_obst), f(k_obst),
                                                             f(d_safe), f(w_goal))
+        s.w_len = f(w_len)
         self.c = s
         self.ref = C.byref(s)
 

@@ -181,7 +181,8 @@ def polished_nodes(pre, post, dump):
     mask[n0:n1] = acc
     hints = {"polish_first_invalid": dump["polish_first_invalid"].astype(np.int32),
              "polish_cell": dump["polish_cell"].astype(np.int64),
-             "polish_goal": dump["polish_goal"].astype(np.uint8)}
+             "polish_goal": dump["polish_goal"].astype(np.uint8),
+             "polish_accepted": dump["polish_accepted"].astype(np.uint8)}
     return mask, hints
 
 

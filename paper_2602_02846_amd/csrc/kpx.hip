@@ -1046,8 +1046,9 @@ size_t polish_lds_bytes(int n_boxes)
            sizeof(unsigned short) * kPolishCkpt * kpxd::kCkpt * kPolishBlock;
 }
 
+template <int COST>
 __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T, DevState* st, kpxd::DiffConst C,
-                                                         int steps, float lr)
+                                                         int steps, float lr, int goal_only)
 {
     extern __shared__ float4 plds[];
     const int nb = P.n_boxes;
@@ -1078,6 +1079,14 @@ __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T
 #pragma unroll
     for (int a = 0; a < 3; ++a) xo[a] = T.x[(long long)a * P.cap + i];
     const bool was_goal = in_goal(P, xo);
+    if (goal_only && !was_goal) {  // left as inserted
+        if (T.d_pfi) {
+            T.d_pfi[t] = 0;
+            T.d_pcell[t] = -1;
+            T.d_pflag[t] = 0;
+        }
+        return;
+    }
     const int nb_pen = C.w_obst != 0.f ? nb : 0;
     for (int r = 0; r < steps; ++r) {
         float uu[16], gu[16];
@@ -1101,7 +1110,7 @@ __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T
     bool ok = true;
     int fi = 0;
     for (int k = 1; k <= n && ok; ++k) {
-        rk4<kQUAD12, kTIME>(H, x, ur, len);
+        rk4<kQUAD12, COST>(H, x, ur, len);
         ok = in_bounds<kQUAD12>(H, x, P.os_lo, P.os_hi);
         for (int b = 0; b < nb; ++b) ok = ok && !in_box(sbox + 2 * b, x[0], x[1], x[2]);
         if (!ok) fi = k;
@@ -1111,7 +1120,16 @@ __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T
     for (int c = 0; c < 12; ++c) xe[c] = x[c] * (rev_state(kQUAD12, c) ? k2Pi : 1.f);
     const bool goal_now = ok && in_goal(P, xe);
     const int cell = ok ? cell_of(P, xe, xe + 6) : -1;
-    const bool accept = ok && cell == T.cell[i] && (!was_goal || goal_now);
+    // the path-length cost: the polished edge must also be shorter (its cost
+    // formed as propagate forms an arrival's)
+    uint32_t cf = T.cost[i];
+    bool shorter = true;
+    if constexpr (COST == kPATH) {
+        const float c_new = __uint_as_float(T.cost[p]) + len;
+        shorter = c_new < __uint_as_float(cf);
+        cf = __float_as_uint(c_new);
+    }
+    const bool accept = ok && cell == T.cell[i] && (!was_goal || goal_now) && shorter;
     if (T.d_pfi) {  // the decisions, for the oracle's replay
         T.d_pfi[t] = fi;
         T.d_pcell[t] = cell;
@@ -1122,8 +1140,14 @@ __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T
     for (int q = 0; q < 12; ++q) T.x[(long long)q * P.cap + i] = xe[q];
 #pragma unroll
     for (int q = 0; q < 4; ++q) T.u[(long long)q * P.cap + i] = u[q];
-    if (goal_now && !was_goal)
-        atomicMin(&st->sol, ((unsigned long long)T.cost[i] << 32) | (unsigned long long)(uint32_t)i);
+    const unsigned long long key = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)i;
+    if constexpr (COST == kPATH) {
+        // a node inserted this iteration has no descendants: its lower cost
+        // re-keys only its own region, which it keeps
+        T.cost[i] = cf;
+        T.tbl[cell] = key;
+    }
+    if (goal_now && (!was_goal || COST == kPATH)) atomicMin(&st->sol, key);
 }
 
 // Closes the iteration and selects the next iteration's nodes with one block
@@ -1843,6 +1867,7 @@ struct kpx_handle {
     int refined = 1;                          // total refinement factor per axis so far
     int polish_steps = 0;                     // edge polish of inserted nodes (0: off)
     float polish_lr = 0.f;
+    int polish_goal_only = 0;                 // 1: polish only nodes inserted in the goal set
     bool cost_first = false;                  // propagate in the cost-first form
     int prop_threads = kPropBlock;            // propagate block size (kPropBlock or kPropBlockWide)
     kpxd::DiffConst polish_c{};
@@ -2361,10 +2386,18 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
              })) != KPX_OK)
             return rc;
         if ((rc = timed_launch(h, 2, [&] { insert(h, T); })) != KPX_OK) return rc;
-        if (h->polish_steps > 0)
-            k_polish<<<(h->P.surv_max + kPolishBlock - 1) / kPolishBlock, kPolishBlock,
-                       polish_lds_bytes(h->P.n_boxes), h->stream>>>(h->P, T, cur_state(h), h->polish_c,
-                                                                     h->polish_steps, h->polish_lr);
+        if (h->polish_steps > 0) {
+            const dim3 grid((h->P.surv_max + kPolishBlock - 1) / kPolishBlock);
+            const size_t lds = polish_lds_bytes(h->P.n_boxes);
+            if (h->P.cost == kPATH)
+                k_polish<kPATH><<<grid, kPolishBlock, lds, h->stream>>>(h->P, T, cur_state(h), h->polish_c,
+                                                                        h->polish_steps, h->polish_lr,
+                                                                        h->polish_goal_only);
+            else
+                k_polish<kTIME><<<grid, kPolishBlock, lds, h->stream>>>(h->P, T, cur_state(h), h->polish_c,
+                                                                        h->polish_steps, h->polish_lr,
+                                                                        h->polish_goal_only);
+        }
         if ((rc = timed_launch(h, 3, [&] {
                  k_finalize_select<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
                      h->P, T, cur_state(h), next_state(h), h->n_prune_blocks);
@@ -2620,14 +2653,16 @@ int kpx_set_polish(kpx_handle* h, const kpx_polish* p)
     }
     if (p->steps < 0 || p->steps > 16 || !(p->lr >= 0.f) || !std::isfinite(p->lr))
         return fail(h, KPX_ERR_ARG, "polish: steps in 0..16 and a finite lr >= 0");
-    const float w[5] = {p->w_ctrl, p->w_obst, p->k_obst, p->d_safe, p->w_goal};
+    if (p->goal_only != 0 && p->goal_only != 1) return fail(h, KPX_ERR_ARG, "polish: goal_only is 0 or 1");
+    const float w[6] = {p->w_ctrl, p->w_obst, p->k_obst, p->d_safe, p->w_goal, p->w_len};
     for (float v : w)
         if (!std::isfinite(v)) return fail(h, KPX_ERR_ARG, "polish: finite weights");
-    if (h->P.dyn != kQUAD12 || h->P.cost != kTIME)
-        return fail(h, KPX_ERR_ARG, "polish: the quadrotor model with the TIME cost only");
+    if (h->P.dyn != kQUAD12)
+        return fail(h, KPX_ERR_ARG, "polish: the quadrotor model only");
     if (h->prm.steps_max > kPolishCkpt * kpxd::kCkpt)
         return fail(h, KPX_ERR_ARG, "polish: edges of at most 64 steps");
-    KPX_HIP(h, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_polish),
+    KPX_HIP(h, hipFuncSetAttribute(h->P.cost == kPATH ? reinterpret_cast<const void*>(&k_polish<kPATH>)
+                                                      : reinterpret_cast<const void*>(&k_polish<kTIME>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)polish_lds_bytes(h->P.n_boxes)));
     kpxd::DiffConst& C = h->polish_c;
@@ -2648,6 +2683,7 @@ int kpx_set_polish(kpx_handle* h, const kpx_polish* p)
     C.k_obst = p->k_obst;
     C.d_safe = p->d_safe;
     C.w_goal = p->w_goal;
+    C.w_len = p->w_len;
     for (int c = 0; c < 4; ++c) {
         C.u_lo[c] = h->prob.u_lo[c];
         C.u_hi[c] = h->prob.u_hi[c];
@@ -2655,6 +2691,7 @@ int kpx_set_polish(kpx_handle* h, const kpx_polish* p)
     C.n_boxes = h->P.n_boxes;
     h->polish_steps = p->steps;
     h->polish_lr = p->lr;
+    h->polish_goal_only = p->goal_only;
     return KPX_OK;
 }
 

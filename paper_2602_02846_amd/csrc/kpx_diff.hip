@@ -107,6 +107,7 @@ int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out)
     if (p->n_boxes < 0 || p->n_boxes > kDiffMaxBoxes || (p->n_boxes > 0 && !p->boxes)) return KPX_ERR_ARG;
     const float m = p->dyn_params[0], jx = p->dyn_params[1], jy = p->dyn_params[2], jz = p->dyn_params[3];
     if (!(m > 0.f) || !(jx > 0.f) || !(jy > 0.f) || !(jz > 0.f) || !(p->dt > 0.f)) return KPX_ERR_ARG;
+    if (!std::isfinite(p->w_len)) return KPX_ERR_ARG;
     for (int c = 0; c < 4; ++c)
         if (!(p->u_lo[c] <= p->u_hi[c])) return KPX_ERR_ARG;
     for (int b = 0; b < p->n_boxes; ++b)
@@ -135,6 +136,7 @@ int kpx_diff_create(const kpx_diff_problem* p, void* hip_stream, kpx_diff** out)
     C.k_obst = p->k_obst;
     C.d_safe = p->d_safe;
     C.w_goal = p->w_goal;
+    C.w_len = p->w_len;
     for (int c = 0; c < 4; ++c) {
         C.u_lo[c] = p->u_lo[c];
         C.u_hi[c] = p->u_hi[c];

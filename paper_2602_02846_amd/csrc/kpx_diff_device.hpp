@@ -8,10 +8,11 @@
 // control segments; step k uses segment j with floor(j n / 4) <= k <
 // floor((j + 1) n / 4).  Its loss
 //   n dt + w_ctrl |u|^2 + w_obst sum_{k=1..n} softplus(k_obst (d_safe - sd(p_k)))
-//        + w_goal |p_n - goal|^2
+//        + w_goal |p_n - goal|^2 + w_len l
 // adds to the edge's duration a control effort, a smooth obstacle penalty on
-// the signed distance sd of each substep position to the nearest box, and a
-// goal distance.  The forward pass keeps the state every 8 steps; the adjoint
+// the signed distance sd of each substep position to the nearest box, a goal
+// distance, and the length l of the position path (the speed |v| integrated
+// by the same RK4 steps, as the planner's path-length cost is).  The forward pass keeps the state every 8 steps; the adjoint
 // recomputes each 8-step block from its checkpoint and runs the adjoint of the
 // RK4 steps through it, with the vector-Jacobian product of the dynamics
 // written out by hand.
@@ -28,7 +29,7 @@ constexpr int kCkpt = 8;  // steps per checkpoint block
 struct DiffConst {
     float inv_m, inv_j[3], gyro[3], grav, dt;
     float goal[3];
-    float w_ctrl, w_obst, k_obst, d_safe, w_goal;
+    float w_ctrl, w_obst, k_obst, d_safe, w_goal, w_len;
     float u_lo[4], u_hi[4];
     float x_lo[12], x_hi[12], ws_lo[3], ws_hi[3];
     int n_boxes;
@@ -99,36 +100,61 @@ __device__ __forceinline__ void vjp_quad(const DiffConst& C, const float* x, con
     gx[11] -= w9 * C.gyro[0] * wq + w10 * C.gyro[1] * wp;
 }
 
-__device__ __forceinline__ void rk4_step(const DiffConst& C, float* x, const float* u)
+__device__ __forceinline__ float speed(const float* x)
+{
+    return sqrtf(fmaf(x[6], x[6], fmaf(x[7], x[7], x[8] * x[8])));
+}
+
+// g[6..8] += c v / |v| (the gradient of c |v|; zero at rest)
+__device__ __forceinline__ void add_speed_grad(const float* x, float c, float* g)
+{
+    const float s = speed(x);
+    if (!(s > 0.f)) return;
+    const float q = c / s;
+#pragma unroll
+    for (int i = 6; i < 9; ++i) g[i] = fmaf(q, x[i], g[i]);
+}
+
+// One RK4 step; when ell is not null it also advances the path length by the
+// RK4 combination of the speeds at the four stage states.
+__device__ __forceinline__ void rk4_step(const DiffConst& C, float* x, const float* u, float* ell = nullptr)
 {
     const float h = C.dt, h2 = 0.5f * C.dt, h6 = C.dt / 6.0f;
     float k[12], acc[12], t[12];
+    float sacc = 0.f;
+    if (ell) sacc = speed(x);
     f_quad(C, x, u, k);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
         acc[i] = k[i];
         t[i] = fmaf(h2, k[i], x[i]);
     }
+    if (ell) sacc = fmaf(2.f, speed(t), sacc);
     f_quad(C, t, u, k);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
         acc[i] = fmaf(2.f, k[i], acc[i]);
         t[i] = fmaf(h2, k[i], x[i]);
     }
+    if (ell) sacc = fmaf(2.f, speed(t), sacc);
     f_quad(C, t, u, k);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
         acc[i] = fmaf(2.f, k[i], acc[i]);
         t[i] = fmaf(h, k[i], x[i]);
     }
+    if (ell) *ell = fmaf(h6, sacc + speed(t), *ell);
     f_quad(C, t, u, k);
 #pragma unroll
     for (int i = 0; i < 12; ++i) x[i] = fmaf(h6, acc[i] + k[i], x[i]);
 }
 
 // Adjoint of one RK4 step from x: lam (dL/dx_{k+1}) becomes dL/dx_k, and
-// gu accumulates dL/du through this step.  The stages are recomputed.
-__device__ __forceinline__ void rk4_vjp(const DiffConst& C, const float* x, const float* u, float* lam, float* gu)
+// gu accumulates dL/du through this step.  The stages are recomputed.  With
+// wl != 0 the step's path-length increment, weighted by wl, is part of the
+// loss: each stage state's speed adds its RK4 weight times wl v / |v|.
+__device__ __forceinline__ void rk4_vjp(const DiffConst& C, const float* x, const float* u, float* lam, float* gu,
+                                        float wl = 0.f)
 {
     const float h = C.dt, h2 = 0.5f * C.dt, h6 = C.dt / 6.0f, h3 = C.dt / 3.0f;
     float k1[12], k2[12], k3[12], x2[12], x3[12], x4[12];
@@ -149,6 +175,7 @@ __device__ __forceinline__ void rk4_vjp(const DiffConst& C, const float* x, cons
         g[i] = 0.f;
     }
     vjp_quad(C, x4, u, a, g, gu);  // g = dL/dx4
+    if (wl != 0.f) add_speed_grad(x4, wl * h6, g);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
         out[i] += g[i];
@@ -156,6 +183,7 @@ __device__ __forceinline__ void rk4_vjp(const DiffConst& C, const float* x, cons
         g[i] = 0.f;
     }
     vjp_quad(C, x3, u, a, g, gu);
+    if (wl != 0.f) add_speed_grad(x3, wl * h3, g);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
         out[i] += g[i];
@@ -163,6 +191,7 @@ __device__ __forceinline__ void rk4_vjp(const DiffConst& C, const float* x, cons
         g[i] = 0.f;
     }
     vjp_quad(C, x2, u, a, g, gu);
+    if (wl != 0.f) add_speed_grad(x2, wl * h3, g);
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
         out[i] += g[i];
@@ -170,6 +199,7 @@ __device__ __forceinline__ void rk4_vjp(const DiffConst& C, const float* x, cons
         g[i] = 0.f;
     }
     vjp_quad(C, x, u, a, g, gu);
+    if (wl != 0.f) add_speed_grad(x, wl * h6, g);
 #pragma unroll
     for (int i = 0; i < 12; ++i) lam[i] = out[i] + g[i];
 }
@@ -284,7 +314,8 @@ __device__ __forceinline__ float edge_pass(const DiffConst& C, const float4* sbo
     float x[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) x[i] = x0[i];
-    float pen = 0.f;
+    float pen = 0.f, ell = 0.f;
+    const bool with_len = C.w_len != 0.f;  // uniform
     first_bad = 0;
     for (int k = 0; k < n; ++k) {
         if (k % kCkpt == 0 && need_grad)
@@ -292,7 +323,7 @@ __device__ __forceinline__ float edge_pass(const DiffConst& C, const float4* sbo
             for (int i = 0; i < 12; ++i) ck[((k / kCkpt) * 12 + i) * stride] = x[i];
         float us[4];
         segment_controls(u, (k >= b1) + (k >= b2) + (k >= b3), us);
-        rk4_step(C, x, us);
+        rk4_step(C, x, us, with_len ? &ell : nullptr);
         const int bi = nearest_box(sce, nb, x);
         if (need_grad) nbx[k * stride] = (unsigned short)bi;
         pen += penalty(C, sbox, bi, x, nullptr);
@@ -322,7 +353,7 @@ __device__ __forceinline__ float edge_pass(const DiffConst& C, const float4* sbo
         gd2 = fmaf(d, d, gd2);
         lam[a] = 2.f * C.w_goal * d;
     }
-    const float L = n * C.dt + C.w_ctrl * u2 + pen + C.w_goal * gd2;
+    const float L = n * C.dt + C.w_ctrl * u2 + pen + C.w_goal * gd2 + C.w_len * ell;
     if (!need_grad) return L;
     // backward, block by block from the last: recompute the block's states
     // from its checkpoint, then the adjoint of its steps in reverse; x still
@@ -357,7 +388,7 @@ __device__ __forceinline__ float edge_pass(const DiffConst& C, const float4* sbo
             segment_controls(u, seg, us);
             const int bi = nb > 0 ? (int)(short)nbx[k * stride] : -1;
             penalty(C, sbox, bi, xb[t + 1], lam);  // the penalty term of x_{k+1}
-            rk4_vjp(C, xb[t], us, lam, gs);
+            rk4_vjp(C, xb[t], us, lam, gs, C.w_len);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 gu[c] += seg == 0 ? gs[c] : 0.f;

@@ -26,7 +26,7 @@ class DiffProblemC(C.Structure):
                 ("k_obst", C.c_float), ("d_safe", C.c_float), ("w_goal", C.c_float),
                 ("u_lo", C.c_float * 4), ("u_hi", C.c_float * 4),
                 ("x_lo", C.c_float * 12), ("x_hi", C.c_float * 12),
-                ("ws_lo", C.c_float * 3), ("ws_hi", C.c_float * 3)]
+                ("ws_lo", C.c_float * 3), ("ws_hi", C.c_float * 3), ("w_len", C.c_float)]
 
 
 _bound = False
@@ -50,7 +50,7 @@ def _lib():
 
 
 def diff_problem_struct(problem, dt, goal=None, w_ctrl=0.1, w_obst=1.0, k_obst=50.0, d_safe=0.02,
-                        w_goal=1.0):
+                        w_goal=1.0, w_len=0.0):
     """kpx_diff_problem from a workloads.Problem (QUAD12); returns (struct,
     kept-alive boxes).  The goal defaults to the problem's goal centre."""
     boxes = np.ascontiguousarray(problem.boxes, dtype=np.float32).reshape(-1, 6)
@@ -61,6 +61,7 @@ def diff_problem_struct(problem, dt, goal=None, w_ctrl=0.1, w_obst=1.0, k_obst=5
     s.n_boxes = boxes.shape[0]
     s.goal = _f(problem.goal_center if goal is None else goal, 3)
     s.w_ctrl, s.w_obst, s.k_obst, s.d_safe, s.w_goal = w_ctrl, w_obst, k_obst, d_safe, w_goal
+    s.w_len = w_len
     s.u_lo = _f(problem.u_lo, 4)
     s.u_hi = _f(problem.u_hi, 4)
     s.x_lo = _f(problem.x_lo, 12)

@@ -104,7 +104,8 @@ STATS_DTYPE = np.dtype([
 
 class PolishC(C.Structure):
     _fields_ = [("steps", C.c_int32), ("lr", C.c_float), ("w_ctrl", C.c_float), ("w_obst", C.c_float),
-                ("k_obst", C.c_float), ("d_safe", C.c_float), ("w_goal", C.c_float)]
+                ("k_obst", C.c_float), ("d_safe", C.c_float), ("w_goal", C.c_float),
+                ("w_len", C.c_float), ("goal_only", C.c_int32)]
 
 
 _lib = None
@@ -400,9 +401,12 @@ class Planner:
         return out
 
     def set_polish(self, steps: int = 3, lr: float = 0.01, w_ctrl: float = 0.1, w_obst: float = 1.0,
-                   k_obst: float = 50.0, d_safe: float = 0.02, w_goal: float = 1.0):
-        """Edge polish of the nodes each later iteration inserts (steps = 0: off)."""
-        p = PolishC(int(steps), lr, w_ctrl, w_obst, k_obst, d_safe, w_goal)
+                   k_obst: float = 50.0, d_safe: float = 0.02, w_goal: float = 1.0, w_len: float = 0.0,
+                   goal_only: bool = False):
+        """Edge polish of the nodes each later iteration inserts (steps = 0:
+        off); w_len weighs the edge's path length in the loss; goal_only
+        polishes only the nodes inserted in the goal set."""
+        p = PolishC(int(steps), lr, w_ctrl, w_obst, k_obst, d_safe, w_goal, w_len, int(bool(goal_only)))
         self._check(lib().kpx_set_polish(self.h, C.byref(p)))
 
     def refine(self, factor: int = 2):

@@ -156,6 +156,30 @@ def test_scene_without_boxes_and_other_weights(kpx, ora):
     _check_grad(ora, D, b.x0, b.u, b.n, grad, range(0, 260, 5))
 
 
+def test_path_length_term_matches_oracle(kpx, ora):
+    """The loss with the path length weighted in, and its gradient through
+    the speeds at every RK4 stage state."""
+    from paper_2602_02846_amd.diff import Rollout
+
+    b = W.diff_workload(5, n_edges=260)
+    kw = dict(w_len=2.0)
+    R = Rollout(b.problem, b.dt, **kw)
+    D = ora.DiffProblem(b.problem, b.dt, **kw)
+    loss, grad = _run(R, b.x0, b.u, b.n)
+    _check_loss(ora, D, b, loss, range(0, 260, 2))
+    worst = _check_grad(ora, D, b.x0, b.u, b.n, grad, range(0, 260, 5))
+    print(f"max-norm relative gradient error with the length term {worst:.2e}")
+    # the term matters: without it most of these gradients would miss the
+    # tolerance they meet
+    D0 = ora.DiffProblem(b.problem, b.dt)
+    far = 0
+    idx = range(0, 260, 5)
+    for e in idx:
+        g0 = ora.diff_grad(D0, b.x0[e], b.u[e], int(b.n[e]))
+        far += np.max(np.abs(grad[e] - g0)) / np.max(np.abs(g0)) > 1e-4
+    assert far >= 0.8 * len(idx), far
+
+
 def test_degenerate_edges(scene):
     import torch
 

@@ -42,6 +42,66 @@ def test_lockstep_with_polish(kpx, ora, seed):
     pl.close()
 
 
+POLISH_PATH = dict(steps=3, lr=0.01, w_len=1.0)
+
+
+@pytest.mark.parametrize("seed", [5, 8])
+def test_lockstep_with_path_length_polish(kpx, ora, seed):
+    """The path-length cost: a polished edge that is shorter lowers its node's
+    cost and its region's key (and the solution's, for a goal node); the
+    oracle replays every decision, adopting the GPU's only within the band."""
+    w = W.make_workload("quad12", seed, cost="PATH_LENGTH", **LOCK)
+    P = ora.Problem(w.problem, w.params, polish=POLISH_PATH)
+    pl = kpx.Planner(w.problem, w.params)
+    pl.set_polish(**POLISH_PATH)
+    lowered = 0
+    rep = parity.new_report()
+    for _ in range(20):
+        pre = pl.snapshot()
+        n0 = int(pre["counters"]["n_tree"])
+        rep = parity.lockstep(ora, P, pl, 1, rep)
+        post = pl.snapshot()
+        # nodes whose polished edge was accepted: their cost is below the
+        # unpolished arrival's key, which the dump still holds
+        dump = pl.read_dump()
+        surv = np.flatnonzero(dump["survivor"][: dump["n_slots"]])
+        keys = (dump["key"][surv] >> np.uint64(32)).astype(np.uint32).view(np.float32)
+        costs = post["cost"][n0:n0 + len(surv)].view(np.float32)
+        acc = dump["polish_accepted"][: len(surv)].astype(bool)
+        assert np.all(costs[acc] < keys[acc]) and np.all(costs[~acc] == keys[~acc])
+        lowered += int(acc.sum())
+    print(seed, rep, "lowered", lowered)
+    assert rep["iterations"] == 20
+    assert lowered > 0
+    pl.close()
+
+
+def test_lockstep_with_goal_only_path_length_polish(kpx, ora):
+    """Only the nodes inserted in the goal set are polished (the others stay
+    as inserted); a shorter polished edge lowers the solution key.  The goal
+    ball is moved to the start's side of the wall (0.3, 0.5, 0.5), radius 0.1,
+    so that this small query inserts goal nodes early."""
+    pol = dict(POLISH_PATH, steps=6, goal_only=True)
+    w = W.make_workload("quad12", 0, cost="PATH_LENGTH", **LOCK)
+    w.problem.goal_center = np.array([0.3, 0.5, 0.5], np.float32)
+    w.problem.goal_radius = float(np.float32(0.1))
+    P = ora.Problem(w.problem, w.params, polish=pol)
+    pl = kpx.Planner(w.problem, w.params)
+    pl.set_polish(**pol)
+    rep = parity.new_report()
+    goal_nodes = 0
+    for _ in range(40):
+        rep = parity.lockstep(ora, P, pl, 1, rep)
+        d = pl.read_dump()
+        S = d["n_slots"]
+        goal_nodes += int((d["goal"][:S].astype(bool) & d["survivor"][:S].astype(bool)).sum())
+    c = pl.counters()
+    print(rep, "goal nodes inserted", goal_nodes, "first solution at", c["first_solution_iteration"])
+    assert rep["iterations"] == 40
+    assert goal_nodes > 0 and c["first_solution_iteration"] >= 0
+    pl.close()
+
+
 def test_polish_arguments(kpx):
     di = W.make_workload("di6", 0)
     pd = kpx.Planner(di.problem, di.params)
@@ -51,8 +111,10 @@ def test_polish_arguments(kpx):
     pd.close()
     qp = W.make_workload("quad12", 0, cost="PATH_LENGTH", **LOCK)
     pp = kpx.Planner(qp.problem, qp.params)
+    pp.set_polish(3, w_len=1.0)  # the path-length cost is polished too
+    pp.set_polish(3, w_len=1.0, goal_only=True)
     with pytest.raises(kpx.KPXError):
-        pp.set_polish(3)
+        pp.set_polish(3, w_len=float("nan"))
     pp.close()
     q = W.make_workload("quad12", 0, **LOCK)
     pq = kpx.Planner(q.problem, q.params)

@@ -91,3 +91,78 @@ def test_gradient_closed_form_without_scene_terms(ora):
         g = ora.diff_grad(D, b.x0[e], b.u[e], int(b.n[e]))
         np.testing.assert_allclose(g, 2 * float(np.float32(0.1)) * b.u[e].astype(np.float64),
                                    rtol=1e-14, atol=1e-14)
+
+
+def _edge(b, v0, thrust):
+    """An edge from a level hover state at (0.5, 0.5, 0.5) with velocity v0 and
+    a constant control (thrust, zero torques) in all four segments."""
+    x0 = np.zeros(12)
+    x0[:3] = 0.5
+    x0[6:9] = v0
+    u = np.tile(np.array([thrust, 0.0, 0.0, 0.0]), 4)
+    return x0, u
+
+
+def test_path_length_at_constant_velocity(ora):
+    """Level hover thrust (T = m g) and zero torques keep a horizontal
+    velocity constant: the path length is |v| n dt."""
+    b = W.diff_workload(0, n_edges=1)
+    D = ora.DiffProblem(b.problem, b.dt, w_ctrl=0.0, w_obst=0.0, w_goal=0.0, w_len=1.0)
+    m, g = float(np.float32(b.problem.dyn_params[0])), float(np.float32(b.problem.dyn_params[4]))
+    dt = float(np.float32(b.dt))
+    for v0, n in (((0.3, -0.4, 0.0), 20), ((0.0, 0.7, 0.0), 33)):
+        x0, u = _edge(b, v0, m * g)
+        L = ora.diff_loss(D, x0, u, n)
+        assert abs((L - n * dt) - np.linalg.norm(v0) * n * dt) <= 1e-13
+
+
+def test_path_length_in_free_fall(ora):
+    """Zero thrust from rest: |v| = g t, so the length is g T^2 / 2, which
+    the RK4 steps integrate exactly."""
+    b = W.diff_workload(0, n_edges=1)
+    D = ora.DiffProblem(b.problem, b.dt, w_ctrl=0.0, w_obst=0.0, w_goal=0.0, w_len=2.5)
+    g = float(np.float32(b.problem.dyn_params[4]))
+    dt = float(np.float32(b.dt))
+    for n in (7, 30):
+        x0, u = _edge(b, (0.0, 0.0, 0.0), 0.0)
+        L = ora.diff_loss(D, x0, u, n)
+        T = n * dt
+        assert abs((L - T) / 2.5 - 0.5 * g * T * T) <= 1e-13
+
+
+def test_path_length_gradient_against_central_differences(ora):
+    b = W.diff_workload(3, n_edges=4)
+    D = ora.DiffProblem(b.problem, b.dt, w_len=3.0)
+    D0 = ora.DiffProblem(b.problem, b.dt, w_len=0.0)
+    for e in range(4):
+        n = int(b.n[e])
+        u = b.u[e].astype(np.float64)
+        g = ora.diff_grad(D, b.x0[e], u, n)
+        fd = np.zeros(16)
+        for j in range(16):
+            h = 1e-6 * max(1.0, abs(u[j]))
+            up, um = u.copy(), u.copy()
+            up[j] += h
+            um[j] -= h
+            fd[j] = (ora.diff_loss(D, b.x0[e], up, n) - ora.diff_loss(D, b.x0[e], um, n)) / (2 * h)
+        assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(g), (g, fd)
+        # the length term changes the gradient (it is not silently dropped)
+        assert np.linalg.norm(g - ora.diff_grad(D0, b.x0[e], u, n)) > 1e-3 * np.linalg.norm(g)
+
+
+def test_path_length_matches_the_planner_oracle(ora):
+    """The rollout's length term equals the planner oracle's path-length cost
+    of the same edge (one control for all segments)."""
+    w = W.make_workload("quad12", 0, cost="PATH_LENGTH")
+    P = ora.Problem(w.problem, w.params)
+    b = W.diff_workload(4, n_edges=6)
+    D = ora.DiffProblem(b.problem, b.dt, w_ctrl=0.0, w_obst=0.0, w_goal=0.0, w_len=1.0)
+    dt = float(np.float32(b.dt))
+    assert dt == float(np.float32(w.params.dt))
+    for e in range(6):
+        n = int(b.n[e])
+        u4 = b.u[e, :4].astype(np.float64)
+        L = ora.diff_loss(D, b.x0[e], np.tile(u4, 4), n)
+        length = ora.integrate(P, b.x0[e].astype(np.float64), u4, n)[12]  # the path-length component
+        assert length > 0.0
+        assert abs((L - n * dt) - length) <= 1e-12 * max(1.0, length)
