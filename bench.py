@@ -280,7 +280,7 @@ def run_queries(K, W, a, polish, timing):
         p.sync()
         p.close()
     rates, spans, edges_all, iters_all, wall, full = [], [], 0, 0, 0.0, 0
-    t_first, costs = [], []
+    t_first, costs, unsolved = [], [], []
     at_budget = {b: [] for b in BUDGETS_MS}
     ksum = {k: 0.0 for k in KERNELS}
     klaunch = {k: 0 for k in KERNELS}
@@ -312,6 +312,8 @@ def run_queries(K, W, a, polish, timing):
         if t is not None:
             t_first.append(t)
             costs.append(p.solution()["cost"])
+        else:
+            unsolved.append(seed)
         t_ms = (st["t_end"].astype(np.float64) - float(st["t_begin"][0])) / rate_hz * 1e3
         for b in BUDGETS_MS:
             keys = st["solution_key"][t_ms <= b]
@@ -336,7 +338,7 @@ def run_queries(K, W, a, polish, timing):
             print(f"[bench] {seed + 1} queries timed", file=sys.stderr, flush=True)
     sols = {
         "queries": a.steps, "iterations": a.iters, "polish_steps": polish, "refine_at": a.refine_at,
-        "solved": len(t_first),
+        "solved": len(t_first), "unsolved_seeds": unsolved,
         "time_to_first_solution_ms_median": round(float(np.median(t_first)), 3) if t_first else None,
         "cost_median": round(float(np.median(costs)), 4) if costs else None,
         "cost_at_budget_median": {f"{b:g}ms": (None if not np.isfinite(np.median(v)) else
