@@ -56,6 +56,12 @@ constexpr int kParMax = 256;              // parent states staged per chunk (at 
 constexpr int kPropBlock = 256;           // propagate: one wave per SIMD, one block per CU
 constexpr int kPropBlockWide = 512;       // ... or two, for cheap models at large sizes
 constexpr int kStatsCap = 1 << 16;
+// regions per thread of prune and the close: one for a query of fewer than
+// kRptRegions regions (short blocks, each a few dependent loads, all resident
+// at once); four for larger ones and for batches, whose regions would
+// otherwise need many successive generations of resident blocks
+constexpr int kRptBatch = 4;
+constexpr long long kRptRegions = 1LL << 20;
 constexpr int kMaxPath = 1 << 16;
 
 struct DevState {
@@ -680,112 +686,138 @@ __global__ __launch_bounds__(NT) void k_propagate(DevProblem P, DevPtrs T, DevSt
 
 // ------------------------------------------------------------------ prune + survivor flags
 
+// One block per region block of RPT x kBlock regions: thread t of block b
+// holds regions c = b RPT kBlock + j kBlock + t (j < RPT), so that each slice
+// j is read coalesced and the block's regions keep their order slice by slice.
+template <int RPT>
 __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevPtrs& T, DevState* st,
                                                  int blk, int n_prune_blocks)
 {
     __shared__ int s_w[kBlock / 64], s_w2[kBlock / 64], s_w3[kBlock / 64];
     if (blk >= n_prune_blocks) return;
-    {
-        // Alg. 3 for the owner of region c (every live node owns its region);
-        // also records whether the region's node is active after this
-        // iteration, and per block the active regions on either side of the
-        // selection cursor.  A region an arrival took marks that slot the
-        // survivor (its key is the region's minimum) and counts it in its
-        // 256-slot tile, for the ranks insert gives the survivors.
-        const int c = blk * kBlock + threadIdx.x;
-        const unsigned long long key = T.tbl[min(c, P.n_cells - 1)];
-        const int full = st->full, cur = st->cursor_next;
-        const long long n_tree = st->n_tree;
-        if (full) return;  // kernel-uniform
-        uint8_t a = 0;
-        bool owned = false;  // a tree node owns the region
-        if (c < P.n_cells && key != kEmpty) {
-            const uint32_t o = (uint32_t)key;
-            if ((long long)o >= n_tree) {
+    // Alg. 3 for the owner of each region (every live node owns its region);
+    // also records whether the region's node is active after this iteration,
+    // and per block the active regions on either side of the selection
+    // cursor.  A region an arrival took marks that slot the survivor (its key
+    // is the region's minimum) and counts it in its 256-slot tile, for the
+    // ranks insert gives the survivors.
+    const int base = blk * kBlock * RPT + (int)threadIdx.x;
+    unsigned long long key[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) key[j] = T.tbl[min(base + j * kBlock, P.n_cells - 1)];
+    const int full = st->full, cur = st->cursor_next;
+    const long long n_tree = st->n_tree;
+    if (full) return;  // kernel-uniform
+    uint8_t a[RPT], s[RPT];
+    bool owned[RPT];  // a tree node owns the region
+    int ic0[RPT];
+    uint32_t o[RPT];
+    int4 A[RPT], B[RPT];
+    // every owner's status, count and first ancestor list in one round trip
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int c = base + j * kBlock;
+        a[j] = 0;
+        owned[j] = false;
+        o[j] = (uint32_t)key[j];
+        if (c < P.n_cells && key[j] != kEmpty) {
+            if ((long long)o[j] >= n_tree) {
                 // an arrival of this iteration owns it: that slot is the
                 // region's survivor (V_U, the App. A U-filter), inserted active
-                a = 1;
-                const int sv = (int)((long long)o - n_tree);
+                a[j] = 1;
+                const int sv = (int)((long long)o[j] - n_tree);
                 T.csurv[sv] = 1;
                 atomicAdd(&T.tile_count[sv / kTile], 1);
                 if (grouped(P.n_tgroups)) atomicAdd(tgroup_at(T, P, (int)(st - T.st), sv / kTile / kGroup), 1);
             } else {
-                owned = true;
-                // status, count and the first ancestor list in one round trip
-                uint8_t s = T.status[o];
-                const int ic0 = T.icount[o];
-                int4 A = T.anc[2 * (size_t)o], B = T.anc[2 * (size_t)o + 1];
-                if (s == kInactive) {  // Alg. 3: a dormant node counts up and wakes past I_max
-                    const int ic = ic0 + 1;
-                    T.icount[o] = (uint8_t)ic;
-                    if (ic > P.i_max) {
-                        s = kActive;
-                        T.status[o] = kActive;
-                    }
-                } else if (s == kActive && ic0 <= P.i_max) {
-                    // Alg. 3: any ancestor beaten in its region (or below
-                    // one); eight ancestors per step from the stored lists, the
-                    // next list fetched together with this step's flags
-                    bool beaten = false;
-                    while (true) {
-                        const int ids[8] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w};
-                        uint8_t d[8];
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) d[j] = ids[j] >= 0 ? T.dead[ids[j]] : 0;
-                        const int nq = ids[7];
-                        int4 NA = make_int4(-1, -1, -1, -1), NB = NA;
-                        if (nq >= 0) {
-                            NA = T.anc[2 * (size_t)nq];
-                            NB = T.anc[2 * (size_t)nq + 1];
-                        }
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) beaten |= d[j] != 0;
-                        if (beaten || nq < 0) break;
-                        A = NA;
-                        B = NB;
-                    }
-                    if (beaten) {
-                        s = kInactive;
-                        T.status[o] = kInactive;
-                        T.dead[o] = 1;
-                    }
-                }  // Alg. 3: a woken region-best node is left alone
-                a = s == kActive;
+                owned[j] = true;
+                s[j] = T.status[o[j]];
+                ic0[j] = T.icount[o[j]];
+                A[j] = T.anc[2 * (size_t)o[j]];
+                B[j] = T.anc[2 * (size_t)o[j] + 1];
             }
         }
-        if (c < P.n_cells) T.act[c] = a;
-        const int hi = __popcll(__ballot(a && c >= cur)), lo = __popcll(__ballot(a && c < cur));
-        const int ow = __popcll(__ballot(owned));
-        if ((threadIdx.x & 63) == 0) {
-            s_w[threadIdx.x >> 6] = hi;
-            s_w2[threadIdx.x >> 6] = lo;
-            s_w3[threadIdx.x >> 6] = ow;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int th = 0, tl = 0, to = 0;
+    }
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) {
-                th += s_w[w];
-                tl += s_w2[w];
-                to += s_w3[w];
+    for (int j = 0; j < RPT; ++j) {
+        if (!owned[j]) continue;
+        uint8_t sj = s[j];
+        if (sj == kInactive) {  // Alg. 3: a dormant node counts up and wakes past I_max
+            const int ic = ic0[j] + 1;
+            T.icount[o[j]] = (uint8_t)ic;
+            if (ic > P.i_max) {
+                sj = kActive;
+                T.status[o[j]] = kActive;
             }
-            T.bcount[blk] = make_int2(th, tl);
-            if (to) atomicAdd(&st->n_live_acc, to);
-            if (grouped(P.n_bgroups)) {
-                int2* g = bgroup_at(T, P, (int)(st - T.st), blk / kGroup);
-                if (th) atomicAdd(&g->x, th);
-                if (tl) atomicAdd(&g->y, tl);
+        } else if (sj == kActive && ic0[j] <= P.i_max) {
+            // Alg. 3: any ancestor beaten in its region (or below one); eight
+            // ancestors per step from the stored lists, the next list fetched
+            // together with this step's flags
+            int4 Aj = A[j], Bj = B[j];
+            bool beaten = false;
+            while (true) {
+                const int ids[8] = {Aj.x, Aj.y, Aj.z, Aj.w, Bj.x, Bj.y, Bj.z, Bj.w};
+                uint8_t d[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) d[q] = ids[q] >= 0 ? T.dead[ids[q]] : 0;
+                const int nq = ids[7];
+                int4 NA = make_int4(-1, -1, -1, -1), NB = NA;
+                if (nq >= 0) {
+                    NA = T.anc[2 * (size_t)nq];
+                    NB = T.anc[2 * (size_t)nq + 1];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) beaten |= d[q] != 0;
+                if (beaten || nq < 0) break;
+                Aj = NA;
+                Bj = NB;
             }
+            if (beaten) {
+                sj = kInactive;
+                T.status[o[j]] = kInactive;
+                T.dead[o[j]] = 1;
+            }
+        }  // Alg. 3: a woken region-best node is left alone
+        a[j] = sj == kActive;
+    }
+    int hi = 0, lo = 0, ow = 0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int c = base + j * kBlock;
+        if (c < P.n_cells) T.act[c] = a[j];
+        hi += __popcll(__ballot(a[j] && c >= cur));
+        lo += __popcll(__ballot(a[j] && c < cur));
+        ow += __popcll(__ballot(owned[j]));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_w[threadIdx.x >> 6] = hi;
+        s_w2[threadIdx.x >> 6] = lo;
+        s_w3[threadIdx.x >> 6] = ow;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int th = 0, tl = 0, to = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            th += s_w[w];
+            tl += s_w2[w];
+            to += s_w3[w];
         }
-        return;
+        T.bcount[blk] = make_int2(th, tl);
+        if (to) atomicAdd(&st->n_live_acc, to);
+        if (grouped(P.n_bgroups)) {
+            int2* g = bgroup_at(T, P, (int)(st - T.st), blk / kGroup);
+            if (th) atomicAdd(&g->x, th);
+            if (tl) atomicAdd(&g->y, tl);
+        }
     }
 }
 
+template <int RPT>
 __global__ __launch_bounds__(kBlock) void k_prune_flags(DevProblem P, DevPtrs T, DevState* st,
                                                         int n_prune_blocks)
 {
-    prune_flags_body(P, T, st, blockIdx.x, n_prune_blocks);
+    prune_flags_body<RPT>(P, T, st, blockIdx.x, n_prune_blocks);
 }
 
 // Exclusive scan of two ints per thread over the block, with the totals.
@@ -1151,25 +1183,32 @@ __global__ __launch_bounds__(kPolishBlock) void k_polish(DevProblem P, DevPtrs T
 }
 
 // Closes the iteration and selects the next iteration's nodes with one block
-// per kBlock regions (the prune kernel's blocks, whose counts of active
-// regions on either side of the cursor give each block the ranks of its own
-// regions; ballots rank them within the block), the block offsets by the
-// two-level scan.  It reads this iteration's state and writes the next one,
+// per region block of RPT x kBlock regions (the prune kernel's blocks, whose
+// counts of active regions on either side of the cursor give each block the
+// ranks of its own regions; ballots rank them within the block, slice by
+// slice), the block offsets by the two-level scan.  It reads this iteration's state and writes the next one,
 // so no block sees another's update; block 0 writes everything but the cursor
 // past the last selected region, which the thread holding that rank writes.
 // The group sums of the other parity, which the next iteration's prune adds
 // to, are cleared here.
+template <int RPT>
 __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const DevPtrs& T, const DevState* st,
                                                      DevState* st_next, int blk, int nb)
 {
     constexpr int NW = kBlock / 64;
-    __shared__ int s_r[6][NW];
-    const int b = blk, c = b * kBlock + threadIdx.x;
+    __shared__ int s_r[4][NW];
+    __shared__ int s_c[2][RPT][NW];  // per slice and wave: active regions at / after the cursor, before it
+    const int b = blk, base = b * kBlock * RPT + (int)threadIdx.x;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    // every load first: this thread's region and owner, the block counts, the state
-    const int cc = min(c, P.n_cells - 1);
-    const uint8_t act = T.act[cc];
-    const uint32_t own = reinterpret_cast<const uint32_t*>(T.tbl)[2 * (size_t)cc];
+    // every load first: this thread's regions and owners, the block counts, the state
+    uint8_t act[RPT];
+    uint32_t own[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int cc = min(base + j * kBlock, P.n_cells - 1);
+        act[j] = T.act[cc];
+        own[j] = reinterpret_cast<const uint32_t*>(T.tbl)[2 * (size_t)cc];
+    }
     // the block counts summed here: every block's (for the totals too) in one
     // level, or those of this block's group before it when grouped
     const bool grp = grouped(P.n_bgroups);
@@ -1219,39 +1258,65 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
     if (grouped(P.n_tgroups))
         for (int j = b * kBlock + (int)threadIdx.x; j < P.n_tgroups; j += nb * kBlock)
             *tgroup_at(T, P, par ^ 1, j) = 0;
-    const bool a = c < P.n_cells && act != 0;
-    const bool h = c >= cur;
-    const unsigned long long mh = __ballot(a && h), ml = __ballot(a && !h);
+    bool a[RPT], h[RPT];
+    unsigned long long mh[RPT], ml[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int c = base + j * kBlock;
+        a[j] = c < P.n_cells && act[j] != 0;
+        h[j] = c >= cur;
+        mh[j] = __ballot(a[j] && h[j]);
+        ml[j] = __ballot(a[j] && !h[j]);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) s_r[k][wid] = v[k];
-        s_r[4][wid] = __popcll(mh);
-        s_r[5][wid] = __popcll(ml);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            s_c[0][j][wid] = __popcll(mh[j]);
+            s_c[1][j][wid] = __popcll(ml[j]);
+        }
     }
     __syncthreads();
-    int HB = 0, LB = 0, HT = 0, LT = 0, wh = 0, wl = 0;
+    int HB = 0, LB = 0, HT = 0, LT = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         HB += s_r[0][w];
         LB += s_r[1][w];
         HT += s_r[2][w];
         LT += s_r[3][w];
-        wh += w < wid ? s_r[4][w] : 0;
-        wl += w < wid ? s_r[5][w] : 0;
     }
     const bool finalize = !was_full;
     const int n_surv = finalize && n_sel > 0 ? n_surv0 : 0;
     const bool full = was_full || n_tree + n_surv + P.surv_max > P.cap;
     const int nsel = full ? 0 : min(HT + LT, P.n_select);
-    if (a) {
-        const unsigned long long below = __lanemask_lt();
-        const int rank = h ? HB + wh + __popcll(mh & below) : HT + LB + wl + __popcll(ml & below);
-        if (rank < nsel) {
-            T.sel[rank] = (int)own;
-            if (rank == nsel - 1) st_next->cursor_next = (c + 1 == P.n_cells) ? 0 : c + 1;
+    // ranks in region order: the block's earlier slices, then this slice's
+    // earlier waves, then the lanes before this one
+    int sh = 0, sl = 0;  // active regions of the block's slices before slice j
+    const unsigned long long below = __lanemask_lt();
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        int wh = 0, wl = 0, th = 0, tl = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            wh += w < wid ? s_c[0][j][w] : 0;
+            wl += w < wid ? s_c[1][j][w] : 0;
+            th += s_c[0][j][w];
+            tl += s_c[1][j][w];
         }
+        if (a[j]) {
+            const int c = base + j * kBlock;
+            const int rank = h[j] ? HB + sh + wh + __popcll(mh[j] & below)
+                                  : HT + LB + sl + wl + __popcll(ml[j] & below);
+            if (rank < nsel) {
+                T.sel[rank] = (int)own[j];
+                if (rank == nsel - 1) st_next->cursor_next = (c + 1 == P.n_cells) ? 0 : c + 1;
+            }
+        }
+        sh += th;
+        sl += tl;
     }
     if (b == 0 && threadIdx.x == 0) {
         DevState* o = st_next;
@@ -1304,10 +1369,11 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
     }
 }
 
+template <int RPT>
 __global__ __launch_bounds__(kBlock) void k_finalize_select(DevProblem P, DevPtrs T, const DevState* st,
                                                             DevState* st_next, int nb)
 {
-    finalize_select_body(P, T, st, st_next, blockIdx.x, nb);
+    finalize_select_body<RPT>(P, T, st, st_next, blockIdx.x, nb);
 }
 
 // ------------------------------------------------------------------ batches of queries
@@ -1390,7 +1456,7 @@ __global__ __launch_bounds__(kBlock) void kb_prune_flags(const DevProblem* __res
 {
     const int4 m = map[blockIdx.x];
     const DevPtrs T = global_ptrs(Ts[m.x]);
-    prune_flags_body(Ps[m.x], T, T.st + par, m.y, m.w);
+    prune_flags_body<kRptBatch>(Ps[m.x], T, T.st + par, m.y, m.w);
 }
 
 template <int DYN>
@@ -1408,7 +1474,7 @@ __global__ __launch_bounds__(kBlock) void kb_finalize_select(const DevProblem* _
 {
     const int4 m = map[blockIdx.x];
     const DevPtrs T = global_ptrs(Ts[m.x]);
-    finalize_select_body(Ps[m.x], T, T.st + par, T.st + (par ^ 1), m.y, m.w);
+    finalize_select_body<kRptBatch>(Ps[m.x], T, T.st + par, T.st + (par ^ 1), m.y, m.w);
 }
 
 // ------------------------------------------------------------------ solution path
@@ -1464,6 +1530,12 @@ int dims_of(int dyn, int* d, int* m)
 }
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// region blocks of rpt x kBlock regions covering n regions
+int region_blocks(long long n, int rpt)
+{
+    return (int)((n + (long long)kBlock * rpt - 1) / ((long long)kBlock * rpt));
+}
 
 struct Sizes {
     int d, m;
@@ -1862,7 +1934,8 @@ struct kpx_handle {
     std::vector<Timed> timed;                 // one per timed launch
     std::vector<hipEvent_t> spare;
     int full_cached = 0;
-    int n_prune_blocks = 0;
+    int n_prune_blocks = 0;                   // region blocks of rpt x kBlock regions
+    int rpt = 1;                              // regions per thread of prune and the close
     int cur = 0;                              // which device state is current
     int refined = 1;                          // total refinement factor per axis so far
     int polish_steps = 0;                     // edge polish of inserted nodes (0: off)
@@ -2318,7 +2391,8 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
         h->owns = true;
     }
     carve(h);
-    h->n_prune_blocks = (z.n_cells + kBlock - 1) / kBlock;
+    h->rpt = (long long)z.n_cells_cap >= kRptRegions ? kRptBatch : 1;
+    h->n_prune_blocks = region_blocks(z.n_cells, h->rpt);
 
     // boxes grown by the margin (two float4 each), the box grid, x_init
     std::vector<float> boxes((size_t)8 * (z.n_boxes > 0 ? z.n_boxes : 1), 0.f);
@@ -2381,8 +2455,12 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
         int rc;
         if ((rc = timed_launch(h, 0, [&] { propagate(h, T); })) != KPX_OK) return rc;
         if ((rc = timed_launch(h, 1, [&] {
-                 k_prune_flags<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
-                     h->P, T, cur_state(h), h->n_prune_blocks);
+                 if (h->rpt == 1)
+                     k_prune_flags<1><<<h->n_prune_blocks, kBlock, 0, h->stream>>>(h->P, T, cur_state(h),
+                                                                                   h->n_prune_blocks);
+                 else
+                     k_prune_flags<kRptBatch><<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
+                         h->P, T, cur_state(h), h->n_prune_blocks);
              })) != KPX_OK)
             return rc;
         if ((rc = timed_launch(h, 2, [&] { insert(h, T); })) != KPX_OK) return rc;
@@ -2399,8 +2477,12 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
                                                                         h->polish_goal_only);
         }
         if ((rc = timed_launch(h, 3, [&] {
-                 k_finalize_select<<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
-                     h->P, T, cur_state(h), next_state(h), h->n_prune_blocks);
+                 if (h->rpt == 1)
+                     k_finalize_select<1><<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
+                         h->P, T, cur_state(h), next_state(h), h->n_prune_blocks);
+                 else
+                     k_finalize_select<kRptBatch><<<h->n_prune_blocks, kBlock, 0, h->stream>>>(
+                         h->P, T, cur_state(h), next_state(h), h->n_prune_blocks);
              })) != KPX_OK)
             return rc;
         h->cur ^= 1;  // the state the close of this iteration wrote is current
@@ -2632,7 +2714,7 @@ int kpx_refine(kpx_handle* h, int32_t factor)
     h->z.n_cells = (int)nc;
     h->P.n_cells = (int)nc;
     h->P.surv_max = (int)std::min<long long>(nc, h->z.s_max);
-    h->n_prune_blocks = (int)((nc + kBlock - 1) / kBlock);
+    h->n_prune_blocks = region_blocks(nc, h->rpt);
     const DevPtrs T = kernel_ptrs(h);
     k_fill_table<<<std::min(1024, (h->z.n_act + kBlock - 1) / kBlock), kBlock, 0, h->stream>>>(
         T.tbl, T.act, h->z.n_cells, h->z.n_act);
@@ -2925,9 +3007,9 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
         const int np = std::max(1, std::min(h->P.n_cu, (h->z.s_max + 2 * kPropBlock - 1) / (2 * kPropBlock)));
         for (int k = 0; k < np; ++k) prop[gi].push_back(make_int4(q, k, np, h->n_prune_blocks));
         for (int k = 0; k < h->z.n_tiles; ++k) ins[gi].push_back(make_int4(q, k, h->z.n_tiles, h->n_prune_blocks));
-        const int npf = h->n_prune_blocks;
-        for (int k = 0; k < npf; ++k) prune.push_back(make_int4(q, k, npf, h->n_prune_blocks));
-        for (int k = 0; k < h->n_prune_blocks; ++k) fin.push_back(make_int4(q, k, h->n_prune_blocks, h->n_prune_blocks));
+        const int nrb = region_blocks(h->z.n_cells, kRptBatch);  // the batch's region blocks of this query
+        for (int k = 0; k < nrb; ++k) prune.push_back(make_int4(q, k, nrb, nrb));
+        for (int k = 0; k < nrb; ++k) fin.push_back(make_int4(q, k, nrb, nrb));
     }
     for (auto& g : b->groups) {
         const int rc = allow_lds(propagate_kernel(g.dyn, g.cost, true), g.lds, lds_max);
