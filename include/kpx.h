@@ -300,7 +300,9 @@ int kpx_set_timing_every(kpx_handle* h, int32_t period);
 
 /* Waits and returns, per kernel (0 propagate, 1 prune + survivor flags,
  * 2 insert, 3 close of the iteration + next selection), the summed
- * milliseconds and the number of launches timed since timing was enabled. */
+ * milliseconds and the number of launches timed since timing was enabled.
+ * Only iterations that ran count: those enqueued after the tree filled
+ * return at once and their launches are left out. */
 int kpx_read_timing(kpx_handle* h, double ms[4], int64_t launches[4]);
 
 /* Number of per-iteration records kept (a ring indexed by iteration). */

@@ -53,6 +53,11 @@ constexpr int kBoxGridBytes = 48 * 1024;  // LDS budget of the box grid, its cle
 constexpr int kChunkMax = 1024;           // expansion slots per propagate chunk (at most)
 constexpr int kChunkMin = 64;
 constexpr int kParMax = 256;              // parent states staged per chunk (at most)
+// from this many samples per node, propagate first keeps, per block and
+// region, only the chunk's lowest key for the region table (few parents
+// then send many edges to the same regions)
+constexpr int kDedupK = 64;
+static_assert(kChunkMax == 1024, "the dedupe table hashes regions to 10 bits");
 constexpr int kPropBlock = 256;           // propagate: one wave per SIMD, one block per CU
 constexpr int kPropBlockWide = 512;       // ... or two, for cheap models at large sizes
 constexpr int kStatsCap = 1 << 16;
@@ -602,16 +607,26 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         }
         __syncthreads();
 
-        // 3. region map, cost, region minimum, candidate records.  Every
-        // atomic of a thread is issued before the first of their results is
-        // looked at, so that their round trips overlap.
+        // 3. region map, cost, region minimum, candidate records.  A valid
+        // slot first reads its region's entry and takes the atomic minimum
+        // only when its key is below the value read: the entry only falls
+        // while propagate runs, so a key at or above it can neither become
+        // the minimum nor beat the region's node.  Regions that many edges
+        // reach at once (the root's neighbours when the root alone shares a
+        // large buffer) then see few atomics instead of one per edge.  A
+        // thread issues all its loads, then all its atomics, before it looks
+        // at their results, so that the round trips overlap.
         unsigned long long keys[PT], olds[PT];
+        int cells[PT];
+        bool beaten[PT];  // a lower key of this chunk reaches the same region
 #pragma unroll
         for (int r = 0; r < PT; ++r) {
             if (r >= nr) break;  // block-uniform
             const int lj = threadIdx.x + r * NT;
             keys[r] = kEmpty;
             olds[r] = kEmpty;
+            cells[r] = 0;
+            beaten[r] = false;
             if (lj >= cnt) continue;
             const int s = base + lj;
             const int fi = s_fi[lj];
@@ -638,7 +653,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                 const unsigned long long key =
                     ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)(n_tree + s);
                 keys[r] = key;
-                olds[r] = atomicMin(&T.tbl[c], key);
+                cells[r] = c;
                 T.ckey[s] = key;
                 T.ccell[s] = c;
                 T.cflag[s] = (uint8_t)(1 | (in_goal(P, pe) ? 2 : 0));
@@ -658,11 +673,55 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                 T.d_fi[s] = fi;
             }
         }
+        if (K >= kDedupK) {  // block-uniform
+            // The chunk's lowest key per region, in an LDS table of kChunkMax
+            // buckets (region in the freed sort order, key in the freed
+            // controls).  A slot whose region lost its bucket to another
+            // region goes to the region table as it is.  A slot beaten by a
+            // lower key of the chunk in its region can neither be the
+            // region's minimum nor the first to beat the region's node.
+            uint32_t* s_hcell = s_order;
+            unsigned long long* s_hkey = reinterpret_cast<unsigned long long*>(s_u);
+            __syncthreads();  // every read of s_u above is done
+            for (int i = threadIdx.x; i < kChunkMax; i += NT) {
+                s_hcell[i] = 0xFFFFFFFFu;
+                s_hkey[i] = kEmpty;
+            }
+            __syncthreads();
+            int hb[PT];
+#pragma unroll
+            for (int r = 0; r < PT; ++r) {
+                hb[r] = -1;
+                if (r >= nr || keys[r] == kEmpty) continue;
+                const uint32_t c = (uint32_t)cells[r];
+                const int h = (int)((c * 2654435761u) >> 22);  // 10 bits: kChunkMax buckets
+                const uint32_t prev = atomicCAS(&s_hcell[h], 0xFFFFFFFFu, c);
+                if (prev == 0xFFFFFFFFu || prev == c) {
+                    atomicMin(&s_hkey[h], keys[r]);
+                    hb[r] = h;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < PT; ++r)
+                if (hb[r] >= 0 && s_hkey[hb[r]] != keys[r]) beaten[r] = true;
+        }
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            if (r >= nr) break;
+            if (keys[r] != kEmpty && !beaten[r])
+                olds[r] = __hip_atomic_load(&T.tbl[cells[r]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            if (r >= nr) break;
+            if (!beaten[r] && keys[r] < olds[r]) olds[r] = atomicMin(&T.tbl[cells[r]], keys[r]);
+        }
 #pragma unroll
         for (int r = 0; r < PT; ++r) {
             if (r >= nr) break;
             const unsigned long long key = keys[r], old = olds[r];
-            if (key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
+            if (!beaten[r] && key < old && old != kEmpty && (long long)(uint32_t)old < n_tree) {
                 // this lane took the region from a tree node: it is beaten (V_T)
                 const uint32_t o = (uint32_t)old;
                 T.status[o] = kTerminal;
@@ -1927,8 +1986,10 @@ struct kpx_handle {
     int timing_mask = 0;                      // bit k: kernel k is timed
     int timing_every = 1;                     // ... in every timing_every-th iteration
     long long timing_iter = 0;                // iterations since timing was set
+    long long enq_iter = 0;                   // iterations enqueued since creation
     struct Timed {
         int kernel;
+        long long iter;                       // the launch's iteration (enq_iter)
         hipEvent_t begin, end;
     };
     std::vector<Timed> timed;                 // one per timed launch
@@ -2150,7 +2211,7 @@ int timed_launch(kpx_handle* h, int k, F&& launch)
     KPX_HIP(h, hipEventRecord(a, h->stream));
     launch();
     KPX_HIP(h, hipEventRecord(b, h->stream));
-    h->timed.push_back({k, a, b});
+    h->timed.push_back({k, h->enq_iter, a, b});
     return KPX_OK;
 }
 
@@ -2487,6 +2548,7 @@ int kpx_iterate(kpx_handle* h, int32_t n_iters)
             return rc;
         h->cur ^= 1;  // the state the close of this iteration wrote is current
         ++h->timing_iter;
+        ++h->enq_iter;
     }
     KPX_HIP(h, hipGetLastError());
     return KPX_OK;
@@ -2809,12 +2871,16 @@ int kpx_set_timing_every(kpx_handle* h, int32_t period)
 int kpx_read_timing(kpx_handle* h, double ms[4], int64_t launches[4])
 {
     if (!h || !ms || !launches) return KPX_ERR_ARG;
-    KPX_HIP(h, hipStreamSynchronize(h->stream));
+    // waits; iterations enqueued after the tree filled did not run
+    kpx_counters c;
+    const int rc = kpx_counters_read(h, &c);
+    if (rc != KPX_OK) return rc;
     for (int k = 0; k < 4; ++k) {
         ms[k] = 0.0;
         launches[k] = 0;
     }
     for (const auto& e : h->timed) {
+        if (e.iter >= c.iteration) continue;
         float t = 0.f;
         KPX_HIP(h, hipEventElapsedTime(&t, e.begin, e.end));
         ms[e.kernel] += t;
@@ -3138,7 +3204,10 @@ int kpx_batch_iterate(kpx_batch* b, int32_t n_iters)
     for (; i < n_iters; ++i) batch_enqueue(b, b->cur ^ (i & 1));
     // parity after n_iters iterations
     if (n_iters & 1) b->cur ^= 1;
-    for (kpx_handle* h : b->hs) h->cur = b->cur;
+    for (kpx_handle* h : b->hs) {
+        h->cur = b->cur;
+        h->enq_iter += n_iters;
+    }
     if (hipGetLastError() != hipSuccess) return bfail(b, KPX_ERR_DEVICE, "a batched launch failed");
     if (hipEventRecord(b->ev_out, b->stream) != hipSuccess || hipStreamWaitEvent(b->user, b->ev_out, 0) != hipSuccess)
         return bfail(b, KPX_ERR_DEVICE, "stream ordering failed");

@@ -146,6 +146,21 @@ def test_stats_ring_and_timing(kpx):
     pl.close()
 
 
+def test_timing_leaves_out_iterations_after_the_tree_filled(kpx):
+    """Iterations enqueued after the tree filled return at once: their
+    launches are not counted, so launches match the iterations that ran."""
+    w = W.make_workload("di6_paper", 0)  # 10^5 slots into a 10^5-node tree: full within ~25 iterations
+    pl = _planner(kpx, w)
+    pl.set_timing(True, every=3)
+    pl.iterate(60)
+    ms, launches = pl.read_timing()
+    c = pl.counters()
+    assert c["full"] and 0 < int(c["iteration"]) < 60, c
+    ran = len(range(0, int(c["iteration"]), 3))
+    assert launches == [ran] * 4 and all(t > 0 for t in ms), (launches, c["iteration"])
+    pl.close()
+
+
 # the uncapped form (samples_per_node = 0): all active nodes share the buffer
 UNCAPPED = {
     "di6": (dict(n_select=900, samples=0, tree_cap=1 << 15), 25),
