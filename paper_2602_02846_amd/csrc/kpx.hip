@@ -57,8 +57,10 @@ constexpr int kParMax = 256;              // parent states staged per chunk (at 
 // region, only the chunk's lowest key for the region table (few parents
 // then send many edges to the same regions)
 constexpr int kDedupK = 64;
-// idle lanes of a propagate wave take new slots together, this many at a time
+// idle lanes of a propagate wave take new slots together, this many at a
+// time; with two waves per SIMD the other wave hides part of a refill
 constexpr int kRefillBatch = 16;
+constexpr int kRefillBatchWide = 8;
 static_assert(kChunkMax == 1024, "the dedupe table hashes regions to 10 bits");
 constexpr int kPropBlock = 256;           // propagate: one wave per SIMD, one block per CU
 constexpr int kPropBlockWide = 512;       // ... or two, for cheap models at large sizes
@@ -497,12 +499,14 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         bool exhausted = wid >= cnt;  // wave-uniform: no place left for this wave
         while (true) {
             // idle lanes refill together, once a quarter of the wave waits
-            // (or no lane integrates): a refill's LDS round trips then cost
-            // the wave a few trips instead of one per finished edge, and the
-            // longest edges, which set the block's time, do not wait for them
+            // (an eighth in 512-thread blocks) or no lane integrates: a
+            // refill's LDS round trips then cost the wave a few trips instead
+            // of one per finished edge, and the longest edges, which set the
+            // block's time, do not wait for them
+            constexpr int kBatch = NT == kPropBlock ? kRefillBatch : kRefillBatchWide;
             const bool want = li < 0 && !exhausted;
             const unsigned long long m = __ballot(want);
-            if (m && (__popcll(m) >= kRefillBatch || !__any(li >= 0))) {
+            if (m && (__popcll(m) >= kBatch || !__any(li >= 0))) {
                 const int qi = wtaken + __popcll(m & __lanemask_lt());
                 wtaken += __popcll(m);
                 if (wtaken * NW + wid >= cnt) exhausted = true;
