@@ -69,8 +69,9 @@ def kernel_bytes(prob, prm, st):
     implementation happens to move):
       prune_flags  every region: table key 8 + activity byte 1; every region a
                    tree node still owns: status and I_count read and written 4;
-                   every slot: flag 1 + survivor byte 1; every valid slot: its
-                   key 8, region 4 and the region's table entry 8
+                   every survivor (named by its region's key): survivor byte 1,
+                   and its tile's count 4 per tile holding one (the ancestor
+                   checks of Alg. 3 are left out: a lower bound)
       insert       every slot: survivor byte 1; per 256-slot tile: count 4;
                    every survivor: end state 4d, key 8, region 4, parent 4
                    read; state 4d, control 4m, steps 2, parent 4, cost 4,
@@ -80,11 +81,10 @@ def kernel_bytes(prob, prm, st):
     d, m = DIMS[prob.dynamics]
     cells = float(prm.n_cells)
     S = st["n_select"].astype(np.float64) * st["samples_per_node"]
-    nv = st["n_valid"].astype(np.float64)
     ns = st["n_survivors"].astype(np.float64)
     nl = st["n_live"].astype(np.float64)
     nsel_next = np.append(st["n_select"][1:], st["n_select"][-1:]).astype(np.float64)
-    prune = cells * 9 + nl * 4 + S * 2 + nv * 20
+    prune = cells * 9 + nl * 4 + ns + np.minimum(ns, np.ceil(S / 256)) * 4
     insert = S + np.ceil(S / 256) * 4 + ns * (4 * d + 16 + 4 * d + 4 * m + 28)
     final = cells * 5 + nsel_next * 4
     return {"prune_flags": prune, "insert": insert, "finalize_select": final}
