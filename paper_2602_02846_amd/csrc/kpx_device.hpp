@@ -293,22 +293,21 @@ __device__ __forceinline__ void rk4(const Hot<DYN>& P, float* x, const float* u,
 }
 
 // Workspace and state bounds (closed).  Each two-sided bound is an affine map
-// onto [-1, 1]; the squares of the mapped values are compared as unsigned
-// integers (order-preserving for non-negative floats), so one three-way
-// integer max folds two components and a NaN (bits above those of 1.0)
-// fails.  Components with one finite bound (rare) are compared directly.
+// onto [-1, 1], and the largest magnitude of the mapped values must not
+// exceed 1.  The IEEE maximum propagates a NaN (which then fails the test),
+// and gfx950 folds three magnitudes into one instruction (absolute values are
+// operand modifiers).  Components with one finite bound (rare) are compared
+// directly.
 template <int DYN>
 __device__ __forceinline__ bool in_bounds(const Hot<DYN>& H, const float* x, const float* os_lo,
                                           const float* os_hi)
 {
     constexpr int D = Dims<DYN>::D;
-    uint32_t m = 0;
+    float m = __builtin_fabsf(__builtin_fmaf(x[0], H.bs[0], H.bo[0]));
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        const float t = __builtin_fmaf(x[i], H.bs[i], H.bo[i]);
-        m = max(m, __float_as_uint(t * t));
-    }
-    bool ok = m <= 0x3F800000u;
+    for (int i = 1; i < D; ++i)
+        m = __builtin_elementwise_maximum(m, __builtin_fabsf(__builtin_fmaf(x[i], H.bs[i], H.bo[i])));
+    bool ok = m <= 1.f;
     if (H.os_mask) {  // uniform
 #pragma unroll
         for (int i = 0; i < D; ++i)

@@ -180,6 +180,36 @@ def test_lockstep_uncapped_form(kpx, ora, case):
     pl.close()
 
 
+@pytest.mark.parametrize("case,kw", [
+    # uncapped: a buffer of 64 slots per region (12^3 regions) keeps every
+    # node's share at 64 or more
+    ("di6", dict(n_select=64 * 12 ** 3, samples=0, tree_cap=1 << 18, grid=(12, 12, 12))),
+    # capped, 64 samples per node
+    ("quad12", dict(n_select=300, samples=64, tree_cap=1 << 17, grid=(8, 8, 8))),
+])
+def test_lockstep_region_minimum_reduced_per_chunk(kpx, ora, case, kw):
+    """From 64 samples per node propagate first keeps each chunk's lowest key
+    per region (an LDS table) before the region table's atomic minimum: every
+    iteration here runs that path, with tree nodes beaten by arrivals, and the
+    oracle replays each one."""
+    w = W.make_workload(case, 3, **kw)
+    P = ora.Problem(w.problem, w.params)
+    pl = _planner(kpx, w)
+    pl.set_dump(True)
+    rep = parity.new_report()
+    rep["polished"] = 0
+    for _ in range(10):
+        pre = pl.snapshot()
+        pl.iterate(1)
+        parity.check_iteration(ora, P, pl, pre, rep)
+        assert int(pl.counters()["samples_per_node"]) >= 64
+    print(case, rep)
+    assert rep["iterations"] == 10 and rep["valid"] > 0
+    st = pl.snapshot()["status"]
+    assert int((st == kpx.TERMINAL).sum()) > 0  # nodes were beaten or pruned
+    pl.close()
+
+
 def test_lockstep_long_one_level_scans(kpx, ora):
     """More than 1024 tiles (300,000 slots) and more than 1024 region blocks
     (70^3 = 343,000 regions), summed in one level: each block's offset runs
