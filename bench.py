@@ -49,7 +49,7 @@ FLOPS_PER_SUBSTEP = {
     ("DUBINS6", "TIME"): 110, ("DUBINS6", "PATH_LENGTH"): 110 + 13,
 }
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (256 CUs x 2.4 GHz x 256 FLOP/clk, packed)
-PEAK_FP32_UNPACKED = 78.6     # ... without packed FP32 (this build issues none)
+PEAK_FP32_UNPACKED = 78.6     # ... without packed FP32 (the kernels are compiled without it)
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2602_02846_amd/csrc/kpx.hip", "paper_2602_02846_amd/csrc/kpx_device.hpp")
 KERNELS = ("propagate", "prune_flags", "insert", "finalize_select")
@@ -211,7 +211,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {a.gpus} is not supported "
-              "(a planner query runs on a single device; this build uses no second GPU)", file=sys.stderr)
+              "(a planner query runs on a single device)", file=sys.stderr)
         sys.exit(2)
     import torch
 
