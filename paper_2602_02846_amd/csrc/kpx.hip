@@ -2257,20 +2257,21 @@ struct kpx_batch {
         size_t lds = 0;
         int4* ins = nullptr;
         int n_ins = 0;
+        int4* prune = nullptr;      // prune and the close, over the group's queries
+        int n_prune = 0;
+        int4* fin = nullptr;
+        int n_fin = 0;
     };
     std::vector<Group> groups;
-    int4* prune = nullptr;
-    int n_prune = 0;
-    int4* fin = nullptr;
-    int n_fin = 0;
     int cur = 0;
     bool graph_on = false;
     hipGraphExec_t exec[2] = {nullptr, nullptr};  // two iterations from state parity 0 / 1
     std::vector<int> cells;         // each handle's region count when the batch was made
     std::vector<char> dump;         // ... and whether it recorded its expansions (fixed since)
-    // groups after the first run their propagate and insert on side streams
-    // forked from and joined back to the batch stream, so that the models'
-    // kernels overlap (each is bound by its longest edge, not by the machine)
+    // groups after the first run their iterations on side streams forked from
+    // and joined back to the batch stream, so that the models' kernels overlap
+    // (each propagate is bound by its longest edge, not by the machine, and
+    // one group's prune and close run while another still propagates)
     std::vector<hipStream_t> side;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
@@ -2314,11 +2315,12 @@ void batch_join(const kpx_batch* b)
     }
 }
 
-// Enqueues one iteration of every query, at state parity par: the groups'
-// propagate and insert kernels run side by side, prune and select once.
+// Enqueues one iteration of every query, at state parity par: each group's
+// four kernels in order on the group's stream (between a batch_fork and a
+// batch_join); the groups' queries are independent, so nothing orders one
+// group after another.
 void batch_enqueue(const kpx_batch* b, int par)
 {
-    batch_fork(b);
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const auto& g = b->groups[gi];
         const hipStream_t s = group_stream(b, gi);
@@ -2330,21 +2332,14 @@ void batch_enqueue(const kpx_batch* b, int par)
         case 4: kb_propagate_launch<kDUBINS6, kTIME>(b, g, par, s); break;
         default: kb_propagate_launch<kDUBINS6, kPATH>(b, g, par, s); break;
         }
-    }
-    batch_join(b);
-    kb_prune_flags<<<b->n_prune, kBlock, 0, b->stream>>>(b->d_P, b->d_T, b->prune, par);
-    batch_fork(b);
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-        const auto& g = b->groups[gi];
-        const hipStream_t s = group_stream(b, gi);
+        kb_prune_flags<<<g.n_prune, kBlock, 0, s>>>(b->d_P, b->d_T, g.prune, par);
         switch (g.dyn) {
         case kDI6: kb_insert<kDI6><<<g.n_ins, kBlock, 0, s>>>(b->d_P, b->d_T, g.ins, par); break;
         case kQUAD12: kb_insert<kQUAD12><<<g.n_ins, kBlock, 0, s>>>(b->d_P, b->d_T, g.ins, par); break;
         default: kb_insert<kDUBINS6><<<g.n_ins, kBlock, 0, s>>>(b->d_P, b->d_T, g.ins, par); break;
         }
+        kb_finalize_select<<<g.n_fin, kBlock, 0, s>>>(b->d_P, b->d_T, g.fin, par);
     }
-    batch_join(b);
-    kb_finalize_select<<<b->n_fin, kBlock, 0, b->stream>>>(b->d_P, b->d_T, b->fin, par);
 }
 
 // Captures two iterations starting at parity p into b->exec[p].
@@ -2353,8 +2348,10 @@ int batch_capture(kpx_batch* b, int p)
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, KPX_ERR_DEVICE, "hipStreamBeginCapture failed");
+    batch_fork(b);
     batch_enqueue(b, p);
     batch_enqueue(b, p ^ 1);
+    batch_join(b);
     if (hipStreamEndCapture(b->stream, &g) != hipSuccess || !g)
         return bfail(b, KPX_ERR_DEVICE, "hipStreamEndCapture failed");
     const hipError_t e = hipGraphInstantiate(&b->exec[p], g, nullptr, nullptr, 0);
@@ -3061,8 +3058,7 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
         return KPX_ERR_DEVICE;
     }
     // block maps: (query, block, blocks of the query, region blocks of the query)
-    std::vector<int4> prune, fin;
-    std::vector<std::vector<int4>> prop, ins;
+    std::vector<std::vector<int4>> prop, ins, prune, fin;
     for (int q = 0; q < n; ++q) {
         const kpx_handle* h = handles[q];
         int gi = -1;
@@ -3075,6 +3071,8 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
             b->groups.push_back(g);
             prop.emplace_back();
             ins.emplace_back();
+            prune.emplace_back();
+            fin.emplace_back();
             gi = (int)b->groups.size() - 1;
         }
         auto& g = b->groups[gi];
@@ -3084,8 +3082,8 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
         for (int k = 0; k < np; ++k) prop[gi].push_back(make_int4(q, k, np, h->n_prune_blocks));
         for (int k = 0; k < h->z.n_tiles; ++k) ins[gi].push_back(make_int4(q, k, h->z.n_tiles, h->n_prune_blocks));
         const int nrb = region_blocks(h->z.n_cells, kRptBatch);  // the batch's region blocks of this query
-        for (int k = 0; k < nrb; ++k) prune.push_back(make_int4(q, k, nrb, nrb));
-        for (int k = 0; k < nrb; ++k) fin.push_back(make_int4(q, k, nrb, nrb));
+        for (int k = 0; k < nrb; ++k) prune[gi].push_back(make_int4(q, k, nrb, nrb));
+        for (int k = 0; k < nrb; ++k) fin[gi].push_back(make_int4(q, k, nrb, nrb));
     }
     for (auto& g : b->groups) {
         const int rc = allow_lds(propagate_kernel(g.dyn, g.cost, true), g.lds, lds_max);
@@ -3114,8 +3112,8 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
         }
         b->ev_join.push_back(e);
     }
-    size_t n4 = prune.size() + fin.size();
-    for (size_t i = 0; i < b->groups.size(); ++i) n4 += prop[i].size() + ins[i].size();
+    size_t n4 = 0;
+    for (size_t i = 0; i < b->groups.size(); ++i) n4 += prop[i].size() + ins[i].size() + prune[i].size() + fin[i].size();
     const size_t bytes = align_up(sizeof(DevProblem) * n) + align_up(sizeof(DevPtrs) * n) + sizeof(int4) * n4;
     if (hipMalloc(&b->mem, bytes) != hipSuccess) {
         b->mem = nullptr;
@@ -3139,11 +3137,11 @@ int kpx_batch_create(kpx_handle* const* handles, int32_t n, kpx_batch** out)
         count = (int)v.size();
         all.insert(all.end(), v.begin(), v.end());
     };
-    place(prune, b->prune, b->n_prune);
-    place(fin, b->fin, b->n_fin);
     for (size_t i = 0; i < b->groups.size(); ++i) {
         place(prop[i], b->groups[i].prop, b->groups[i].n_prop);
         place(ins[i], b->groups[i].ins, b->groups[i].n_ins);
+        place(prune[i], b->groups[i].prune, b->groups[i].n_prune);
+        place(fin[i], b->groups[i].fin, b->groups[i].n_fin);
     }
     if (hipMemcpy(b->d_P, hp.data(), sizeof(DevProblem) * n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->d_T, ht.data(), sizeof(DevPtrs) * n, hipMemcpyHostToDevice) != hipSuccess ||
@@ -3211,7 +3209,11 @@ int kpx_batch_iterate(kpx_batch* b, int32_t n_iters)
                 return bfail(b, KPX_ERR_DEVICE, "hipGraphLaunch failed");
         }
     }
-    for (; i < n_iters; ++i) batch_enqueue(b, b->cur ^ (i & 1));
+    if (i < n_iters) {
+        batch_fork(b);
+        for (; i < n_iters; ++i) batch_enqueue(b, b->cur ^ (i & 1));
+        batch_join(b);
+    }
     // parity after n_iters iterations
     if (n_iters & 1) b->cur ^= 1;
     for (kpx_handle* h : b->hs) {
