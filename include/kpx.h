@@ -389,9 +389,10 @@ const char* kpx_last_error(const kpx_handle* h);
 /* ---------------------------------------------------------------- batches
  * Independent queries (handles made by kpx_create, any mix of models, sizes,
  * obstacle sets and capacities) iterated together: each kernel of an
- * iteration is launched once for all the queries (once per robot model and
- * cost for propagate and insert), so that small queries share the GPU.  Every
- * query computes exactly what kpx_iterate would compute for it alone. */
+ * iteration is launched once for all the queries of one robot model and
+ * cost, each such group on a stream of its own, so that small queries share
+ * the GPU.  Every query computes exactly what kpx_iterate would compute for
+ * it alone. */
 typedef struct kpx_batch kpx_batch;
 
 /* Groups n host-array handles (not copied; the caller keeps them alive and
