@@ -229,3 +229,36 @@ def test_batch_lockstep_with_the_oracle(kpx, ora):
     assert reps[0]["full_at"] is not None and reps[0]["iterations"] < 14, reps[0]
     for p in ps:
         p.close()
+
+
+def test_batch_of_four_model_cost_groups_matches_each_alone(kpx):
+    """Four (model, cost) groups, each iterating on a stream of its own:
+    double integrators (time), quadrotors (time and path length) and Dubins
+    airplanes (path length), graph-replayed in odd runs with eager work
+    between them; every query's tree is the one it grows alone."""
+    from workloads.scenes import small_overrides
+
+    ws = []
+    for seed in range(2):
+        ws.append(W.make_workload("di6", seed, **small_overrides("di6")))
+        ws.append(W.make_workload("quad12", seed, **small_overrides("quad12")))
+        ws.append(W.make_workload("quad12", seed + 2, cost="PATH_LENGTH", **small_overrides("quad12")))
+        ws.append(W.make_workload("dubins6", seed, **small_overrides("dubins6")))
+    assert len({(w.problem.dynamics, w.problem.cost) for w in ws}) == 4
+    alone = []
+    for w in ws:
+        p = kpx.Planner(w.problem, w.params)
+        p.iterate(17)
+        alone.append(p.snapshot())
+        p.close()
+    ps = [kpx.Planner(w.problem, w.params) for w in ws]
+    b = kpx.Batch(ps, graph=True)
+    for step in (5, 4, 1, 7):
+        b.iterate(step)
+        ps[0].counters()  # eager work between the runs
+    b.sync()
+    for q, (p, a) in enumerate(zip(ps, alone)):
+        _same(p.snapshot(), a, f"query {q}")
+    b.close()
+    for p in ps:
+        p.close()
