@@ -57,6 +57,10 @@ constexpr int kParMax = 256;              // parent states staged per chunk (at 
 // region, only the chunk's lowest key for the region table (few parents
 // then send many edges to the same regions)
 constexpr int kDedupK = 64;
+// floats per candidate end-state row (slot-major: one row per slot, so that
+// a lane writes its end state, and insert reads a survivor's, as whole
+// 16-byte words)
+__host__ __device__ constexpr int cx_row(int d) { return (d + 3) & ~3; }
 // idle lanes of a propagate wave take new slots together, this many at a
 // time; with two waves per SIMD the other wave hides part of a refill
 constexpr int kRefillBatch = 16;
@@ -109,7 +113,7 @@ struct DevPtrs {
     int* sel;
     unsigned long long* ckey;
     int* ccell;
-    float* cx;           // D x s_max
+    float* cx;           // s_max rows of cx_row(D) floats: a slot's end state, padded to 16-byte words
     uint8_t* cflag;      // bit 0 valid, bit 1 goal
     uint8_t* csurv;
     int* tile_count;
@@ -607,9 +611,17 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
 #pragma unroll
                         for (int a = 0; a < 3; ++a) s_pe[a][li] = x[a];
                         s_vs[li] = (uint8_t)((x[VI] >= 0.f) | (x[VI + 1] >= 0.f) << 1 | (x[VI + 2] >= 0.f) << 2);
+                        float4* cr = reinterpret_cast<float4*>(T.cx) + (long long)(base + li) * (SD / 4);
 #pragma unroll
-                        for (int c = 0; c < D; ++c)
-                            T.cx[(long long)c * P.s_max + base + li] = x[c] * (rev_state(DYN, c) ? k2Pi : 1.f);
+                        for (int w = 0; w < SD / 4; ++w) {
+                            float v[4];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int c = 4 * w + e;
+                                v[e] = c < D ? x[c] * (rev_state(DYN, c) ? k2Pi : 1.f) : 0.f;
+                            }
+                            cr[w] = make_float4(v[0], v[1], v[2], v[3]);
+                        }
                     }
                     li = -1;
                 }
@@ -1094,9 +1106,17 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     }
     if (f) {
         const long long i = n_tree + rank;
-        float xv[D];
+        constexpr int SD = cx_row(D);
+        float xv[SD];
+        const float4* cr = reinterpret_cast<const float4*>(T.cx) + (long long)s * (SD / 4);
 #pragma unroll
-        for (int q = 0; q < D; ++q) xv[q] = T.cx[(long long)q * P.s_max + s];
+        for (int w = 0; w < SD / 4; ++w) {
+            const float4 v = cr[w];
+            xv[4 * w] = v.x;
+            xv[4 * w + 1] = v.y;
+            xv[4 * w + 2] = v.z;
+            xv[4 * w + 3] = v.w;
+        }
         const int4 pa = T.anc[2 * (size_t)par], pb = T.anc[2 * (size_t)par + 1];
         float u[M];
         int n;
@@ -1637,7 +1657,7 @@ void for_each_array(const Sizes& z, F&& f)
     f("sel", sizeof(int) * S);
     f("ckey", sizeof(unsigned long long) * S);
     f("ccell", sizeof(int) * S);
-    f("cx", sizeof(float) * z.d * S);
+    f("cx", sizeof(float) * cx_row(z.d) * S);
     f("cflag", S);
     f("csurv", S);
     f("tile_count", sizeof(int) * (size_t)z.n_tiles);
@@ -2729,14 +2749,14 @@ int kpx_read_dump(kpx_handle* h, kpx_dump_view* v, int64_t* n_slots)
                 std::memset(v->control + k * ld, 0, sizeof(float) * S);
             }
         }
-    if (v->state)
-        for (int k = 0; k < KPX_MAX_STATE; ++k) {
-            if (k < h->z.d) {
-                if ((rc = get(v->state + k * ld, h->T.cx + k * sm, sizeof(float) * S))) return rc;
-            } else {
-                std::memset(v->state + k * ld, 0, sizeof(float) * S);
-            }
-        }
+    if (v->state) {
+        // slot-major rows on the device, component-major in the view
+        const int R = cx_row(h->z.d);
+        std::vector<float> rows((size_t)R * S);
+        if ((rc = get(rows.data(), h->T.cx, sizeof(float) * rows.size()))) return rc;
+        for (int k = 0; k < KPX_MAX_STATE; ++k)
+            for (size_t q = 0; q < (size_t)S; ++q) v->state[k * ld + q] = k < h->z.d ? rows[q * R + k] : 0.f;
+    }
     std::vector<uint8_t> flag(S);
     if ((rc = get(flag.data(), h->T.cflag, S))) return rc;
     // edge polish decisions, one per inserted node
