@@ -48,6 +48,7 @@ constexpr int kGroup = 1024;             // tiles, or region blocks, per group o
 constexpr int kDirect = 8 * kGroup;      // at most this many counts are summed in one level
 constexpr int kGroupPad = 32;            // ints per group sum: one 128-byte line each
 constexpr int kSortBins = 64;             // step-count bins of the in-block sort
+static_assert(kSortBins == 64, "the sort bins' prefix is one wave's scan");
 constexpr int kBoxGridMax = 16;           // box-grid cells per workspace axis (at most)
 constexpr int kBoxGridBytes = 48 * 1024;  // LDS budget of the box grid, its clearances and lists
 constexpr int kChunkMax = 1024;           // expansion slots per propagate chunk (at most)
@@ -150,6 +151,35 @@ __device__ __forceinline__ int wave_sum(int v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
+}
+
+// The same sum for a wave whose 64 lanes are all active, without LDS: DPP row
+// shifts by 1, 2, 4 and 8 leave each row of 16 lanes its running sum, whose
+// last lanes (15, 31, 47, 63) hold the row totals.
+__device__ __forceinline__ int wave_sum_rows(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    return __builtin_amdgcn_readlane(v, 15) + __builtin_amdgcn_readlane(v, 31) +
+           __builtin_amdgcn_readlane(v, 47) + __builtin_amdgcn_readlane(v, 63);
+}
+
+// Exclusive prefix sum over the 64 lanes of a fully active wave, without LDS:
+// the DPP row shifts above give each lane the running sum of its row of 16,
+// and the totals of the rows before its own come from lanes 15, 31 and 47.
+__device__ __forceinline__ int wave_exclusive_scan(int v)
+{
+    int x = v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    const int t0 = __builtin_amdgcn_readlane(x, 15), t1 = __builtin_amdgcn_readlane(x, 31),
+              t2 = __builtin_amdgcn_readlane(x, 47);
+    const int row = (int)(threadIdx.x & 63) >> 4;
+    return x - v + (row > 0 ? t0 : 0) + (row > 1 ? t1 : 0) + (row > 2 ? t2 : 0);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v)
@@ -291,28 +321,35 @@ __device__ __forceinline__ int samples_for(const DevProblem& P, int nsel)
 
 // ------------------------------------------------------------------ propagate
 
-// Copies three arrays of 16-byte words from global memory into LDS, each
-// thread issuing all of its loads (from clamped, always valid addresses)
-// before its first store, so that one memory round trip covers the copy.
-__device__ __forceinline__ void stage_lds(const int4* s0, int4* d0, int n0, const int4* s1, int4* d1, int n1,
-                                          const int4* s2, int4* d2, int n2)
+// Copies three arrays of 16-byte words from global memory into LDS, at word
+// offsets o0, o1 and o2 of `lds`, each thread issuing all of its loads (from
+// clamped, always valid addresses) before its first store, so that one memory
+// round trip covers the copy.  Past the end a thread stores the last word
+// again (the same value to the same place), and the destinations are integer
+// offsets: no store sits in a branch, where the compiler would move each load
+// down to its store and wait for the loads one by one.
+__device__ __forceinline__ void stage_lds(int4* lds, const int4* s0, int o0, int n0, const int4* s1, int o1,
+                                          int n1, const int4* s2, int o2, int n2)
 {
     constexpr int U = 8;
     const int e0 = n0, e1 = e0 + n1, e2 = e1 + n2;
     if (e2 == 0) return;
+    // word i of the concatenation: source address base_k + 16 i, LDS word c_k + i
+    const uintptr_t a0 = (uintptr_t)s0, a1 = (uintptr_t)s1 - 16u * (uintptr_t)e0,
+                    a2 = (uintptr_t)s2 - 16u * (uintptr_t)e1;
+    const int c0 = o0, c1 = o1 - e0, c2 = o2 - e1;
     for (int b = 0; b < e2; b += U * (int)blockDim.x) {
         int4 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = min(b + (int)threadIdx.x + u * (int)blockDim.x, e2 - 1);
-            const int4* src = i < e0 ? s0 + i : i < e1 ? s1 + (i - e0) : s2 + (i - e1);
-            v[u] = *src;
+            const uintptr_t a = (i >= e1 ? a2 : i >= e0 ? a1 : a0) + 16u * (uintptr_t)i;
+            v[u] = *(const int4*)(const __attribute__((address_space(1))) int4*)a;  // a global load
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = b + (int)threadIdx.x + u * (int)blockDim.x;
-            int4* dst = i < e0 ? d0 + i : i < e1 ? d1 + (i - e0) : d2 + (i - e1);
-            if (i < e2) *dst = v[u];
+            const int i = min(b + (int)threadIdx.x + u * (int)blockDim.x, e2 - 1);
+            lds[(i >= e1 ? c2 : i >= e0 ? c1 : c0) + i] = v[u];
         }
     }
 }
@@ -360,9 +397,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
 
     // the obstacle data does not depend on the device state: its loads go
     // out together with the state's
-    stage_lds(reinterpret_cast<const int4*>(T.boxes), reinterpret_cast<int4*>(sbox), 2 * P.n_boxes,
-              reinterpret_cast<const int4*>(T.gcell), reinterpret_cast<int4*>(sgc), gbp / 2,
-              reinterpret_cast<const int4*>(T.glist), reinterpret_cast<int4*>(sgl), (P.gb_entries + 7) / 8);
+    stage_lds(reinterpret_cast<int4*>(dyn_lds), reinterpret_cast<const int4*>(T.boxes), 0, 2 * P.n_boxes,
+              reinterpret_cast<const int4*>(T.gcell), (int)(reinterpret_cast<float4*>(sgc) - dyn_lds), gbp / 2,
+              reinterpret_cast<const int4*>(T.glist), (int)(reinterpret_cast<float4*>(sgl) - dyn_lds),
+              (P.gb_entries + 7) / 8);
     const int K = st->k;
     const int S = st->n_sel * K;
     if (st->full || S == 0) return;  // kernel-uniform
@@ -393,22 +431,24 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         // 1. parents (tree index, cost, state) into LDS, samples, sort by step
         // count (longest first).  The parent loads are issued before the
         // sampling so that their latency overlaps it.
+        // (Indexes past the end are clamped rather than branched on, so that
+        // each group of loads leaves together.)
         constexpr int kStage = 4;
         const int nstage = npar * D;
         int prow[kStage];
         float pv[kStage];
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
-            const int idx = threadIdx.x + r * NT;
-            prow[r] = idx < nstage ? T.sel[r0 + idx % npar] : 0;
+            const int idx = min((int)threadIdx.x + r * NT, nstage - 1);
+            prow[r] = T.sel[r0 + idx % npar];
         }
-        const int my_pid = (int)threadIdx.x < npar ? T.sel[r0 + threadIdx.x] : 0;
+        const int my_pid = T.sel[r0 + min((int)threadIdx.x, npar - 1)];
 #pragma unroll
         for (int r = 0; r < kStage; ++r) {
-            const int idx = threadIdx.x + r * NT;
-            pv[r] = idx < nstage ? T.x[(long long)(idx / npar) * P.cap + prow[r]] : 0.f;
+            const int idx = min((int)threadIdx.x + r * NT, nstage - 1);
+            pv[r] = T.x[(long long)(idx / npar) * P.cap + prow[r]];
         }
-        const uint32_t my_pcost = (int)threadIdx.x < npar ? T.cost[my_pid] : 0u;
+        const uint32_t my_pcost = T.cost[my_pid];
         const bool one_each = cnt <= NT;  // one slot per thread: no sort needed
         const int nr = (cnt + NT - 1) / NT;  // slot rounds of this chunk
         int bins[PT];
@@ -448,16 +488,8 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
         }
         __syncthreads();
         if (!one_each) {  // block-uniform: counting sort of the queue, longest first
-            if (threadIdx.x < 64) {  // exclusive prefix over the 64 bins in one wave
-                const int v = s_bin[threadIdx.x];
-                int x = v;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int y = __shfl_up(x, o);
-                    if ((int)threadIdx.x >= o) x += y;
-                }
-                s_bin[threadIdx.x] = x - v;
-            }
+            if (threadIdx.x < 64)  // exclusive prefix over the 64 bins in one wave
+                s_bin[threadIdx.x] = wave_exclusive_scan(s_bin[threadIdx.x]);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < PT; ++r) {
@@ -794,29 +826,29 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
     int ic0[RPT];
     uint32_t o[RPT];
     int4 A[RPT], B[RPT];
-    // every owner's status, count and first ancestor list in one round trip
+    // every owner's status, count and first ancestor list in one round trip;
+    // lanes without an owner read node 0's (one line for the wave) rather than
+    // branch, so that no load waits for another
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int c = base + j * kBlock;
         a[j] = 0;
-        owned[j] = false;
         o[j] = (uint32_t)key[j];
-        if (c < P.n_cells && key[j] != kEmpty) {
-            if ((long long)o[j] >= n_tree) {
-                // an arrival of this iteration owns it: that slot is the
-                // region's survivor (V_U, the App. A U-filter), inserted active
-                a[j] = 1;
-                const int sv = (int)((long long)o[j] - n_tree);
-                T.csurv[sv] = 1;
-                atomicAdd(&T.tile_count[sv / kTile], 1);
-                if (grouped(P.n_tgroups)) atomicAdd(tgroup_at(T, P, (int)(st - T.st), sv / kTile / kGroup), 1);
-            } else {
-                owned[j] = true;
-                s[j] = T.status[o[j]];
-                ic0[j] = T.icount[o[j]];
-                A[j] = T.anc[2 * (size_t)o[j]];
-                B[j] = T.anc[2 * (size_t)o[j] + 1];
-            }
+        const bool taken = c < P.n_cells && key[j] != kEmpty;
+        owned[j] = taken && (long long)o[j] < n_tree;
+        const uint32_t on = owned[j] ? o[j] : 0u;
+        s[j] = T.status[on];
+        ic0[j] = T.icount[on];
+        A[j] = T.anc[2 * (size_t)on];
+        B[j] = T.anc[2 * (size_t)on + 1];
+        if (taken && !owned[j]) {
+            // an arrival of this iteration owns it: that slot is the region's
+            // survivor (V_U, the App. A U-filter), inserted active
+            a[j] = 1;
+            const int sv = (int)((long long)o[j] - n_tree);
+            T.csurv[sv] = 1;
+            atomicAdd(&T.tile_count[sv / kTile], 1);
+            if (grouped(P.n_tgroups)) atomicAdd(tgroup_at(T, P, (int)(st - T.st), sv / kTile / kGroup), 1);
         }
     }
 #pragma unroll
@@ -833,22 +865,20 @@ __device__ __forceinline__ void prune_flags_body(const DevProblem& P, const DevP
         } else if (sj == kActive && ic0[j] <= P.i_max) {
             // Alg. 3: any ancestor beaten in its region (or below one); eight
             // ancestors per step from the stored lists, the next list fetched
-            // together with this step's flags
+            // together with this step's flags (a missing ancestor, -1, reads
+            // node 0's and is masked, so the step's loads share one round trip)
             int4 Aj = A[j], Bj = B[j];
             bool beaten = false;
             while (true) {
                 const int ids[8] = {Aj.x, Aj.y, Aj.z, Aj.w, Bj.x, Bj.y, Bj.z, Bj.w};
                 uint8_t d[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) d[q] = ids[q] >= 0 ? T.dead[ids[q]] : 0;
+                for (int q = 0; q < 8; ++q) d[q] = T.dead[max(ids[q], 0)];
                 const int nq = ids[7];
-                int4 NA = make_int4(-1, -1, -1, -1), NB = NA;
-                if (nq >= 0) {
-                    NA = T.anc[2 * (size_t)nq];
-                    NB = T.anc[2 * (size_t)nq + 1];
-                }
+                const size_t nqc = (size_t)max(nq, 0);
+                const int4 NA = T.anc[2 * nqc], NB = T.anc[2 * nqc + 1];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) beaten |= d[q] != 0;
+                for (int q = 0; q < 8; ++q) beaten |= ids[q] >= 0 && d[q] != 0;
                 if (beaten || nq < 0) break;
                 Aj = NA;
                 Bj = NB;
@@ -1039,8 +1069,9 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(DevProblem P, DevPtrs
 
 // App. A UpdateTree: survivors appended at |T| + rank (exclusive scan of V_U).
 // Every load that does not depend on another is issued first (the state, the
-// counts of the earlier tiles, this slot's flag and candidate record, its
-// parent); one barrier then gives each survivor its rank.
+// counts of the earlier tiles, this slot's survivor mark and its parent), then
+// a survivor's candidate record, end state and parent's ancestor lists; one
+// barrier gives each survivor its rank while those are in flight.
 template <int DYN>
 __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& T, DevState* st, int blk)
 {
@@ -1062,6 +1093,9 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     }
     const uint8_t f0 = T.csurv[sc];
     const int K = P.K > 0 ? P.K : st->k;
+    // every slot's parent, read with its survivor mark (a node's K slots share
+    // one entry), so that the parent's ancestor list needs no third round trip
+    const int par0 = T.sel[sc / max(K, 1)];
     const int full = st->full, n_sel = st->n_sel;
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
@@ -1072,30 +1106,32 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     if (grp)  // the earlier groups
         for (int j = threadIdx.x; j < tile / kGroup; j += kBlock) pre += *tgroup_at(T, P, (int)(st - T.st), j);
     const int f = s < S ? f0 : 0;
-    // a survivor's candidate record and parent, in flight while the ranks are
-    // scanned (the other slots' records are not read)
-    unsigned long long key = 0;
-    int c = 0, par = 0;
-    uint8_t flag = 0;
-    if (f) {
-        key = T.ckey[s];
-        c = T.ccell[s];
-        flag = T.cflag[s];
-        par = T.sel[s / K];
-    }
-    // rank = survivors of the earlier tiles + those before this slot in its tile
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int inc = f;
+    // a survivor's candidate cost, region and flags, end state and parent's
+    // ancestor lists, in flight while the ranks are scanned.  The other lanes
+    // read slot 0 and node 0 (one line for the whole wave) rather than branch,
+    // so that nothing waits for these loads before the barrier.
+    constexpr int SD = cx_row(D);
+    const int sl = f ? s : 0;
+    const int par = f ? par0 : 0;
+    const uint32_t cf = reinterpret_cast<const uint32_t*>(T.ckey)[2 * (size_t)sl + 1];
+    const int c = T.ccell[sl];
+    const uint8_t flag = T.cflag[sl];
+    float4 xr[SD / 4];
+    const float4* cr = reinterpret_cast<const float4*>(T.cx) + (long long)sl * (SD / 4);
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(inc, o);
-        if (lane >= o) inc += y;
+    for (int w = 0; w < SD / 4; ++w) xr[w] = cr[w];
+    const int4 pa = T.anc[2 * (size_t)par], pb = T.anc[2 * (size_t)par + 1];
+    // rank = survivors of the earlier tiles + those before this slot in its
+    // tile (a ballot of the marks: the survivors before this lane in its wave)
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long fm = __ballot(f);
+    const int wpre = wave_sum_rows(pre);
+    if (lane == 0) {
+        s_w[0][wid] = __popcll(fm);
+        s_w[1][wid] = wpre;
     }
-    const int wpre = wave_sum(pre);
-    if (lane == 63) s_w[0][wid] = inc;
-    if (lane == 0) s_w[1][wid] = wpre;
     __syncthreads();
-    int rank = inc - f;
+    int rank = __popcll(fm & __lanemask_lt());
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) rank += (w < wid ? s_w[0][w] : 0) + s_w[1][w];
     if (threadIdx.x == 0 && (tile + 1) * kTile >= S) {  // the last tile: the survivor count
@@ -1106,18 +1142,14 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     }
     if (f) {
         const long long i = n_tree + rank;
-        constexpr int SD = cx_row(D);
         float xv[SD];
-        const float4* cr = reinterpret_cast<const float4*>(T.cx) + (long long)s * (SD / 4);
 #pragma unroll
         for (int w = 0; w < SD / 4; ++w) {
-            const float4 v = cr[w];
-            xv[4 * w] = v.x;
-            xv[4 * w + 1] = v.y;
-            xv[4 * w + 2] = v.z;
-            xv[4 * w + 3] = v.w;
+            xv[4 * w] = xr[w].x;
+            xv[4 * w + 1] = xr[w].y;
+            xv[4 * w + 2] = xr[w].z;
+            xv[4 * w + 3] = xr[w].w;
         }
-        const int4 pa = T.anc[2 * (size_t)par], pb = T.anc[2 * (size_t)par + 1];
         float u[M];
         int n;
         sample<DYN>(P, it, (uint32_t)s, u, n);
@@ -1125,7 +1157,6 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
         for (int q = 0; q < D; ++q) T.x[(long long)q * P.cap + i] = xv[q];
 #pragma unroll
         for (int q = 0; q < M; ++q) T.u[(long long)q * P.cap + i] = u[q];
-        const uint32_t cf = (uint32_t)(key >> 32);
         T.anc[2 * i] = make_int4(par, pa.x, pa.y, pa.z);
         T.anc[2 * i + 1] = make_int4(pa.w, pb.x, pb.y, pb.z);
         T.steps[i] = (uint16_t)n;
@@ -1307,23 +1338,23 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
 #pragma unroll
     for (int k = 0; k < kGroup / kBlock; ++k)
         bc[k] = T.bcount[min(g0 + (int)threadIdx.x + k * kBlock, max(jend - 1, 0))];
-    const int was_full = st->full, n_sel = st->n_sel, n_surv0 = st->n_surv, cur = st->cursor_next;
-    const int k_cur = st->k;
-    const long long n_tree = st->n_tree;
+    // the whole state in one go (read before any store, which the compiler
+    // could not otherwise move these loads across)
+    const DevState q = *st;
+    const int was_full = q.full, n_sel = q.n_sel, n_surv0 = q.n_surv, cur = q.cursor_next;
+    const int k_cur = q.k;
+    const long long n_tree = q.n_tree;
     // active regions at / after the cursor and before it: in the blocks before
     // this one, and in all
     int v[4] = {0, 0, 0, 0};
     auto add = [&](int j, int2 t) {
-        if (j < jend) {
-            if (!grp) {
-                v[2] += t.x;
-                v[3] += t.y;
-            }
-            if (j < b) {
-                v[0] += t.x;
-                v[1] += t.y;
-            }
-        }
+        // selects, not branches: a load whose value only a branch used would
+        // be moved into it and waited for there
+        const bool in = j < jend, before = in && j < b, all = in && !grp;
+        v[0] += before ? t.x : 0;
+        v[1] += before ? t.y : 0;
+        v[2] += all ? t.x : 0;
+        v[3] += all ? t.y : 0;
     };
 #pragma unroll
     for (int k = 0; k < kGroup / kBlock; ++k) add(g0 + (int)threadIdx.x + k * kBlock, bc[k]);
@@ -1358,7 +1389,7 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
         ml[j] = __ballot(a[j] && !h[j]);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+    for (int k = 0; k < 4; ++k) v[k] = wave_sum_rows(v[k]);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) s_r[k][wid] = v[k];
@@ -1409,8 +1440,8 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
     }
     if (b == 0 && threadIdx.x == 0) {
         DevState* o = st_next;
-        const long long it = st->it;
-        o->sol = st->sol;
+        const long long it = q.it;
+        o->sol = q.sol;
         o->full = full ? 1 : 0;
         o->n_sel = nsel;
         o->k = samples_for(P, nsel);
@@ -1421,21 +1452,21 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
             r->iteration = it;
             r->n_tree = nt;
             r->n_select = n_sel;
-            r->n_valid = st->n_valid_acc;
-            r->n_live = st->n_live_acc;
+            r->n_valid = q.n_valid_acc;
+            r->n_live = q.n_live_acc;
             r->n_survivors = n_surv;
             r->samples_per_node = k_cur;
-            r->substeps = (long long)st->substeps_acc;
-            r->solution_key = st->sol;
+            r->substeps = (long long)q.substeps_acc;
+            r->solution_key = q.sol;
             r->t_end = wall_clock64();
             o->n_tree = nt;
             o->it = it + 1;
-            o->first_sol_it = (st->sol != kEmpty && st->first_sol_it < 0) ? it : st->first_sol_it;
+            o->first_sol_it = (q.sol != kEmpty && q.first_sol_it < 0) ? it : q.first_sol_it;
             o->last_n_sel = n_sel;
             o->last_k = k_cur;
-            o->last_n_valid = st->n_valid_acc;
+            o->last_n_valid = q.n_valid_acc;
             o->last_n_surv = n_surv;
-            o->last_substeps = (long long)st->substeps_acc;
+            o->last_substeps = (long long)q.substeps_acc;
             o->n_valid_acc = 0;
             o->n_live_acc = 0;
             o->substeps_acc = 0;
@@ -1443,16 +1474,16 @@ __device__ __forceinline__ void finalize_select_body(const DevProblem& P, const 
         } else {
             o->n_tree = n_tree;
             o->it = it;
-            o->first_sol_it = st->first_sol_it;
-            o->last_n_sel = st->last_n_sel;
-            o->last_k = st->last_k;
-            o->last_n_valid = st->last_n_valid;
-            o->last_n_surv = st->last_n_surv;
-            o->last_substeps = st->last_substeps;
-            o->n_valid_acc = st->n_valid_acc;
-            o->n_live_acc = st->n_live_acc;
-            o->substeps_acc = st->substeps_acc;
-            o->cursor = st->cursor;
+            o->first_sol_it = q.first_sol_it;
+            o->last_n_sel = q.last_n_sel;
+            o->last_k = q.last_k;
+            o->last_n_valid = q.last_n_valid;
+            o->last_n_surv = q.last_n_surv;
+            o->last_substeps = q.last_substeps;
+            o->n_valid_acc = q.n_valid_acc;
+            o->n_live_acc = q.n_live_acc;
+            o->substeps_acc = q.substeps_acc;
+            o->cursor = q.cursor;
         }
         if (nsel == 0) o->cursor_next = cur;
     }

@@ -99,21 +99,21 @@ struct DevProblem {
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
 // with the published multipliers, the key advancing by the published Weyl
-// increments between rounds.
+// increments between rounds.  Each product is formed whole, as one 64-bit
+// multiply-add (v_mad_u64_u32), instead of its high and low words apart.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a = c[0], b = c[2];
-        const uint32_t hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
-        const uint32_t n0 = hi1 ^ c[1] ^ k0;
-        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
         c[0] = n0;
-        c[1] = lo1;
+        c[1] = (uint32_t)p1;
         c[2] = n2;
-        c[3] = lo0;
+        c[3] = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -149,7 +149,7 @@ __device__ __forceinline__ void sample(const DevProblem& P, uint32_t it, uint32_
 template <int DYN>
 struct Hot {
     static constexpr int D = Dims<DYN>::D;
-    float dt, h2, h6;
+    float dt, h2, h6, hh6;          // hh6 = dt^2 / 6
     float bs[D], bo[D];            // scaled bound test (see DevProblem)
     uint32_t os_mask;
     float inv_mass, inv_j[3], gyro_j[3], grav;  // gyro_j: gyroscopic coefficient times 1/J, revolution units
@@ -165,6 +165,7 @@ __device__ __forceinline__ Hot<DYN> make_hot(const DevProblem& P)
     H.dt = P.dt;
     H.h2 = P.h2;
     H.h6 = P.h6;
+    H.hh6 = P.dt * P.h6;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         H.bs[i] = P.bnd_s[i];
@@ -177,7 +178,7 @@ __device__ __forceinline__ Hot<DYN> make_hot(const DevProblem& P)
     H.os_mask = P.os_mask;
     H.inv_mass = P.inv_mass;
     H.grav = P.grav;
-    asm volatile("" : "+v"(H.dt), "+v"(H.h2), "+v"(H.h6), "+v"(H.inv_mass), "+v"(H.grav));
+    asm volatile("" : "+v"(H.dt), "+v"(H.h2), "+v"(H.h6), "+v"(H.hh6), "+v"(H.inv_mass), "+v"(H.grav));
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         H.inv_j[a] = P.inv_j[a];
@@ -259,12 +260,56 @@ __device__ __forceinline__ void deriv(const Hot<DYN>& P, const float* x, const f
 }
 
 // Classical RK4 step of size dt on the state (and the path length).
+//
+// Quadrotor under the time cost: the position rates are the velocities, and
+// the velocity rates depend on neither positions nor velocities, so the four
+// stage velocities v, v + h/2 a1, v + h/2 a2 and v + h a3 (a_i the velocity
+// rates of stage i) weigh in as 6 v + h (a1 + a2 + a3): the position advances
+// by h v + h^2/6 (a1 + a2 + a3).  That is the same step, rounded differently,
+// and the stage velocities are never formed (the path-length cost needs them
+// for the speed).
 template <int DYN, int COST>
 __device__ __forceinline__ void rk4(const Hot<DYN>& P, float* x, const float* u, float& len)
 {
     constexpr int D = Dims<DYN>::D;
     float k[D], acc[D], t[D];
     float lk = 0.f, lacc = 0.f;
+    if constexpr (DYN == kQUAD12 && COST != kPATH) {
+        float a[3];
+        deriv<DYN, COST>(P, x, u, k, lk);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            a[i] = k[6 + i];
+            t[i] = x[i];
+        }
+#pragma unroll
+        for (int i = 3; i < D; ++i) {
+            acc[i] = k[i];
+            t[i] = __builtin_fmaf(P.h2, k[i], x[i]);
+        }
+        deriv<DYN, COST>(P, t, u, k, lk);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) a[i] += k[6 + i];
+#pragma unroll
+        for (int i = 3; i < D; ++i) {
+            acc[i] = __builtin_fmaf(2.f, k[i], acc[i]);
+            t[i] = __builtin_fmaf(P.h2, k[i], x[i]);
+        }
+        deriv<DYN, COST>(P, t, u, k, lk);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) a[i] += k[6 + i];
+#pragma unroll
+        for (int i = 3; i < D; ++i) {
+            acc[i] = __builtin_fmaf(2.f, k[i], acc[i]);
+            t[i] = __builtin_fmaf(P.dt, k[i], x[i]);
+        }
+        deriv<DYN, COST>(P, t, u, k, lk);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) x[i] = __builtin_fmaf(P.hh6, a[i], __builtin_fmaf(P.dt, x[6 + i], x[i]));
+#pragma unroll
+        for (int i = 3; i < D; ++i) x[i] = __builtin_fmaf(P.h6, acc[i] + k[i], x[i]);
+        return;
+    }
     deriv<DYN, COST>(P, x, u, k, lk);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
