@@ -96,6 +96,34 @@ def test_same_seed_same_tree(kpx, name):
     assert a["counters"] == b["counters"]
 
 
+@pytest.mark.parametrize("name,kw,cost_first", [
+    ("quad12", {}, False),                        # the benchmark shape, 4096 x 32 slots
+    ("quad12", dict(cost="PATH_LENGTH"), False),
+    ("quad12", {}, True),
+    ("di6", {}, False),
+    ("dubins6", {}, False),
+])
+def test_recording_leaves_the_tree_unchanged(kpx, name, kw, cost_first):
+    """With every slot recorded (the record the lockstep tests replay) each
+    slot writes its candidate record; otherwise only the slots that take a
+    region's atomic minimum write theirs.  Both must grow the same tree."""
+    trees = []
+    for record in (True, False):
+        w = W.make_workload(name, 4, **kw)
+        pl = _planner(kpx, w)
+        pl.set_dump(record)
+        if cost_first:
+            pl.set_cost_first(True)
+        pl.iterate(60)
+        trees.append(pl.snapshot())
+        pl.close()
+    a, b = trees
+    assert a["counters"]["n_tree"] > 1000, a["counters"]
+    for k in ("state", "control", "steps", "parent", "cost", "cell", "status", "icount", "cell_table"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert a["counters"] == b["counters"]
+
+
 def test_double_integrator_solution_verifies(kpx, ora):
     w = W.make_workload("di6", 0)  # full size: 256 nodes x 8 samples
     P = ora.Problem(w.problem, w.params)
