@@ -58,6 +58,7 @@ constexpr int kParMax = 256;              // parent states staged per chunk (at 
 // region, only the chunk's lowest key for the region table (few parents
 // then send many edges to the same regions)
 constexpr int kDedupK = 64;
+constexpr int kInsertEarlyParents = 1 << 21;  // slot buffers up to this read every slot's parent in insert
 // floats per candidate end-state row (slot-major: one row per slot, so that
 // a lane writes its end state, and insert reads a survivor's, as whole
 // 16-byte words)
@@ -1093,9 +1094,13 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     }
     const uint8_t f0 = T.csurv[sc];
     const int K = P.K > 0 ? P.K : st->k;
-    // every slot's parent, read with its survivor mark (a node's K slots share
-    // one entry), so that the parent's ancestor list needs no third round trip
-    const int par0 = T.sel[sc / max(K, 1)];
+    // With a small slot buffer every slot's parent is read with its survivor
+    // mark (a node's K slots share one entry), so that the parent's ancestor
+    // lists need no third round trip; with a large one the per-slot division
+    // and reads would cost more than that round trip, and only survivors read
+    // theirs (uniform).
+    const bool early = P.s_max <= kInsertEarlyParents;
+    const int par0 = early ? T.sel[sc / max(K, 1)] : 0;
     const int full = st->full, n_sel = st->n_sel;
     const long long n_tree = st->n_tree;
     const uint32_t it = (uint32_t)st->it;
@@ -1106,25 +1111,34 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
     if (grp)  // the earlier groups
         for (int j = threadIdx.x; j < tile / kGroup; j += kBlock) pre += *tgroup_at(T, P, (int)(st - T.st), j);
     const int f = s < S ? f0 : 0;
+    const unsigned long long fm = __ballot(f);
     // a survivor's candidate cost, region and flags, end state and parent's
-    // ancestor lists, in flight while the ranks are scanned.  The other lanes
-    // read slot 0 and node 0 (one line for the whole wave) rather than branch,
-    // so that nothing waits for these loads before the barrier.
+    // ancestor lists, in flight while the ranks are scanned.  In a wave that
+    // holds a survivor the other lanes read slot 0 and node 0 (one line for
+    // the wave) rather than branch, so that nothing waits for these loads
+    // before the barrier; a wave without one (most of them, when survivors
+    // are sparse) reads nothing (a wave-uniform branch).
     constexpr int SD = cx_row(D);
-    const int sl = f ? s : 0;
-    const int par = f ? par0 : 0;
-    const uint32_t cf = reinterpret_cast<const uint32_t*>(T.ckey)[2 * (size_t)sl + 1];
-    const int c = T.ccell[sl];
-    const uint8_t flag = T.cflag[sl];
+    uint32_t cf, flag;
+    int c, par;
     float4 xr[SD / 4];
-    const float4* cr = reinterpret_cast<const float4*>(T.cx) + (long long)sl * (SD / 4);
+    int4 pa, pb;
+    if (fm) {
+        const int sl = f ? s : 0;
+        par = f ? par0 : 0;
+        if (!early && f) par = T.sel[s / K];
+        cf = reinterpret_cast<const uint32_t*>(T.ckey)[2 * (size_t)sl + 1];
+        c = T.ccell[sl];
+        flag = T.cflag[sl];
+        const float4* cr = reinterpret_cast<const float4*>(T.cx) + (long long)sl * (SD / 4);
 #pragma unroll
-    for (int w = 0; w < SD / 4; ++w) xr[w] = cr[w];
-    const int4 pa = T.anc[2 * (size_t)par], pb = T.anc[2 * (size_t)par + 1];
+        for (int w = 0; w < SD / 4; ++w) xr[w] = cr[w];
+        pa = T.anc[2 * (size_t)par];
+        pb = T.anc[2 * (size_t)par + 1];
+    }
     // rank = survivors of the earlier tiles + those before this slot in its
     // tile (a ballot of the marks: the survivors before this lane in its wave)
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const unsigned long long fm = __ballot(f);
     const int wpre = wave_sum_rows(pre);
     if (lane == 0) {
         s_w[0][wid] = __popcll(fm);
@@ -1168,6 +1182,9 @@ __device__ __forceinline__ void insert_body(const DevProblem& P, const DevPtrs& 
         T.dead[i] = 0;
         const unsigned long long nk = ((unsigned long long)cf << 32) | (unsigned long long)(uint32_t)i;
         T.tbl[c] = nk;
+        // (an opaque copy, so that the compiler does not test the flag, and
+        // wait for its load, before the barrier)
+        asm volatile("" : "+v"(flag));
         if (flag & 2) atomicMin(&st->sol, nk);  // Alg. 4: a goal node competes for the solution
     }
 }
