@@ -52,6 +52,7 @@ static_assert(kSortBins == 64, "the sort bins' prefix is one wave's scan");
 constexpr int kBoxGridMax = 16;           // box-grid cells per workspace axis (at most)
 constexpr int kBoxGridBytes = 48 * 1024;  // LDS budget of the box grid, its clearances and lists
 constexpr int kChunkMax = 1024;           // expansion slots per propagate chunk (at most)
+constexpr int kChunkBig = 2048;           // ... for blocks whose share of the slots exceeds kChunkMax
 constexpr int kChunkMin = 64;
 constexpr int kParMax = 256;              // parent states staged per chunk (at most)
 // from this many samples per node, propagate first keeps, per block and
@@ -67,7 +68,7 @@ __host__ __device__ constexpr int cx_row(int d) { return (d + 3) & ~3; }
 // time; with two waves per SIMD the other wave hides part of a refill
 constexpr int kRefillBatch = 16;
 constexpr int kRefillBatchWide = 8;
-static_assert(kChunkMax == 1024, "the dedupe table hashes regions to 10 bits");
+static_assert(kChunkMax == 1024 && kChunkBig == 2048, "the dedupe table hashes regions to 10 or 11 bits");
 constexpr int kPropBlock = 256;           // propagate: one wave per SIMD, one block per CU
 constexpr int kPropBlockWide = 512;       // ... or two, for cheap models at large sizes
 constexpr int kStatsCap = 1 << 16;
@@ -369,21 +370,21 @@ __device__ __forceinline__ void stage_lds(int4* lds, const int4* s0, int o0, int
 // table value is loaded when the first pass ends and compared after the next
 // trip, so that its latency hides under one RK4 step.
 constexpr short kSkipped = -1;
-template <int DYN, int COST, bool CF = false, int NT = kPropBlock>
+template <int DYN, int COST, bool CF = false, int NT = kPropBlock, int CH = kChunkMax>
 __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtrs& T, DevState* st, int blk,
                                                int nblk)
 {
     constexpr int D = Dims<DYN>::D, M = Dims<DYN>::M;
-    constexpr int PT = kChunkMax / NT;   // slot rounds per thread in a full chunk
+    constexpr int PT = CH / NT;          // slot rounds per thread in a full chunk
     extern __shared__ float4 dyn_lds[];  // boxes | parent states | grid cells | grid lists
     constexpr int SD = (D + 3) & ~3;     // a staged parent state: whole 16-byte words
-    __shared__ float4 s_u[kChunkMax];    // a slot's control (one 16-byte read per refill)
-    __shared__ unsigned short s_n[kChunkMax];
-    __shared__ uint32_t s_order[kChunkMax];  // slot in chunk | parent row << 16
-    __shared__ short s_fi[kChunkMax];
-    __shared__ float s_len[COST == kPATH ? kChunkMax : 1];
-    __shared__ float s_pe[3][kChunkMax];  // end position of valid slots
-    __shared__ uint8_t s_vs[kChunkMax];   // ... and the signs of their velocity (bit a: v_a >= 0)
+    __shared__ float4 s_u[CH];           // a slot's control (one 16-byte read per refill)
+    __shared__ unsigned short s_n[CH];
+    __shared__ uint32_t s_order[CH];     // slot in chunk | parent row << 16
+    __shared__ short s_fi[CH];
+    __shared__ float s_len[COST == kPATH ? CH : 1];
+    __shared__ float s_pe[3][CH];        // end position of valid slots
+    __shared__ uint8_t s_vs[CH];         // ... and the signs of their velocity (bit a: v_a >= 0)
     __shared__ int s_pid[kParMax];        // the chunk's parents: tree index
     __shared__ uint32_t s_pcost[kParMax]; //                     cost field
     constexpr int VI = DYN == kQUAD12 ? 6 : 3;  // first velocity component
@@ -407,7 +408,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     if (st->full || S == 0) return;  // kernel-uniform
     int chunk = max(kChunkMin, (S + nblk - 1) / nblk);
     // at most kParMax parents per chunk (K may be up to the buffer size: 64-bit)
-    chunk = (int)min((long long)chunk, min((long long)kChunkMax, (long long)(kParMax - 1) * K));
+    chunk = (int)min((long long)chunk, min((long long)CH, (long long)(kParMax - 1) * K));
     if (blk * chunk >= S) return;  // block-uniform
     if (blk == 0 && threadIdx.x == 0) T.stats[st->it & (kStatsCap - 1)].t_begin = wall_clock64();
     const long long n_tree = st->n_tree;
@@ -729,7 +730,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             }
         }
         if (K >= kDedupK) {  // block-uniform
-            // The chunk's lowest key per region, in an LDS table of kChunkMax
+            // The chunk's lowest key per region, in an LDS table of CH
             // buckets (region in the freed sort order, key in the freed
             // controls).  A slot whose region lost its bucket to another
             // region goes to the region table as it is.  A slot beaten by a
@@ -738,7 +739,7 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
             uint32_t* s_hcell = s_order;
             unsigned long long* s_hkey = reinterpret_cast<unsigned long long*>(s_u);
             __syncthreads();  // every read of s_u above is done
-            for (int i = threadIdx.x; i < kChunkMax; i += NT) {
+            for (int i = threadIdx.x; i < CH; i += NT) {
                 s_hcell[i] = 0xFFFFFFFFu;
                 s_hkey[i] = kEmpty;
             }
@@ -749,7 +750,8 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
                 hb[r] = -1;
                 if (r >= nr || keys[r] == kEmpty) continue;
                 const uint32_t c = (uint32_t)cells[r];
-                const int h = (int)((c * 2654435761u) >> 22);  // 10 bits: kChunkMax buckets
+                constexpr int kHashShift = CH == kChunkBig ? 21 : 22;  // 11 or 10 bits: CH buckets
+                const int h = (int)((c * 2654435761u) >> kHashShift);
                 const uint32_t prev = atomicCAS(&s_hcell[h], 0xFFFFFFFFu, c);
                 if (prev == 0xFFFFFFFFu || prev == c) {
                     atomicMin(&s_hkey[h], keys[r]);
@@ -792,10 +794,10 @@ __device__ __forceinline__ void propagate_body(const DevProblem& P, const DevPtr
     }
 }
 
-template <int DYN, int COST, bool CF, int NT>
+template <int DYN, int COST, bool CF, int NT, int CH = kChunkMax>
 __global__ __launch_bounds__(NT) void k_propagate(DevProblem P, DevPtrs T, DevState* st)
 {
-    propagate_body<DYN, COST, CF, NT>(P, T, st, blockIdx.x, gridDim.x);
+    propagate_body<DYN, COST, CF, NT, CH>(P, T, st, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ prune + survivor flags
@@ -2082,6 +2084,7 @@ struct kpx_handle {
     int polish_goal_only = 0;                 // 1: polish only nodes inserted in the goal set
     bool cost_first = false;                  // propagate in the cost-first form
     int prop_threads = kPropBlock;            // propagate block size (kPropBlock or kPropBlockWide)
+    int prop_chunk = kChunkMax;               // propagate chunk (kChunkMax or kChunkBig slots)
     kpxd::DiffConst polish_c{};
     std::string err;
 };
@@ -2189,19 +2192,26 @@ size_t propagate_lds_bytes(const Sizes& z, int d)
            sizeof(int2) * gbp + 16 * (((size_t)z.gb_entries + 7) / 8);
 }
 
+template <int DYN, int COST, int CH>
+void launch_propagate_ch(kpx_handle* h, const DevPtrs& T, size_t lds)
+{
+    const bool wide = h->prop_threads == kPropBlockWide;
+    if (h->cost_first && wide)
+        k_propagate<DYN, COST, true, kPropBlockWide, CH><<<h->P.n_cu, kPropBlockWide, lds, h->stream>>>(h->P, T, cur_state(h));
+    else if (h->cost_first)
+        k_propagate<DYN, COST, true, kPropBlock, CH><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
+    else if (wide)
+        k_propagate<DYN, COST, false, kPropBlockWide, CH><<<h->P.n_cu, kPropBlockWide, lds, h->stream>>>(h->P, T, cur_state(h));
+    else
+        k_propagate<DYN, COST, false, kPropBlock, CH><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
+}
+
 template <int DYN, int COST>
 void launch_propagate(kpx_handle* h, const DevPtrs& T)
 {
     const size_t lds = propagate_lds_bytes(h->z, Dims<DYN>::D);
-    const bool wide = h->prop_threads == kPropBlockWide;
-    if (h->cost_first && wide)
-        k_propagate<DYN, COST, true, kPropBlockWide><<<h->P.n_cu, kPropBlockWide, lds, h->stream>>>(h->P, T, cur_state(h));
-    else if (h->cost_first)
-        k_propagate<DYN, COST, true, kPropBlock><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
-    else if (wide)
-        k_propagate<DYN, COST, false, kPropBlockWide><<<h->P.n_cu, kPropBlockWide, lds, h->stream>>>(h->P, T, cur_state(h));
-    else
-        k_propagate<DYN, COST, false, kPropBlock><<<h->P.n_cu, kPropBlock, lds, h->stream>>>(h->P, T, cur_state(h));
+    if (h->prop_chunk == kChunkBig) launch_propagate_ch<DYN, COST, kChunkBig>(h, T, lds);
+    else launch_propagate_ch<DYN, COST, kChunkMax>(h, T, lds);
 }
 
 // Allows `dynamic` bytes of dynamic LDS for a propagate kernel, after checking
@@ -2219,24 +2229,30 @@ int allow_lds(const void* kernel, size_t dynamic, int lds_max)
 
 // The propagate kernel for a (model, cost) pair: batched, or single-query in
 // the plain or the cost-first form.
+template <int DYN, int COST, int CH>
+const void* propagate_kernel_ch(bool cf, bool wide)
+{
+    if (wide)
+        return cf ? (const void*)k_propagate<DYN, COST, true, kPropBlockWide, CH>
+                  : (const void*)k_propagate<DYN, COST, false, kPropBlockWide, CH>;
+    return cf ? (const void*)k_propagate<DYN, COST, true, kPropBlock, CH>
+              : (const void*)k_propagate<DYN, COST, false, kPropBlock, CH>;
+}
 template <int DYN, int COST>
-const void* propagate_kernel_t(bool batched, bool cf, bool wide)
+const void* propagate_kernel_t(bool batched, bool cf, bool wide, bool big)
 {
     if (batched) return wide ? (const void*)kb_propagate<DYN, COST, kPropBlockWide> : (const void*)kb_propagate<DYN, COST, kPropBlock>;
-    if (wide)
-        return cf ? (const void*)k_propagate<DYN, COST, true, kPropBlockWide>
-                  : (const void*)k_propagate<DYN, COST, false, kPropBlockWide>;
-    return cf ? (const void*)k_propagate<DYN, COST, true, kPropBlock> : (const void*)k_propagate<DYN, COST, false, kPropBlock>;
+    return big ? propagate_kernel_ch<DYN, COST, kChunkBig>(cf, wide) : propagate_kernel_ch<DYN, COST, kChunkMax>(cf, wide);
 }
-const void* propagate_kernel(int dyn, int cost, bool batched, bool cf = false, bool wide = false)
+const void* propagate_kernel(int dyn, int cost, bool batched, bool cf = false, bool wide = false, bool big = false)
 {
     switch (dyn * 2 + cost) {
-    case 0: return propagate_kernel_t<kDI6, kTIME>(batched, cf, wide);
-    case 1: return propagate_kernel_t<kDI6, kPATH>(batched, cf, wide);
-    case 2: return propagate_kernel_t<kQUAD12, kTIME>(batched, cf, wide);
-    case 3: return propagate_kernel_t<kQUAD12, kPATH>(batched, cf, wide);
-    case 4: return propagate_kernel_t<kDUBINS6, kTIME>(batched, cf, wide);
-    default: return propagate_kernel_t<kDUBINS6, kPATH>(batched, cf, wide);
+    case 0: return propagate_kernel_t<kDI6, kTIME>(batched, cf, wide, big);
+    case 1: return propagate_kernel_t<kDI6, kPATH>(batched, cf, wide, big);
+    case 2: return propagate_kernel_t<kQUAD12, kTIME>(batched, cf, wide, big);
+    case 3: return propagate_kernel_t<kQUAD12, kPATH>(batched, cf, wide, big);
+    case 4: return propagate_kernel_t<kDUBINS6, kTIME>(batched, cf, wide, big);
+    default: return propagate_kernel_t<kDUBINS6, kPATH>(batched, cf, wide, big);
     }
 }
 
@@ -2506,11 +2522,25 @@ int kpx_create(const kpx_problem* prob, const kpx_params* prm, void* hip_stream,
         // whatever their priorities (25% slower measured).
         h->prop_threads = (h->P.dyn != kQUAD12 && (long long)z.s_max >= 2LL * kPropBlock * h->P.n_cu)
                               ? kPropBlockWide : kPropBlock;
+        // Chunks of kChunkBig slots when a block's share of the slot buffer
+        // exceeds kChunkMax: one chunk instead of two up to kChunkBig, half as
+        // many beyond, each paying its parents, sort and longest edge once.
+        // The larger LDS arrays must fit beside the scene's obstacle data,
+        // else the block keeps kChunkMax.
+        const bool wide = h->prop_threads == kPropBlockWide;
+        const size_t dyn_lds = propagate_lds_bytes(z, z.d);
         int rc = KPX_OK;
+        if ((long long)z.s_max > (long long)kChunkMax * h->P.n_cu) {
+            bool fits = true;
+            for (bool cf : {false, true})
+                fits = fits && allow_lds(propagate_kernel(h->P.dyn, h->P.cost, false, cf, wide, true), dyn_lds,
+                                         lds_max) == KPX_OK;
+            if (fits) h->prop_chunk = kChunkBig;
+        }
         for (bool cf : {false, true})  // both forms, so that kpx_set_cost_first needs no device call
             if (rc == KPX_OK)
-                rc = allow_lds(propagate_kernel(h->P.dyn, h->P.cost, false, cf, h->prop_threads == kPropBlockWide),
-                               propagate_lds_bytes(z, z.d), lds_max);
+                rc = allow_lds(propagate_kernel(h->P.dyn, h->P.cost, false, cf, wide, h->prop_chunk == kChunkBig),
+                               dyn_lds, lds_max);
         if (rc != KPX_OK) {
             delete h;
             return rc;
