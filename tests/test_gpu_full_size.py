@@ -120,7 +120,9 @@ def test_full_size_lockstep_at_the_benchmark_shapes(kpx, ora, name, warm):
     queue).  dubins6: after 40 iterations; its capped selection never exceeds
     the ~2,000 regions with an active owner (of 16,384), so its lanes hold one
     slot each.  dubins6_paper, the uncapped form with a 300,000-slot buffer:
-    1,024-slot chunks, four slots per lane, the Dubins sort and refill path."""
+    more than 1,024 slots per block, so one chunk of up to 2,048 (about 1,170
+    here) and two to three slots per lane of 512-thread blocks, the Dubins
+    sort and refill path."""
     w = W.make_workload(name, 0)
     P = ora.Problem(w.problem, w.params)
     pl = kpx.Planner(w.problem, w.params)
@@ -139,5 +141,5 @@ def test_full_size_lockstep_at_the_benchmark_shapes(kpx, ora, name, warm):
     if warm is None:
         assert rep["slots"] == 3 * w.params.n_slots, rep
     if name == "dubins6_paper":
-        assert rep["slots"] > 3 * 4 * 256 * 256, rep  # more than four slots per lane on 256 CUs
+        assert rep["slots"] > 3 * 1024 * 256, rep  # more than 1,024 slots per block on 256 CUs
     pl.close()
