@@ -105,7 +105,8 @@ def bench_args_key(a):
             + (f" --cost {a.cost}" if a.cost else "")
             + (f" --polish {a.polish}" if a.polish else "") + (" --polish-goal-only" if a.polish_goal_only else "")
             + (" --cost-first" if a.cost_first else "")
-            + (f" --refine-at {a.refine_at}" if a.refine_at else ""))
+            + (f" --refine-at {a.refine_at}" if a.refine_at else "")
+            + (f" --timing-every {a.timing_every}" if a.timing_every != 16 else ""))
 
 
 def profile_fields(a, kind):
@@ -198,7 +199,7 @@ def parse():
     ap.add_argument("--refine-at", type=int, default=0,
                     help="halve the region cells per axis after this many iterations of each query")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
-    ap.add_argument("--timing-every", type=int, default=8,
+    ap.add_argument("--timing-every", type=int, default=16,
                     help="bracket the kernels with HIP events in every n-th iteration of each query")
     ap.add_argument("--steady-window", type=int, default=20,
                     help="iterations of the steady-state window (0: none)")

@@ -2286,8 +2286,12 @@ hipEvent_t take_event(kpx_handle* h)
         h->spare.pop_back();
         return e;
     }
+    // Timing events only: recorded without the system-scope fence, which
+    // would make each record write back and invalidate the caches between
+    // two kernels of the iteration (nothing of the device memory need be
+    // visible to the host when such an event completes).
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

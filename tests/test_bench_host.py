@@ -57,7 +57,7 @@ def test_key_cost_and_budgets(bench):
 
 def test_profile_figures_follow_the_sources_and_the_arguments(bench):
     a = _Obj(workload="quad12", steps=20, warmup=5, iters=200, cost=None, polish=0, polish_goal_only=False,
-             cost_first=False, refine_at=0)
+             cost_first=False, refine_at=0, timing_every=16)
     # the committed summary of `bench.py --gpus 1 --steps 20 --warmup 5` covers the current kernels
     trace, traffic = bench.measured_trace(a), bench.measured_traffic(a)
     assert trace is not None and traffic is not None, "profiles/quad12_* were taken on other kernel sources"
@@ -66,6 +66,7 @@ def test_profile_figures_follow_the_sources_and_the_arguments(bench):
     # another window of queries, or another form of the kernels, reads nothing
     assert bench.measured_traffic(_Obj(**dict(vars(a), steps=100))) is None
     assert bench.measured_trace(_Obj(**dict(vars(a), cost_first=True))) is None
+    assert bench.measured_trace(_Obj(**dict(vars(a), timing_every=8))) is None  # other bracketed launches
 
 
 def test_more_than_one_gpu_is_refused():
